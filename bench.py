@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Throughput of the time-domain Gaussian log-likelihood on one MI355X.
+
+Workload (two detectors x N = 16384 samples at 4096 Hz, 4 s; 4096 chirp templates
+per launch; analytic-PSD ACF with nugget 1e-6; seeded synthetic data standing in
+for LIGO strain): every step scores all templates against both detectors and
+returns the network logL per template.  One step runs the per-evaluation hot
+path with the factors resident in HBM: template gather and BF16 hi/lo split,
+the two BF16x3 whitening products, the FP64 FFT refinement and the FP64
+reductions (mixed precision), or the blocked FP64 triangular solve with fused
+reductions (FP64).  The one-time costs (covariance assembly, FP64 Cholesky,
+whitening operator and its split, whitened data) are timed separately.
+
+Prints one JSON line.  `value` is the mixed-precision evals/s (one eval = one
+template against all detectors); the FP64 path on the same GPU is reported
+beside it, with |dlogL| of mixed vs FP64 over every template and of both vs the
+FP64 CPU oracle on a sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "logL evals/s @N=16384, mixed vs FP64 at |ΔlogL|≤1e-3; p50/p99 latency"
+PEAK_BF16 = 2.5e15       # dense BF16 matrix-core peak, FLOP/s
+PEAK_FP64 = 78.6e12      # FP64 matrix-core peak, FLOP/s
+
+
+def _pct(x, p):
+    return float(np.percentile(np.asarray(x), p))
+
+
+def cpu_baseline(inst, sample, fs_cache):
+    """Time the FP64 oracle (as it is) on `sample` templates against both detectors."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 0) for i in threadpool_info()] or [0])
+    except Exception:
+        threads = 0
+    cores = threads or len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    fs = [oracle.factor(inst.acf, inst.N, inst.masks[k]) for k in range(inst.n_det)]
+    t_factor = time.perf_counter() - t0
+    fs_cache.extend(fs)
+    Hs = inst.H[:sample]
+    oracle.loglik_network(fs, inst.d, Hs[:2])  # warm-up
+    reps, t = 0, 0.0
+    while reps < 3 or (t < 10.0 and reps < 10):
+        t1 = time.perf_counter()
+        ref = oracle.loglik_network(fs, inst.d, Hs)
+        t += time.perf_counter() - t1
+        reps += 1
+    return ref, {
+        "value": sample * reps / t,
+        "unit": "evals/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": f"{sample} of the {inst.B} templates x {inst.n_det} detectors, N={inst.N}, "
+                  f"{reps} repetitions after 1 warm-up; factorisation ({t_factor:.1f} s, "
+                  f"once per detector) excluded like on the GPU",
+        "factor_s": t_factor,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--templates", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; run with --gpus 1 "
+              "(templates and datasets shard across GPUs with no exchange in the hot loop, "
+              "see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2603_06010_amd as tda
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    tda.load_library()
+    dev = torch.device("cuda", 0)
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+
+    t0 = time.perf_counter()
+    w = synth.c2_workload(B=args.templates, n=args.n)
+    inst = w.instances[0]
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: N={inst.N} B={inst.B} det={inst.n_det}")
+    d = [torch.from_numpy(inst.d[k]).to(dev) for k in range(inst.n_det)]
+    H = torch.from_numpy(inst.H).to(dev)
+
+    setup = {}
+    t0 = time.perf_counter()
+    hs = [tda.Handle(inst.acf, inst.N, inst.masks[k], precision="mixed") for k in range(inst.n_det)]
+    torch.cuda.synchronize()
+    setup["cov_build_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for h in hs:
+        h.factor()
+    torch.cuda.synchronize()
+    setup["factor_and_operator_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for h, dk in zip(hs, d):
+        h.set_data(dk)
+    torch.cuda.synchronize()
+    setup["whitened_data_s"] = time.perf_counter() - t0
+    log("setup", setup)
+    n_eff = [h.info()["n_eff"] for h in hs]
+
+    out = {p: torch.empty(inst.B, dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
+    items = {p: [(h, dk, H, out[p]) for h, dk in zip(hs, d)] for p in out}
+
+    def run(prec, steps, warmup):
+        for _ in range(warmup):
+            tda.loglik_multi(items[prec], precision=prec)
+        torch.cuda.synchronize()
+        tda.timing_read(reset=True)
+        tda.timing_enable(True)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for a, b in evs:
+            a.record()
+            tda.loglik_multi(items[prec], precision=prec)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tda.timing_enable(False)
+        kt = tda.timing_read(reset=True)
+        lat = [a.elapsed_time(b) for a, b in evs]
+        return wall, lat, kt
+
+    wall_m, lat_m, kt_m = run("mixed", args.steps, args.warmup)
+    log(f"mixed: {wall_m / args.steps * 1e3:.3f} ms/step", kt_m)
+    fsteps = args.fp64_steps or max(3, args.steps // 4)
+    wall_f, lat_f, kt_f = run("fp64", fsteps, 1)
+    log(f"fp64: {wall_f / fsteps * 1e3:.3f} ms/step", kt_f)
+    res_m = out["mixed"].cpu().numpy()
+    res_f = out["fp64"].cpu().numpy()
+    d_mf = np.abs(res_m - res_f)
+
+    evals_m = inst.B * args.steps / wall_m
+    evals_f = inst.B * fsteps / wall_f
+
+    # dominant kernel of the mixed step and its roofline (algorithmic flops: one
+    # triangular product = N_eff^2 flops per template and detector)
+    dom = max((k for k in kt_m if k.startswith("trmm")), key=lambda k: kt_m[k][1])
+    cnt, tot = kt_m[dom]
+    alg_flops = float(sum(n * n for n in n_eff)) * inst.B
+    achieved = alg_flops / (tot / cnt * 1e-3)
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
+                "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
+                "traffic": None, "avg_ms": tot / cnt,
+                "issued_frac": 3 * achieved / PEAK_BF16}
+    dom_f = "trsm_f64"
+    cf, tf = kt_f[dom_f]
+    ach_f = alg_flops / (tf / cf * 1e-3)
+
+    line = {
+        "metric": METRIC,
+        "value": evals_m,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_m / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+f64",
+        "data": "synthetic",
+        "config": {"workload": f"two detectors x N={inst.N} (fs=4096 Hz), {inst.B} chirp templates "
+                               f"per launch, analytic-PSD ACF + nugget {synth.EPS_PRIMARY:g}, no gaps",
+                   "n_det": inst.n_det, "N": inst.N, "templates_per_launch": inst.B,
+                   "n_eff": n_eff},
+        "latency_ms": {"p50": _pct(lat_m, 50), "p99": _pct(lat_m, 99),
+                       "unit": "one launch of all templates"},
+        "fp64": {"value": evals_f, "unit": "evals/s", "ms_per_step": wall_f / fsteps * 1e3,
+                 "steps": fsteps, "latency_ms": {"p50": _pct(lat_f, 50), "p99": _pct(lat_f, 99)},
+                 "roofline": {"bound": "mfma", "kernel": dom_f, "achieved": ach_f / 1e12,
+                              "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                              "frac": ach_f / PEAK_FP64, "avg_ms": tf / cf}},
+        "speedup_mixed_vs_fp64": evals_m / evals_f,
+        "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
+                     "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
+                     "templates_compared": int(inst.B)},
+        "roofline": roofline,
+        "kernels_ms": {k: v[1] / v[0] for k, v in kt_m.items()},
+        "setup_s": setup,
+    }
+    if not args.no_cpu_baseline:
+        fs = []
+        ref, cb = cpu_baseline(inst, args.cpu_sample, fs)
+        line["cpu_baseline"] = cb
+        line["accuracy"]["max_abs_dlogL_mixed_vs_oracle"] = float(np.abs(res_m[:len(ref)] - ref).max())
+        line["accuracy"]["max_abs_dlogL_fp64_vs_oracle"] = float(np.abs(res_f[:len(ref)] - ref).max())
+        line["accuracy"]["oracle_sample"] = len(ref)
+    print(json.dumps(line), flush=True)
+    for h in hs:
+        h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,282 @@
+/*
+ * tda.h -- C ABI of libtda: exact time-domain Gaussian log-likelihood on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper Sec. II):
+ *   For a detector with data d and a waveform template h, both real vectors
+ *   of N samples, and stationary Gaussian noise with autocorrelation function
+ *   (ACF) rho, the noise covariance is the symmetric Toeplitz matrix
+ *   C_ij = rho(|i-j|) (Sec. II, Toeplitz definition).  The log-likelihood is
+ *   the exact Gaussian one (eqn:lik, no Whittle approximation):
+ *       logL(h) = -1/2 (d-h)^T C^-1 (d-h) - 1/2 log det C - (N_eff/2) log 2 pi.
+ *   C is factored once, C = L L^T (Sec. II.A), and each template is scored
+ *   through the whitened residual w = L^-1 (d-h), logL = -1/2 w^T w + const
+ *   (eq:td_like_whitened).
+ *   Time segments (Sec. II.B item 1): C is block-diagonal over disjoint
+ *   segments, each block the Toeplitz matrix of the ACF truncated to the
+ *   segment length.  Data gaps (Sec. II.B item 2): excluded samples are
+ *   marginalised out, i.e. each block is C[keep, keep] over the retained
+ *   samples; values of d and h at excluded samples are never read.
+ *   N_eff is the number of retained samples over all segments.
+ *   Several detectors (Sec. II.B item 3): per-detector logL are summed;
+ *   tda_loglik_multi sums items that share an output array.
+ *
+ * Precision:
+ *   TDA_PREC_FP64  -- every step in FP64 (Cholesky, blocked triangular solve
+ *                     on FP64 matrix cores, reductions).
+ *   TDA_PREC_MIXED -- factorisation, log det and every reduction in FP64; the
+ *                     bulk whitening products run on BF16 matrix cores with a
+ *                     hi/lo split of both operands (three products, FP32
+ *                     accumulation) against the explicit whitening operator
+ *                     W = L^-1, followed by an FP64 refinement whose residual
+ *                     uses an FP64 FFT Toeplitz product (eq:toeplitz_fft).
+ *                     The refined quadratic form is never larger than the
+ *                     exact one (variational bound) and its error is
+ *                     quadratic in the BF16 product error.
+ *
+ * Conventions for every entry point:
+ *   - Returns a tda_status; nothing is thrown across the ABI.  On failure a
+ *     message is available from tda_last_error() (thread-local).
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     HIP device memory of the handle's device and must stay valid until the
+ *     work enqueued on the given stream has finished.
+ *   - Calls on one handle must not run concurrently from several host
+ *     threads.  Different handles are independent.
+ *   - Enqueued work is asynchronous with respect to the host unless stated.
+ */
+#ifndef TDA_H
+#define TDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tda_ctx *tda_handle;
+
+typedef enum {
+  TDA_OK = 0,
+  TDA_EINVAL = 1,    /* invalid argument (sizes, pointers, segments, ACF) */
+  TDA_ENOTSPD = 2,   /* a Cholesky pivot was <= 0 or not finite */
+  TDA_ENOMEM = 3,    /* device allocation failed or the HBM budget is exceeded */
+  TDA_ESTATE = 4,    /* call out of order (e.g. tda_loglik before tda_factor) */
+  TDA_ENODEV = 5,    /* no usable HIP device */
+  TDA_EHIP = 6,      /* a HIP runtime call failed */
+  TDA_EINTERNAL = 7, /* internal consistency check failed */
+  TDA_EAGAIN = 8     /* serving: request not admitted now, retry later */
+} tda_status;
+
+typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1 } tda_precision;
+
+/* Half-open sample range [offset, offset + length) of the N-sample series. */
+typedef struct {
+  int64_t offset;
+  int64_t length;
+} tda_segment;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(tda_options) */
+  int32_t precision;      /* tda_precision */
+  int32_t device;         /* HIP device ordinal; -1 = current device */
+  int32_t reserved;       /* must be 0 */
+  size_t hbm_budget_bytes;/* cap on this handle's device memory; 0 = none */
+} tda_options;
+
+typedef struct {
+  int64_t n;            /* N given to tda_cov_build */
+  int64_t n_eff;        /* retained samples over all segments */
+  int64_t n_pad;        /* padded row count used on the device */
+  int64_t n_segments;
+  double logdet;        /* log det C (valid once factored) */
+  int64_t fail_row;     /* ENOTSPD: retained-sample row (0-based, within the segment); else -1 */
+  int32_t fail_segment; /* ENOTSPD: segment index; else -1 */
+  int32_t factored;     /* 1 once tda_factor succeeded */
+  int32_t precision;
+  int32_t data_set;     /* mixed: 1 once whitened data is cached */
+  size_t device_bytes;  /* device memory held by the handle */
+} tda_info_t;
+
+/*
+ * tda_cov_build -- describe one detector's noise model and assemble its
+ * covariance blocks on the device (paper Sec. II Toeplitz definition,
+ * Sec. II.B items 1-2).
+ *   acf      host, float64[acf_len]: rho(0..acf_len-1); acf[0] > 0 and finite.
+ *            acf_len must be >= the longest segment.  No regularisation is
+ *            added: a numerically singular ACF is reported by tda_factor.
+ *   N        total sample count, >= 1.
+ *   gap_mask host, uint8[N] or NULL: nonzero = excluded sample.
+ *   segments host, tda_segment[n_segments], sorted, disjoint, inside [0, N);
+ *            NULL with n_segments == 0 means one segment [0, N).  Samples
+ *            outside every segment are excluded.
+ *   opt      host, may be NULL (FP64, current device, no budget).
+ *   out      receives the handle.  All inputs are copied; the caller may free
+ *            them on return.
+ * Errors: EINVAL (N < 1, acf_len too short, acf[0] <= 0 or non-finite,
+ *   bad segments, no retained sample), ENOMEM, ENODEV, EHIP.
+ * Synchronous: returns after assembly finished.
+ */
+tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t N, const uint8_t *gap_mask,
+                         const tda_segment *segments, int64_t n_segments, const tda_options *opt,
+                         tda_handle *out);
+
+/*
+ * tda_factor -- FP64 blocked Cholesky of every block, C = L L^T, and
+ * log det C = 2 sum log L_ii (Sec. II.A; one-time cost, Sec. III.A.2).
+ * Builds the packed triangular-solve panels; for TDA_PREC_MIXED also the
+ * FP64 whitening operator W = L^-1 and its BF16 hi/lo copies.
+ * Errors: ENOTSPD (tda_info gives fail_row / fail_segment; the handle stays
+ *   destroyable), ENOMEM, EHIP.  Idempotent after success.  Synchronous.
+ */
+tda_status tda_factor(tda_handle h);
+
+/*
+ * tda_set_data -- cache the whitened data of a mixed-precision handle:
+ * dbar = W d, y_d = W^T dbar = C^-1 d and q_dd = dbar^T dbar, all FP64
+ * (Sec. III.A: cache L and the whitened data once).  d is device
+ * float64[N]; only retained samples are read.  FP64 handles accept and
+ * ignore the call.  Enqueued on hip_stream (NULL = default stream).
+ * Errors: ESTATE (not factored), EINVAL.
+ */
+tda_status tda_set_data(tda_handle h, const double *d, void *hip_stream);
+
+/*
+ * tda_loglik -- logL for B templates against one detector, constants
+ * included (eq:td_like_whitened plus -1/2 log det C - N_eff/2 log 2 pi).
+ *   d    device float64[N]: data.  Mixed handles use the whitened data
+ *        cached by the last tda_set_data; if d differs from the pointer
+ *        given there (or none was given), tda_set_data(h, d) runs first.
+ *        After changing d's contents in place, call tda_set_data again.
+ *   H    device float64, B rows of length >= N, row stride ldh (>= N).
+ *   out  device float64[B], written (not accumulated).
+ *   B = 0 is a no-op.  NaN/Inf in a template affects only its own out[b].
+ * Errors: ESTATE (not factored), EINVAL (B < 0, ldh < N, NULL pointers).
+ * Asynchronous on hip_stream (NULL = default stream).
+ */
+tda_status tda_loglik(tda_handle h, const double *d, const double *H, int64_t B, int64_t ldh,
+                      double *out, void *hip_stream);
+
+/* As tda_loglik, with the precision chosen per call: a mixed handle may
+ * also be evaluated in TDA_PREC_FP64; an FP64 handle rejects
+ * TDA_PREC_MIXED with ESTATE. */
+tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t B, int64_t ldh,
+                         double *out, int32_t precision, void *hip_stream);
+
+/*
+ * tda_loglik_multi -- one batched evaluation over many (handle, data,
+ * templates) items, e.g. all detectors of all instances (Sec. II.B item 3).
+ * Items whose `out` pointers are equal are summed into that array in item
+ * order (network logL); otherwise each out is written.  All handles must be
+ * factored, live on one device and be evaluated in `precision`.  The work of
+ * all items of one precision runs in the same kernel launches.
+ * Asynchronous on hip_stream.
+ */
+typedef struct {
+  tda_handle h;
+  const double *d; /* device float64[N of h] */
+  const double *H; /* device, B rows, stride ldh */
+  int64_t B;
+  int64_t ldh;
+  double *out;     /* device float64[B] */
+} tda_work;
+
+tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, int32_t precision,
+                            void *hip_stream);
+
+tda_status tda_info(tda_handle h, tda_info_t *info);
+
+/*
+ * Request server: continuous batching of likelihood requests from many
+ * concurrent sampler walkers (the paper's proposal pool, Sec. III.B.2, where
+ * many proposals are evaluated while the sampler waits) against datasets kept
+ * resident in HBM.
+ *
+ * A dataset is one factored handle plus its data vector.  tda_server_submit
+ * enqueues a request of B templates against one dataset and returns at once.
+ * A scheduler thread repeatedly takes, for every dataset with pending work,
+ * the queued requests in arrival order (up to max_batch templates per dataset),
+ * gathers their template rows into one block so a single sweep over the
+ * dataset's operator serves all of them, evaluates all datasets in one
+ * tda_loglik_multi-style launch sequence, and scatters the results.  Up to
+ * n_slots such launches are in flight on separate streams, so requests that
+ * arrive while others run are admitted as soon as a slot and staging memory
+ * free up, and their work overlaps on the device.  A template's result does not
+ * depend on which other templates share its launch.
+ *
+ * Admission: submit returns TDA_EAGAIN when max_queue requests are pending or
+ * when a request alone would exceed a slot's staging memory
+ * (staging_bytes / n_slots); datasets are admitted by tda_server_add_dataset
+ * only while the sum of their handles' device memory stays within
+ * dataset_budget_bytes (0 = no limit), else TDA_ENOMEM.
+ * Latency of a request = completion observed by the server minus submit time.
+ */
+typedef struct tda_server *tda_server_t;
+
+typedef struct {
+  uint32_t struct_size;       /* sizeof(tda_server_options) */
+  int32_t device;             /* -1 = current device */
+  int32_t precision;          /* evaluation precision (datasets must support it) */
+  int32_t n_slots;            /* launches in flight, >= 1 */
+  int32_t max_batch;          /* max templates per dataset per launch, >= 1 */
+  int32_t max_queue;          /* max pending requests before TDA_EAGAIN */
+  size_t staging_bytes;       /* device staging for gathered templates, all slots */
+  size_t dataset_budget_bytes;/* admission cap on resident datasets; 0 = none */
+} tda_server_options;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t launches, templates;
+  int64_t max_queue_depth;
+  double p50_ms, p99_ms, mean_ms, max_ms; /* request latency */
+  double mean_templates_per_launch;
+  double busy_s;                          /* wall time with work in flight */
+} tda_server_stats_t;
+
+tda_status tda_server_create(const tda_server_options *opt, tda_server_t *out);
+/* h: factored handle (not destroyed by the server); d: device float64[N of h],
+ * kept alive by the caller while the server runs.  *dataset receives the id. */
+tda_status tda_server_add_dataset(tda_server_t s, tda_handle h, const double *d, int32_t *dataset);
+/* H: device, B rows (stride ldh >= N); out: device float64[B].  Both stay
+ * owned by the caller and must stay valid until the request completes.
+ * *ticket identifies the request.  Thread-safe. */
+tda_status tda_server_submit(tda_server_t s, int32_t dataset, const double *H, int64_t B,
+                             int64_t ldh, double *out, uint64_t *ticket);
+/* *done = 1 once the request's results are in `out` (device writes finished). */
+tda_status tda_server_poll(tda_server_t s, uint64_t ticket, int32_t *done);
+/* Blocks until the request completed or timeout_s elapsed (TDA_EAGAIN). */
+tda_status tda_server_wait(tda_server_t s, uint64_t ticket, double timeout_s);
+tda_status tda_server_stats(tda_server_t s, tda_server_stats_t *st, int32_t reset);
+/* Drains in-flight work, stops the threads, frees server memory (not the datasets). */
+tda_status tda_server_destroy(tda_server_t s);
+
+/*
+ * Kernel timing (tracing aid).  When enabled, every kernel launch made by the
+ * library is bracketed by two HIP events recorded on the launch's stream, so the
+ * measured interval is that kernel's own execution in stream order.
+ * tda_timing_read synchronises the recorded events and returns, per kernel
+ * name, the number of launches and their summed duration in milliseconds
+ * (at most `max` entries, count in *n); reset != 0 clears the totals.
+ * Process-wide; not intended for concurrent use from several host threads.
+ */
+typedef struct {
+  char name[32];
+  int64_t count;
+  double total_ms;
+} tda_kernel_time;
+
+tda_status tda_timing_enable(int32_t on);
+tda_status tda_timing_read(tda_kernel_time *out, int32_t max, int32_t *n, int32_t reset);
+
+/* Releases all device memory of the handle.  Waits for the device first.
+ * NULL is accepted. */
+tda_status tda_destroy(tda_handle h);
+
+const char *tda_status_str(tda_status s);
+const char *tda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TDA_H */

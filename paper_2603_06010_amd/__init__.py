@@ -1,0 +1,321 @@
+"""Python binding of libtda (argument marshalling only).
+
+Every step of the likelihood runs in the HIP library ``libtda.so`` built in this
+directory (``python -m paper_2603_06010_amd.build``).  PyTorch provides device
+memory and streams: tensors are passed by device pointer together with the
+current HIP stream.  If the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = ["TdaError", "Handle", "loglik_multi", "load_library", "LIB_PATH",
+           "timing_enable", "timing_read", "Server",
+           "PREC_FP64", "PREC_MIXED", "EXPORTED_SYMBOLS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
+PREC_FP64, PREC_MIXED = 0, 1
+EXPORTED_SYMBOLS = [
+    "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
+    "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_timing_enable", "tda_timing_read",
+    "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
+    "tda_server_wait", "tda_server_stats", "tda_server_destroy",
+]
+
+_STATUS = {0: "TDA_OK", 1: "TDA_EINVAL", 2: "TDA_ENOTSPD", 3: "TDA_ENOMEM", 4: "TDA_ESTATE",
+           5: "TDA_ENODEV", 6: "TDA_EHIP", 7: "TDA_EINTERNAL", 8: "TDA_EAGAIN"}
+
+
+class TdaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+class _Segment(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("length", ctypes.c_int64)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_eff", ctypes.c_int64), ("n_pad", ctypes.c_int64),
+                ("n_segments", ctypes.c_int64), ("logdet", ctypes.c_double),
+                ("fail_row", ctypes.c_int64), ("fail_segment", ctypes.c_int32),
+                ("factored", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("data_set", ctypes.c_int32), ("device_bytes", ctypes.c_size_t)]
+
+
+class _KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("count", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
+
+
+class _Work(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_void_p), ("d", ctypes.c_void_p), ("H", ctypes.c_void_p),
+                ("B", ctypes.c_int64), ("ldh", ctypes.c_int64), ("out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtda.so and declare its C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"libtda.so not found at {path}; build it with "
+                      "`python -m paper_2603_06010_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    L.tda_cov_build.argtypes = [vp, i64, i64, vp, vp, i64, vp, ctypes.POINTER(vp)]
+    L.tda_factor.argtypes = [vp]
+    L.tda_set_data.argtypes = [vp, vp, vp]
+    L.tda_loglik.argtypes = [vp, vp, vp, i64, i64, vp, vp]
+    L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
+    L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
+    L.tda_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    L.tda_destroy.argtypes = [vp]
+    L.tda_status_str.argtypes = [ctypes.c_int]
+    L.tda_status_str.restype = ctypes.c_char_p
+    L.tda_last_error.argtypes = []
+    L.tda_last_error.restype = ctypes.c_char_p
+    L.tda_timing_enable.argtypes = [i32]
+    L.tda_timing_read.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
+    for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
+              "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
+              "tda_timing_read"):
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        msg = _lib.tda_last_error().decode(errors="replace")
+        raise TdaError(status, msg)
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError("expected float64")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _precision(p) -> int:
+    if p in (None,):
+        return None
+    if isinstance(p, str):
+        return {"fp64": PREC_FP64, "mixed": PREC_MIXED}[p.lower()]
+    return int(p)
+
+
+class Handle:
+    """One detector's noise model: covariance blocks, FP64 factor and evaluations.
+
+    acf: float64[>= longest segment]; N: samples; gap_mask: uint8[N] (1 = excluded) or None;
+    segments: [(offset, length), ...] or None for one segment [0, N).
+    """
+
+    def __init__(self, acf, N: int, gap_mask=None, segments: Optional[Sequence] = None,
+                 precision="fp64", device: int = -1, hbm_budget: int = 0):
+        L = load_library()
+        acf = np.ascontiguousarray(acf, dtype=np.float64)
+        self._acf = acf
+        mask_ptr = None
+        if gap_mask is not None:
+            m = np.ascontiguousarray(gap_mask, dtype=np.uint8)
+            if m.shape != (N,):
+                raise ValueError("gap_mask must have length N")
+            self._mask = m
+            mask_ptr = m.ctypes.data
+        seg_arr, nseg = None, 0
+        if segments is not None:
+            nseg = len(segments)
+            seg_arr = (_Segment * max(nseg, 1))(*[_Segment(int(o), int(l)) for o, l in segments])
+        opt = _Options(ctypes.sizeof(_Options), _precision(precision), int(device), 0,
+                       int(hbm_budget))
+        h = ctypes.c_void_p()
+        _check(L.tda_cov_build(acf.ctypes.data, len(acf), int(N), mask_ptr,
+                               ctypes.cast(seg_arr, ctypes.c_void_p) if seg_arr is not None else None,
+                               nseg, ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self.N = int(N)
+        self.precision = _precision(precision)
+
+    @property
+    def ptr(self):
+        return self._h.value
+
+    def factor(self):
+        _check(_lib.tda_factor(self._h))
+        return self
+
+    def set_data(self, d, stream=None):
+        _check(_lib.tda_set_data(self._h, _ptr(d), _stream(stream)))
+
+    def loglik(self, d, H, out=None, precision=None, stream=None):
+        import torch
+        if H.dim() != 2:
+            raise ValueError("H must be 2-D")
+        B = H.shape[0]
+        if out is None:
+            out = torch.empty(B, dtype=torch.float64, device=H.device)
+        if B == 0:
+            return out
+        if H.stride(1) != 1:
+            raise ValueError("H rows must be contiguous")
+        p = self.precision if precision is None else _precision(precision)
+        _check(_lib.tda_loglik_ex(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), p,
+                                  _stream(stream)))
+        return out
+
+    def info(self) -> dict:
+        i = _Info()
+        _check(_lib.tda_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _Info._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.tda_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def timing_enable(on: bool = True):
+    """Record HIP events around every library kernel launch (see tda_timing_read)."""
+    _check(load_library().tda_timing_enable(1 if on else 0))
+
+
+def timing_read(reset: bool = True) -> dict:
+    """{kernel name: (launch count, total ms)} of the launches timed so far."""
+    L = load_library()
+    arr = (_KernelTime * 64)()
+    n = ctypes.c_int32()
+    _check(L.tda_timing_read(ctypes.cast(arr, ctypes.c_void_p), 64, ctypes.byref(n),
+                             1 if reset else 0))
+    return {arr[k].name.decode(): (arr[k].count, arr[k].total_ms) for k in range(min(n.value, 64))}
+
+
+def loglik_multi(items, precision="fp64", stream=None):
+    """items: sequence of (Handle, d, H, out) -- items sharing `out` are summed."""
+    L = load_library()
+    arr = (_Work * max(len(items), 1))()
+    for k, (h, d, H, out) in enumerate(items):
+        arr[k] = _Work(h.ptr, _ptr(d), _ptr(H), H.shape[0], H.stride(0), _ptr(out))
+    _check(L.tda_loglik_multi(ctypes.cast(arr, ctypes.c_void_p), len(items),
+                              _precision(precision), _stream(stream)))
+
+
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("staging_bytes", ctypes.c_size_t), ("dataset_budget_bytes", ctypes.c_size_t)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("templates", ctypes.c_int64), ("max_queue_depth", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_templates_per_launch", ctypes.c_double), ("busy_s", ctypes.c_double)]
+
+
+def _declare_server(L):
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.tda_server_create.argtypes = [vp, ctypes.POINTER(vp)]
+    L.tda_server_add_dataset.argtypes = [vp, vp, vp, ctypes.POINTER(i32)]
+    L.tda_server_submit.argtypes = [vp, i32, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.tda_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32)]
+    L.tda_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.c_double]
+    L.tda_server_stats.argtypes = [vp, ctypes.POINTER(_ServerStats), i32]
+    L.tda_server_destroy.argtypes = [vp]
+    for f in ("tda_server_create", "tda_server_add_dataset", "tda_server_submit",
+              "tda_server_poll", "tda_server_wait", "tda_server_stats", "tda_server_destroy"):
+        getattr(L, f).restype = ctypes.c_int
+
+
+class Server:
+    """Continuous-batching request server over resident datasets (see tda.h)."""
+
+    EAGAIN = 8
+
+    def __init__(self, precision="mixed", n_slots=2, max_batch=1024, max_queue=1 << 16,
+                 staging_bytes=64 << 20, dataset_budget_bytes=0, device=-1):
+        L = load_library()
+        _declare_server(L)
+        opt = _ServerOptions(ctypes.sizeof(_ServerOptions), int(device), _precision(precision),
+                             int(n_slots), int(max_batch), int(max_queue), int(staging_bytes),
+                             int(dataset_budget_bytes))
+        s = ctypes.c_void_p()
+        _check(L.tda_server_create(ctypes.byref(opt), ctypes.byref(s)))
+        self._s = s
+        self._keep = []
+
+    def add_dataset(self, handle: Handle, d) -> int:
+        i = ctypes.c_int32()
+        _check(_lib.tda_server_add_dataset(self._s, handle.ptr, _ptr(d), ctypes.byref(i)))
+        self._keep.append((handle, d))
+        return i.value
+
+    def submit(self, dataset: int, H, out) -> Optional[int]:
+        """Returns a ticket, or None if the request was not admitted (TDA_EAGAIN)."""
+        t = ctypes.c_uint64()
+        st = _lib.tda_server_submit(self._s, int(dataset), _ptr(H), H.shape[0], H.stride(0),
+                                    _ptr(out), ctypes.byref(t))
+        if st == self.EAGAIN:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32()
+        _check(_lib.tda_server_poll(self._s, ticket, ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        _check(_lib.tda_server_wait(self._s, ticket, float(timeout_s)))
+
+    def stats(self, reset=False) -> dict:
+        st = _ServerStats()
+        _check(_lib.tda_server_stats(self._s, ctypes.byref(st), 1 if reset else 0))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value:
+            _lib.tda_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

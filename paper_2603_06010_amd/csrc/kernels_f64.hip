@@ -1,0 +1,481 @@
+// FP64 kernels: covariance assembly, blocked Cholesky, diagonal-block inverses,
+// triangular-solve panel packing and the batched FP64 triangular solve with the
+// fused sum-of-squares / log-likelihood epilogue.  gfx950 only.
+//
+// FP64 matrix-core operation used throughout (v_mfma_f64_16x16x4_f64):
+//   D(16x16) += A(16x4) B(4x16); lane l supplies A[l%16][l/16] and B[l/16][l%16]
+//   and holds D[l/16 + 4j][l%16] in register j (j = 0..3).
+#include <math.h>
+
+#include "tda_internal.h"
+
+namespace tda {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------- covariance assembly
+// Dense column-major block of one segment, lower triangle only (paper Sec. II: C_ij =
+// rho(|i-j|); Sec. II.B: the block of a segment restricted to its retained samples).
+// Rows >= n_keep are padding: identity on the diagonal, zero elsewhere, so the
+// padded factor is diag(L, I) and contributes nothing to log det or to w^T w.
+__global__ void k_assemble(const double *__restrict__ acf, const int32_t *__restrict__ idx,
+                           int64_t n_keep, int64_t n_pad, double *__restrict__ A) {
+  const int64_t c = blockIdx.x;
+  const int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (r >= n_pad || r < c) return;
+  double v;
+  if (r < n_keep && c < n_keep) {
+    int64_t lag = (int64_t)idx[r] - (int64_t)idx[c];
+    v = acf[lag < 0 ? -lag : lag];
+  } else {
+    v = (r == c) ? 1.0 : 0.0;
+  }
+  A[c * n_pad + r] = v;
+}
+
+hipError_t launch_assemble(const double *acf, const int32_t *idx, int64_t n_keep, int64_t n_pad,
+                           double *A, hipStream_t s) {
+  dim3 grid((unsigned)n_pad, (unsigned)((n_pad + 255) / 256));
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, acf, idx, n_keep, n_pad, A);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- blocked Cholesky
+// Right-looking, panel width CP = 128, on the lower triangle of a column-major block.
+// Step k: (1) factor the 128x128 diagonal block in LDS and invert it,
+// (2) panel rows below: L_ik = A_ik L_kk^-T, (3) trailing update A_IJ -= L_Ik L_Jk^T.
+// A pivot <= 0 or non-finite stops the factorisation: its row goes to fail[0] and
+// every later kernel returns immediately.
+
+constexpr int TS = CP + 1;  // LDS row stride (bank spread)
+
+__global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t lda, int64_t k,
+                                               double *__restrict__ dinv,
+                                               double *__restrict__ logdiag,
+                                               int32_t *__restrict__ fail) {
+  if (fail[0] >= 0) return;
+  extern __shared__ double T[];  // CP x TS
+  __shared__ double diagX[CP];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < CP * CP; e += 256) {
+    const int c = e / CP, r = e % CP;
+    if (r >= c) T[r * TS + c] = A[(k + c) * lda + k + r];
+  }
+  if (tid == 0) bad = -1;
+  __syncthreads();
+  const int cl = tid & (CP - 1);
+  const int half = tid >> 7;
+  for (int j = 0; j < CP; ++j) {
+    if (tid == 0) {
+      const double dj = T[j * TS + j];
+      if (!(dj > 0.0) || !isfinite(dj))
+        bad = j;
+      else
+        T[j * TS + j] = sqrt(dj);
+    }
+    __syncthreads();
+    if (bad >= 0) break;
+    const double piv = T[j * TS + j];
+    for (int r = j + 1 + tid; r < CP; r += 256) T[r * TS + j] /= piv;
+    __syncthreads();
+    if (cl > j) {
+      const double lcj = T[cl * TS + j];
+      for (int r = cl + half; r < CP; r += 2) T[r * TS + cl] -= T[r * TS + j] * lcj;
+    }
+    __syncthreads();
+  }
+  if (bad >= 0) {
+    if (tid == 0) fail[0] = (int32_t)(k + bad);
+    return;
+  }
+  // L back to global (lower, incl. diagonal)
+  for (int e = tid; e < CP * CP; e += 256) {
+    const int c = e / CP, r = e % CP;
+    if (r >= c) A[(k + c) * lda + k + r] = T[r * TS + c];
+  }
+  // X = L^-1 (lower): thread c solves column c; X[r][c] (r > c) kept in T[c][r] (strict upper).
+  if (tid < CP) {
+    const int c = tid;
+    const double xcc = 1.0 / T[c * TS + c];
+    diagX[c] = xcc;
+    for (int r = c + 1; r < CP; ++r) {
+      double s = T[r * TS + c] * xcc;
+      for (int q = c + 1; q < r; ++q) s += T[r * TS + q] * T[c * TS + q];
+      T[c * TS + r] = -s / T[r * TS + r];
+    }
+  }
+  __syncthreads();
+  // dinv[t*CP + c] = X[c][t]  (row t of X^T)
+  for (int e = tid; e < CP * CP; e += 256) {
+    const int t = e / CP, c = e % CP;
+    double v = 0.0;
+    if (c > t) v = T[t * TS + c];
+    else if (c == t) v = diagX[t];
+    dinv[e] = v;
+  }
+  if (tid == 0) {
+    double s = 0.0;
+    for (int j = 0; j < CP; ++j) s += log(T[j * TS + j]);
+    logdiag[0] = s;
+  }
+}
+
+// rows i in [k+CP, n): L[i, k:k+CP] = A[i, k:k+CP] * X^T, X = L_kk^-1; 64 rows per workgroup.
+__global__ __launch_bounds__(256) void k_panel(double *__restrict__ A, int64_t lda, int64_t k,
+                                               const double *__restrict__ dinvT,
+                                               const int32_t *__restrict__ fail) {
+  if (fail[0] >= 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int64_t i0 = k + CP + (int64_t)blockIdx.x * 64 + 16 * w;
+  d4 acc[8];
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct) acc[ct] = d4{0, 0, 0, 0};
+  for (int t0 = 0; t0 < CP; t0 += 4) {
+    const double a = A[(k + t0 + lr) * lda + i0 + lc];
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      const double b = dinvT[(t0 + lr) * CP + 16 * ct + lc];
+      acc[ct] = mfma64(a, b, acc[ct]);
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) A[(k + 16 * ct + lc) * lda + i0 + lr + 4 * j] = acc[ct][j];
+}
+
+// trailing update of lower 64x64 tiles (I >= J) of the region [k+CP, n)
+__global__ __launch_bounds__(256) void k_syrk(double *__restrict__ A, int64_t lda, int64_t k,
+                                              const int32_t *__restrict__ fail) {
+  if (fail[0] >= 0) return;
+  const int64_t e = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > e) --I;
+  while ((I + 1) * (I + 2) / 2 <= e) ++I;
+  const int64_t J = e - I * (I + 1) / 2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int64_t k1 = k + CP;
+  const int64_t I0 = k1 + 64 * I + 16 * w, J0 = k1 + 64 * J;
+  d4 acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0, 0, 0, 0};
+#pragma unroll 4
+  for (int t0 = 0; t0 < CP; t0 += 4) {
+    const double *col = A + (k + t0 + lr) * lda;
+    const double a = col[I0 + lc];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma64(a, col[J0 + 16 * ct + lc], acc[ct]);
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) A[(J0 + 16 * ct + lc) * lda + I0 + lr + 4 * j] -= acc[ct][j];
+}
+
+hipError_t launch_cholesky(double *A, int64_t n, double *dinv, double *logdiag, int32_t *fail,
+                           hipStream_t s) {
+  const size_t lds = sizeof(double) * CP * TS;
+  for (int64_t k = 0; k < n; k += CP) {
+    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), lds, s, A, n, k, dinv + (k / CP) * CP * CP,
+                       logdiag + k / CP, fail);
+    const int64_t rest = n - k - CP;
+    if (rest > 0) {
+      hipLaunchKernelGGL(k_panel, dim3((unsigned)(rest / 64)), dim3(256), 0, s, A, n, k,
+                         dinv + (k / CP) * CP * CP, fail);
+      const int64_t T = rest / 64;
+      hipLaunchKernelGGL(k_syrk, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, A, n, k,
+                         fail);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------- inverses of TB x TB diagonal blocks
+// inv([Ai^-1 0; B C]) with the two CP x CP Cholesky inverses:
+//   [Ai 0; X21 Ci], X21 = -Ci B Ai.  Output row-major TB x TB (upper part zero).
+__global__ __launch_bounds__(256) void k_diag_inverse(const double *__restrict__ A, int64_t lda,
+                                                      const double *__restrict__ dinv128,
+                                                      double *__restrict__ out) {
+  extern __shared__ double T1[];  // CP x TS : B * Ai
+  const int b = blockIdx.x;
+  const int64_t r0 = (int64_t)b * TB;
+  const double *dA = dinv128 + (int64_t)(2 * b) * CP * CP;      // dA[t*CP + c] = Ai[c][t]
+  const double *dC = dinv128 + (int64_t)(2 * b + 1) * CP * CP;  // dC[t*CP + c] = Ci[c][t]
+  double *O = out + (int64_t)b * TB * TB;
+  const int tid = threadIdx.x;
+  // T1[r][c] = sum_{t >= c} B[r][t] Ai[t][c],  B[r][t] = L[r0+CP+r][r0+t]
+  for (int e = tid; e < CP * CP; e += 256) {
+    const int r = e % CP, c = e / CP;
+    double s = 0.0;
+    for (int t = c; t < CP; ++t) s += A[(r0 + t) * lda + r0 + CP + r] * dA[c * CP + t];
+    T1[r * TS + c] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < TB * TB; e += 256) {
+    const int r = e / TB, c = e % TB;
+    double v = 0.0;
+    if (r < CP) {
+      if (c < CP && c <= r) v = dA[c * CP + r];
+    } else if (c < CP) {
+      const int rr = r - CP;
+      double s = 0.0;
+      for (int t = 0; t <= rr; ++t) s += dC[t * CP + rr] * T1[t * TS + c];
+      v = -s;
+    } else {
+      const int rr = r - CP, cc = c - CP;
+      if (cc <= rr) v = dC[cc * CP + rr];
+    }
+    O[e] = v;
+  }
+}
+
+hipError_t launch_diag_inverse(const double *A, int64_t n, const double *dinv128, double *dinv256,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_inverse, dim3((unsigned)(n / TB)), dim3(256),
+                     sizeof(double) * CP * TS, s, A, n, dinv128, dinv256);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- panel packing
+// Block row i (TB rows) of a segment owns K_i = i*TB off-diagonal columns and TB
+// diagonal-inverse columns.  Layout [s][t][lane]: k-step s (4 columns), row tile t
+// (16 rows), lane l holds row 16t + l%16, column 4s + l/16 -- exactly the A operand
+// of the FP64 matrix-core op.  Off-diagonal entries are stored negated so the solve
+// accumulates with plain multiply-adds.
+__global__ void k_pack(const double *__restrict__ A, int64_t lda, const double *__restrict__ dinv256,
+                       double *__restrict__ panels, const int64_t *__restrict__ offs, int32_t blk0) {
+  const int i = blockIdx.y;  // local block row
+  const int64_t K = (int64_t)i * TB;
+  const int64_t total = (K + TB) * TB;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int lane = (int)(e & 63), t = (int)((e >> 6) & 15);
+  const int64_t s = e >> 10;
+  const int64_t row = 16 * t + (lane & 15);
+  const int64_t col = 4 * s + (lane >> 4);
+  double v;
+  if (col < K)
+    v = -A[col * lda + K + row];
+  else
+    v = dinv256[(int64_t)i * TB * TB + row * TB + (col - K)];
+  panels[offs[blk0 + i] + e] = v;
+}
+
+hipError_t launch_pack_panels(const double *A, int64_t n, int64_t row0, const double *dinv256,
+                              double *panels, const int64_t *panel_off_dev, int32_t blk0,
+                              int32_t nblk_seg, hipStream_t s) {
+  (void)row0;
+  const int64_t maxel = (int64_t)nblk_seg * TB * TB;
+  dim3 grid((unsigned)((maxel + 255) / 256), (unsigned)nblk_seg);
+  hipLaunchKernelGGL(k_pack, grid, dim3(256), 0, s, A, n, dinv256, panels, panel_off_dev, blk0);
+  return hipGetLastError();
+}
+
+__global__ void k_sum_logdet(const double *logdiag, int64_t count, double *logdet) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int64_t i = 0; i < count; ++i) s += logdiag[i];
+    logdet[0] = 2.0 * s;
+  }
+}
+
+hipError_t launch_sum_logdet(const double *logdiag, int64_t count, double *logdet, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(64), 0, s, logdiag, count, logdet);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- batched FP64 triangular solve
+// One workgroup solves L W = R for 32 right-hand sides (columns c0..c0+31) over the block
+// rows [blk_begin, blk_end), left-looking (paper Sec. III.A, the CDL solve):
+//   acc = R_i + sum_{j<i} (-L_ij) W_j      (FP64 matrix cores, panel streamed from HBM/L2)
+//   W_i = inv(L_ii) acc                    (acc staged in LDS)
+// Four waves; wave w owns the 16-row tiles w, w+4, w+8, w+12 of each block row, so the
+// triangular diagonal product is balanced.  Solved rows go to the tile's scratch and are
+// re-read by later block rows.  MODE_LOGLIK fuses R = d - h_b on the retained rows and
+// the epilogue out[b] = -1/2 sum_i W[i][b]^2 + cterm (eq:td_like_whitened plus the
+// constant); MODE_IDENTITY solves against identity columns (W = L^-1).
+__device__ __forceinline__ void trsm_tile(const TrsmItem &it, const TrsmTile &tl) {
+  __shared__ double S[TB * BC];
+  __shared__ double red[4][4][BC];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  double *W = it.scratch + tl.w_off;
+  const int64_t rbase = (int64_t)tl.blk_begin * TB;
+  double ss0 = 0.0, ss1 = 0.0;
+
+  for (int i = tl.blk_begin; i < tl.blk_end; ++i) {
+    d4 acc[4][2];
+    const int64_t rowblk = (int64_t)i * TB;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = w + 4 * j;
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc) {
+        const int col = 16 * tc + lc;
+        const int b = tl.c0 + col;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = rowblk + 16 * t + lr + 4 * v;
+          double val = 0.0;
+          if (it.mode == MODE_LOGLIK) {
+            const int32_t p = it.idx[row];
+            if (p >= 0 && b < it.B) val = it.d[p] - template_row(it, b)[p];
+          } else {
+            val = (row == (int64_t)b) ? 1.0 : 0.0;
+          }
+          acc[j][tc][v] = val;
+        }
+      }
+    }
+    const double *P = it.panels + it.panel_off[i];
+    const int bf = it.blk_first[i];
+    const int f = bf > tl.blk_begin ? bf : tl.blk_begin;
+    const int s_begin = (f - bf) * (TB / 4);
+    const int s_end = (i - bf) * (TB / 4);
+    const double *Wk = W + ((int64_t)f * TB - rbase) * BC;
+#pragma unroll 4
+    for (int s = s_begin; s < s_end; ++s) {
+      const double *Ps = P + (int64_t)s * 16 * 64 + lane;
+      double a0 = Ps[(w + 0) * 64], a1 = Ps[(w + 4) * 64], a2 = Ps[(w + 8) * 64],
+             a3 = Ps[(w + 12) * 64];
+      const double *Wr = Wk + ((int64_t)(s - s_begin) * 4 + lr) * BC + lc;
+      const double b0 = Wr[0], b1 = Wr[16];
+      acc[0][0] = mfma64(a0, b0, acc[0][0]);
+      acc[0][1] = mfma64(a0, b1, acc[0][1]);
+      acc[1][0] = mfma64(a1, b0, acc[1][0]);
+      acc[1][1] = mfma64(a1, b1, acc[1][1]);
+      acc[2][0] = mfma64(a2, b0, acc[2][0]);
+      acc[2][1] = mfma64(a2, b1, acc[2][1]);
+      acc[3][0] = mfma64(a3, b0, acc[3][0]);
+      acc[3][1] = mfma64(a3, b1, acc[3][1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tc = 0; tc < 2; ++tc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          S[(16 * (w + 4 * j) + lr + 4 * v) * BC + 16 * tc + lc] = acc[j][tc][v];
+    __syncthreads();
+    double *Wi = W + (rowblk - rbase) * BC;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int t = w + 4 * j;
+      d4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
+      const double *Pd = P + (int64_t)s_end * 16 * 64 + t * 64 + lane;
+      for (int s2 = 0; s2 < 4 * (t + 1); ++s2) {
+        const double a = Pd[(int64_t)s2 * 16 * 64];
+        const double *Sr = S + (4 * s2 + lr) * BC + lc;
+        x0 = mfma64(a, Sr[0], x0);
+        x1 = mfma64(a, Sr[16], x1);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = 16 * t + lr + 4 * v;
+        Wi[r * BC + lc] = x0[v];
+        Wi[r * BC + 16 + lc] = x1[v];
+        ss0 += x0[v] * x0[v];
+        ss1 += x1[v] * x1[v];
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (it.mode == MODE_LOGLIK) {
+    red[w][lr][lc] = ss0;
+    red[w][lr][16 + lc] = ss1;
+    __syncthreads();
+    if (threadIdx.x < BC) {
+      const int col = threadIdx.x;
+      double q = 0.0;
+      for (int w2 = 0; w2 < 4; ++w2)
+        for (int r2 = 0; r2 < 4; ++r2) q += red[w2][r2][col];
+      const int b = tl.c0 + col;
+      if (b < it.B) it.out[b] = -0.5 * q + it.cterm;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256, 1) void k_trsm_f64(const TrsmItem *__restrict__ items,
+                                                     const TrsmTile *__restrict__ tiles) {
+  const TrsmTile tl = tiles[blockIdx.x];
+  const TrsmItem it = items[tl.item];
+  trsm_tile(it, tl);
+}
+
+hipError_t launch_trsm_f64(const TrsmItem *items, const TrsmTile *tiles, int64_t n_tiles,
+                           hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_f64, dim3((unsigned)n_tiles), dim3(256), 0, s, items, tiles);
+  return hipGetLastError();
+}
+
+// One item passed by value; tile t covers columns [32t, 32t+32) over all block rows.
+__global__ __launch_bounds__(256, 1) void k_trsm_f64_single(const TrsmItem it, int32_t nblk) {
+  const TrsmTile tl{0, (int32_t)(blockIdx.x * BC), 0, nblk,
+                    (int64_t)blockIdx.x * (int64_t)nblk * TB * BC};
+  trsm_tile(it, tl);
+}
+
+hipError_t launch_trsm_f64_single(const TrsmItem &it, int32_t nblk, int64_t n_tiles,
+                                  hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_trsm_f64_single, dim3((unsigned)n_tiles), dim3(256), 0, s, it, nblk);
+  return hipGetLastError();
+}
+
+void register_kernel_attributes() {
+  hipFuncSetAttribute((const void *)k_potf2, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(sizeof(double) * CP * TS));
+  hipFuncSetAttribute((const void *)k_diag_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(sizeof(double) * CP * TS));
+}
+
+// ---------------------------------------------------------------- network sums
+// out_g[b] = sum over the items of group g (in item order) of parts_item[b].
+__global__ void k_combine(const double *__restrict__ parts, const int64_t *__restrict__ part_off,
+                          const int32_t *__restrict__ group_of, int64_t n_items,
+                          double *const *__restrict__ outs, const int64_t *__restrict__ Bs) {
+  const int g = blockIdx.y;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= Bs[g]) return;
+  double s = 0.0;
+  for (int64_t it = 0; it < n_items; ++it)
+    if (group_of[it] == g) s += parts[part_off[it] + b];
+  outs[g][b] = s;
+}
+
+hipError_t launch_combine(const double *parts, const int64_t *part_off, const int32_t *group_of,
+                          int64_t n_items, double *const *outs, const int64_t *Bs,
+                          int64_t n_groups, int64_t max_B, hipStream_t s) {
+  if (n_groups <= 0 || max_B <= 0) return hipSuccess;
+  dim3 grid((unsigned)((max_B + 255) / 256), (unsigned)n_groups);
+  hipLaunchKernelGGL(k_combine, grid, dim3(256), 0, s, parts, part_off, group_of, n_items, outs, Bs);
+  return hipGetLastError();
+}
+
+// Copy result runs: desc[3k] = destination pointer (as integer), desc[3k+1] = source
+// offset, desc[3k+2] = count.
+__global__ void k_scatter(const int64_t *__restrict__ desc, const double *__restrict__ src) {
+  const int64_t k = blockIdx.x;
+  double *dst = reinterpret_cast<double *>(desc[3 * k]);
+  const int64_t off = desc[3 * k + 1], cnt = desc[3 * k + 2];
+  for (int64_t j = threadIdx.x; j < cnt; j += blockDim.x) dst[j] = src[off + j];
+}
+
+hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)n), dim3(64), 0, s, desc, src);
+  return hipGetLastError();
+}
+
+}  // namespace tda

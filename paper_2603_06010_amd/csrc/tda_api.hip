@@ -1,0 +1,1161 @@
+// libtda C ABI: handles, device memory, validation and the launch sequences of the
+// factorisation and of the FP64 / mixed-precision log-likelihood evaluations.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tda_internal.h"
+
+using namespace tda;
+
+namespace {
+
+thread_local std::string g_err;
+
+tda_status fail_with(tda_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail_with(TDA_EHIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                       __FILE__, __LINE__);                                                 \
+  } while (0)
+
+#define TDA_TRY(expr)            \
+  do {                           \
+    tda_status s_ = (expr);      \
+    if (s_ != TDA_OK) return s_; \
+  } while (0)
+
+const double kLog2Pi = 1.8378770664093454835606594728112;
+
+struct Seg {
+  int64_t offset, length, n_keep, n_pad, row0;
+  int32_t blk0, nblk;
+  int64_t m;
+  int32_t log2m;
+};
+
+// Device buffer with budget accounting.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Ring of pinned host staging slots and matching device buffers for per-call
+// descriptors.  A slot is reused only after the work that read it has finished.
+struct DescRing {
+  static constexpr int K = 4;
+  void *host[K] = {};
+  void *dev[K] = {};
+  size_t cap[K] = {};
+  hipEvent_t ev[K] = {};
+  int next = 0;
+  int cur = -1;
+
+  // Returns a device pointer holding a copy of `data` (enqueued on s).
+  hipError_t push(const void *data, size_t n, hipStream_t s, void **dptr) {
+    if (cur < 0) {
+      cur = next;
+      next = (next + 1) % K;
+      if (ev[cur]) {
+        hipError_t e = hipEventSynchronize(ev[cur]);
+        if (e != hipSuccess) return e;
+      }
+      used = 0;
+    }
+    const size_t need = used + ((n + 255) & ~(size_t)255);
+    if (need > cap[cur]) {
+      if (used) return hipErrorInvalidValue;  // one growth per call, before any push
+      if (host[cur]) hipHostFree(host[cur]);
+      if (dev[cur]) hipFree(dev[cur]);
+      host[cur] = dev[cur] = nullptr;
+      size_t c = std::max(need * 2, (size_t)1 << 16);
+      hipError_t e = hipHostMalloc(&host[cur], c, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      e = hipMalloc(&dev[cur], c);
+      if (e != hipSuccess) return e;
+      cap[cur] = c;
+    }
+    memcpy((char *)host[cur] + used, data, n);
+    hipError_t e = hipMemcpyAsync((char *)dev[cur] + used, (char *)host[cur] + used, n,
+                                  hipMemcpyHostToDevice, s);
+    *dptr = (char *)dev[cur] + used;
+    used = need;
+    return e;
+  }
+  // Reserve room for a whole call up front (so a call never grows mid-way).
+  hipError_t reserve(size_t total) {
+    if (cur >= 0) return hipSuccess;
+    int slot = next;
+    if (ev[slot]) {
+      hipError_t e = hipEventSynchronize(ev[slot]);
+      if (e != hipSuccess) return e;
+    }
+    if (total > cap[slot]) {
+      if (host[slot]) hipHostFree(host[slot]);
+      if (dev[slot]) hipFree(dev[slot]);
+      host[slot] = dev[slot] = nullptr;
+      cap[slot] = 0;
+      size_t c = std::max(total * 2, (size_t)1 << 16);
+      hipError_t e = hipHostMalloc(&host[slot], c, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      e = hipMalloc(&dev[slot], c);
+      if (e != hipSuccess) return e;
+      cap[slot] = c;
+    }
+    cur = slot;
+    next = (next + 1) % K;
+    used = 0;
+    return hipSuccess;
+  }
+  hipError_t seal(hipStream_t s) {
+    if (cur < 0) return hipSuccess;
+    if (!ev[cur]) {
+      hipError_t e = hipEventCreateWithFlags(&ev[cur], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipEventRecord(ev[cur], s);
+    cur = -1;
+    return e;
+  }
+  void destroy() {
+    for (int k = 0; k < K; ++k) {
+      if (ev[k]) hipEventSynchronize(ev[k]), hipEventDestroy(ev[k]);
+      if (host[k]) hipHostFree(host[k]);
+      if (dev[k]) hipFree(dev[k]);
+      host[k] = dev[k] = nullptr;
+      ev[k] = nullptr;
+      cap[k] = 0;
+    }
+  }
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct tda_ctx {
+  int device = 0;
+  int precision = TDA_PREC_FP64;
+  size_t budget = 0;
+  size_t held = 0;
+  int64_t N = 0, n_eff = 0, n_pad = 0;
+  int32_t nblk = 0;
+  std::vector<Seg> segs;
+  std::vector<double> acf;
+  std::vector<int32_t> blk_first_h, blk_last_h;
+  std::vector<int64_t> panel_off_h;
+  int64_t panel_total = 0;
+
+  // device state
+  DevBuf acf_d, idx_d, pos2row_d, blk_first_d, blk_last_d;
+  DevBuf A_d;          // dense per-segment blocks (until factored)
+  DevBuf dinv128_d, dinv256_d, logdiag_d, logdet_d, fail_d;
+  DevBuf panels_d, panel_off_d;
+  double logdet = 0.0;
+  bool factored = false;
+  int64_t fail_row = -1;
+  int32_t fail_segment = -1;
+
+  // mixed state
+  DevBuf w64_d, w64_off_d, w64_rb_d;
+  DevBuf wa_hi, wa_lo, wb_hi, wb_lo, wa_off_d, wb_off_d;
+  DevBuf lam_d, tw_d, segdev_d;
+  DevBuf dbar_d, yd_d, ydpos_d, qdd_d;
+  const double *data_ptr = nullptr;
+
+  // workspaces
+  DevBuf ws_scratch, ws_tiles, ws_items;
+  DevBuf ws_hs_hi, ws_hs_lo, ws_w0_hi, ws_w0_lo, ws_y0, ws_fft, ws_work, ws_mix, ws_ref;
+  hipEvent_t done = nullptr;  // last enqueued work of this handle
+  DescRing ring;
+  std::vector<SegDev> segdev_h;
+  int64_t max_m = 0;
+  std::vector<int64_t> w64_off_h;
+  std::vector<int32_t> w64_rb_h;
+  std::vector<int64_t> wa_off_h, wb_off_h;
+  int64_t work_Bp = -1;      // Bp the cached mixed work lists were built for
+  int64_t n_work_fwd = 0, n_work_bwd = 0;
+
+  tda_status alloc(DevBuf &b, size_t bytes) {
+    if (b.p) {
+      if (b.bytes >= bytes) return TDA_OK;
+      hipDeviceSynchronize();
+      hipFree(b.p);
+      held -= b.bytes;
+      b.p = nullptr;
+      b.bytes = 0;
+    }
+    if (bytes == 0) bytes = 256;
+    if (budget && held + bytes > budget)
+      return fail_with(TDA_ENOMEM, "HBM budget exceeded: need %zu more bytes, hold %zu of %zu",
+                       bytes, held, budget);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+      b.p = nullptr;
+      return fail_with(TDA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.bytes = bytes;
+    held += bytes;
+    return TDA_OK;
+  }
+  void release(DevBuf &b) {
+    if (b.p) {
+      hipFree(b.p);
+      held -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  void release_all() {
+    DevBuf *all[] = {&acf_d,   &idx_d,    &pos2row_d,  &blk_first_d, &blk_last_d, &A_d,
+                     &dinv128_d, &dinv256_d, &logdiag_d, &logdet_d,  &fail_d,     &panels_d,
+                     &panel_off_d, &w64_d, &w64_off_d, &w64_rb_d,    &wa_hi,      &wa_lo,
+                     &wb_hi,   &wb_lo,    &wa_off_d,   &wb_off_d,    &lam_d,      &tw_d,
+                     &segdev_d, &dbar_d,  &yd_d,       &ydpos_d,     &qdd_d,      &ws_scratch,
+                     &ws_tiles, &ws_items, &ws_hs_hi,  &ws_hs_lo,    &ws_w0_hi,   &ws_w0_lo,
+                     &ws_y0,   &ws_fft,   &ws_work,    &ws_mix,      &ws_ref};
+    for (DevBuf *b : all) release(*b);
+  }
+  double cterm() const { return -0.5 * logdet - 0.5 * (double)n_eff * kLog2Pi; }
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    hipGetDevice(&prev);
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+std::once_flag g_attr_once;
+void set_kernel_attributes();
+
+tda_status upload(tda_ctx *h, DevBuf &b, const void *src, size_t bytes) {
+  TDA_TRY(h->alloc(b, bytes));
+  HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+  return TDA_OK;
+}
+
+// Wait (on `s`) for the handle's previous work, so workspaces are never shared by two
+// calls that run concurrently on different streams.
+tda_status order_after_previous(tda_ctx *h, hipStream_t s) {
+  if (!h->done) HIP_TRY(hipEventCreateWithFlags(&h->done, hipEventDisableTiming));
+  HIP_TRY(hipStreamWaitEvent(s, h->done, 0));
+  return TDA_OK;
+}
+
+tda_status mark_done(tda_ctx *h, hipStream_t s) {
+  HIP_TRY(hipEventRecord(h->done, s));
+  return TDA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- build
+
+extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t N,
+                                    const uint8_t *gap_mask, const tda_segment *segments,
+                                    int64_t n_segments, const tda_options *opt, tda_handle *out) {
+  if (!out) return fail_with(TDA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!acf) return fail_with(TDA_EINVAL, "acf is NULL");
+  if (N < 1) return fail_with(TDA_EINVAL, "N must be >= 1");
+  if (N > (int64_t)1 << 30) return fail_with(TDA_EINVAL, "N too large");
+  if (!(acf_len >= 1) || !(acf[0] > 0.0) || !isfinite(acf[0]))
+    return fail_with(TDA_EINVAL, "acf[0] must be positive and finite");
+  if (n_segments < 0 || (n_segments > 0 && !segments))
+    return fail_with(TDA_EINVAL, "bad segment list");
+  tda_options o{sizeof(tda_options), TDA_PREC_FP64, -1, 0, 0};
+  if (opt) {
+    if (opt->struct_size < sizeof(tda_options)) return fail_with(TDA_EINVAL, "options struct_size");
+    o = *opt;
+  }
+  if (o.precision != TDA_PREC_FP64 && o.precision != TDA_PREC_MIXED)
+    return fail_with(TDA_EINVAL, "unknown precision %d", o.precision);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail_with(TDA_ENODEV, "no HIP device");
+  int dev = o.device;
+  if (dev < 0) hipGetDevice(&dev);
+  if (dev >= ndev) return fail_with(TDA_EINVAL, "device %d out of range", dev);
+
+  std::vector<tda_segment> segs;
+  if (n_segments == 0)
+    segs.push_back({0, N});
+  else
+    segs.assign(segments, segments + n_segments);
+  int64_t prev_end = 0, longest = 0;
+  for (size_t i = 0; i < segs.size(); ++i) {
+    const tda_segment &s = segs[i];
+    if (s.length < 1 || s.offset < prev_end || s.offset + s.length > N)
+      return fail_with(TDA_EINVAL, "segment %zu must be non-empty, sorted, disjoint, inside [0,N)",
+                       i);
+    prev_end = s.offset + s.length;
+    longest = std::max(longest, s.length);
+  }
+  if (acf_len < longest)
+    return fail_with(TDA_EINVAL, "acf_len %lld shorter than the longest segment %lld",
+                     (long long)acf_len, (long long)longest);
+  for (int64_t i = 0; i < longest; ++i)
+    if (!isfinite(acf[i])) return fail_with(TDA_EINVAL, "acf[%lld] is not finite", (long long)i);
+
+  std::call_once(g_attr_once, set_kernel_attributes);
+  DeviceGuard guard(dev);
+  tda_ctx *h = new tda_ctx();
+  h->device = dev;
+  h->precision = o.precision;
+  h->budget = o.hbm_budget_bytes;
+  h->N = N;
+  h->acf.assign(acf, acf + longest);
+
+  std::vector<int32_t> idx, pos2row((size_t)N, -1);
+  int64_t row = 0;
+  int32_t blk = 0;
+  for (const tda_segment &s : segs) {
+    Seg g{};
+    g.offset = s.offset;
+    g.length = s.length;
+    g.row0 = row;
+    g.blk0 = blk;
+    int64_t keep = 0;
+    for (int64_t j = s.offset; j < s.offset + s.length; ++j) {
+      if (gap_mask && gap_mask[j]) continue;
+      pos2row[j] = (int32_t)(row + keep);
+      idx.push_back((int32_t)j);
+      ++keep;
+    }
+    if (keep == 0) continue;  // a fully excluded segment contributes nothing
+    g.n_keep = keep;
+    g.n_pad = (keep + TB - 1) / TB * TB;
+    for (int64_t j = keep; j < g.n_pad; ++j) idx.push_back(-1);
+    g.nblk = (int32_t)(g.n_pad / TB);
+    int32_t l2 = 0;
+    while (((int64_t)1 << l2) < 2 * g.length) ++l2;
+    g.log2m = l2;
+    g.m = (int64_t)1 << l2;
+    for (int32_t b = 0; b < g.nblk; ++b) {
+      h->blk_first_h.push_back(g.blk0);
+      h->blk_last_h.push_back(g.blk0 + g.nblk - 1);
+    }
+    row += g.n_pad;
+    blk += g.nblk;
+    h->n_eff += keep;
+    h->segs.push_back(g);
+  }
+  if (h->n_eff == 0) {
+    delete h;
+    return fail_with(TDA_EINVAL, "no retained sample");
+  }
+  h->n_pad = row;
+  h->nblk = blk;
+  if (h->n_pad > ((int64_t)1 << 31) / TB) {
+    delete h;
+    return fail_with(TDA_EINVAL, "too many rows");
+  }
+  // panel offsets: block row i of its segment has (local i + 1) * TB * TB doubles
+  h->panel_off_h.resize(h->nblk);
+  int64_t off = 0;
+  for (const Seg &g : h->segs)
+    for (int32_t i = 0; i < g.nblk; ++i) {
+      h->panel_off_h[g.blk0 + i] = off;
+      off += (int64_t)(i + 1) * TB * TB;
+    }
+  h->panel_total = off;
+
+  tda_status st = TDA_OK;
+  auto cleanup = [&](tda_status s) {
+    h->release_all();
+    delete h;
+    return s;
+  };
+  if ((st = upload(h, h->acf_d, h->acf.data(), h->acf.size() * sizeof(double))) != TDA_OK ||
+      (st = upload(h, h->idx_d, idx.data(), idx.size() * sizeof(int32_t))) != TDA_OK ||
+      (st = upload(h, h->pos2row_d, pos2row.data(), pos2row.size() * sizeof(int32_t))) != TDA_OK ||
+      (st = upload(h, h->blk_first_d, h->blk_first_h.data(), h->nblk * sizeof(int32_t))) != TDA_OK ||
+      (st = upload(h, h->blk_last_d, h->blk_last_h.data(), h->nblk * sizeof(int32_t))) != TDA_OK ||
+      (st = upload(h, h->panel_off_d, h->panel_off_h.data(), h->nblk * sizeof(int64_t))) != TDA_OK)
+    return cleanup(st);
+  // dense blocks (lower triangle used), assembled now
+  size_t dense = 0;
+  for (const Seg &g : h->segs) dense += (size_t)g.n_pad * g.n_pad;
+  if ((st = h->alloc(h->A_d, dense * sizeof(double))) != TDA_OK) return cleanup(st);
+  size_t a_off = 0;
+  for (const Seg &g : h->segs) {
+    hipError_t e = launch_assemble((const double *)h->acf_d.p, (const int32_t *)h->idx_d.p + g.row0,
+                                   g.n_keep, g.n_pad, (double *)h->A_d.p + a_off, 0);
+    if (e != hipSuccess)
+      return cleanup(fail_with(TDA_EHIP, "assemble launch: %s", hipGetErrorString(e)));
+    a_off += (size_t)g.n_pad * g.n_pad;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cleanup(fail_with(TDA_EHIP, "assemble: %s", hipGetErrorString(e)));
+  *out = h;
+  return TDA_OK;
+}
+
+// ---------------------------------------------------------------- factor
+
+static tda_status build_mixed(tda_ctx *h);
+
+extern "C" tda_status tda_factor(tda_handle h) {
+  if (!h) return fail_with(TDA_EINVAL, "NULL handle");
+  if (h->factored) return TDA_OK;
+  if (!h->A_d.p) return fail_with(TDA_ESTATE, "handle has no assembled covariance");
+  DeviceGuard guard(h->device);
+  int64_t ncp = 0;
+  for (const Seg &g : h->segs) ncp += g.n_pad / CP;
+  TDA_TRY(h->alloc(h->dinv128_d, (size_t)ncp * CP * CP * sizeof(double)));
+  TDA_TRY(h->alloc(h->dinv256_d, (size_t)h->nblk * TB * TB * sizeof(double)));
+  TDA_TRY(h->alloc(h->logdiag_d, (size_t)ncp * sizeof(double)));
+  TDA_TRY(h->alloc(h->logdet_d, sizeof(double)));
+  TDA_TRY(h->alloc(h->fail_d, sizeof(int32_t)));
+  TDA_TRY(h->alloc(h->panels_d, (size_t)h->panel_total * sizeof(double)));
+  size_t a_off = 0;
+  int64_t cp_off = 0;
+  for (size_t si = 0; si < h->segs.size(); ++si) {
+    const Seg &g = h->segs[si];
+    int32_t minus1 = -1;
+    HIP_TRY(hipMemcpy(h->fail_d.p, &minus1, sizeof minus1, hipMemcpyHostToDevice));
+    double *A = (double *)h->A_d.p + a_off;
+    double *dinv = (double *)h->dinv128_d.p + cp_off * CP * CP;
+    HIP_TRY(launch_cholesky(A, g.n_pad, dinv, (double *)h->logdiag_d.p + cp_off,
+                            (int32_t *)h->fail_d.p, 0));
+    int32_t failrow = -1;
+    HIP_TRY(hipMemcpy(&failrow, h->fail_d.p, sizeof failrow, hipMemcpyDeviceToHost));
+    if (failrow >= 0) {
+      h->fail_row = failrow;
+      h->fail_segment = (int32_t)si;
+      return fail_with(TDA_ENOTSPD,
+                       "covariance not positive definite: pivot of retained row %d of segment %zu",
+                       failrow, si);
+    }
+    double *d256 = (double *)h->dinv256_d.p + (int64_t)g.blk0 * TB * TB;
+    HIP_TRY(launch_diag_inverse(A, g.n_pad, dinv, d256, 0));
+    HIP_TRY(launch_pack_panels(A, g.n_pad, g.row0, d256, (double *)h->panels_d.p,
+                               (const int64_t *)h->panel_off_d.p, g.blk0, g.nblk, 0));
+    a_off += (size_t)g.n_pad * g.n_pad;
+    cp_off += g.n_pad / CP;
+  }
+  HIP_TRY(launch_sum_logdet((const double *)h->logdiag_d.p, ncp, (double *)h->logdet_d.p, 0));
+  HIP_TRY(hipMemcpy(&h->logdet, h->logdet_d.p, sizeof(double), hipMemcpyDeviceToHost));
+  h->release(h->A_d);
+  h->release(h->dinv128_d);
+  h->release(h->dinv256_d);
+  if (!isfinite(h->logdet)) return fail_with(TDA_ENOTSPD, "log det is not finite");
+  if (h->precision == TDA_PREC_MIXED) TDA_TRY(build_mixed(h));
+  h->factored = true;
+  return TDA_OK;
+}
+
+// ---------------------------------------------------------------- FP64 evaluation
+
+static tda_status loglik_f64(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
+                             double *out, hipStream_t s) {
+  const int64_t ntile = (B + BC - 1) / BC;
+  TDA_TRY(h->alloc(h->ws_scratch, (size_t)ntile * h->n_pad * BC * sizeof(double)));
+  TrsmItem it{};
+  it.panels = (const double *)h->panels_d.p;
+  it.panel_off = (const int64_t *)h->panel_off_d.p;
+  it.blk_first = (const int32_t *)h->blk_first_d.p;
+  it.idx = (const int32_t *)h->idx_d.p;
+  it.d = d;
+  it.H = H;
+  it.ldh = ldh;
+  it.out = out;
+  it.scratch = (double *)h->ws_scratch.p;
+  it.cterm = h->cterm();
+  it.B = (int32_t)B;
+  it.mode = MODE_LOGLIK;
+  {
+    TimedScope ts("trsm_f64", s);
+    HIP_TRY(launch_trsm_f64_single(it, h->nblk, ntile, s));
+  }
+  return TDA_OK;
+}
+
+static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
+                               int64_t ldh, double *out, hipStream_t s);
+
+extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t B,
+                                    int64_t ldh, double *out, int32_t precision,
+                                    void *hip_stream) {
+  if (!h) return fail_with(TDA_EINVAL, "NULL handle");
+  if (!h->factored) return fail_with(TDA_ESTATE, "tda_loglik before a successful tda_factor");
+  if (B < 0) return fail_with(TDA_EINVAL, "B < 0");
+  if (B == 0) return TDA_OK;
+  if (B > (int64_t)1 << 30) return fail_with(TDA_EINVAL, "B too large");
+  if (!d || !H || !out) return fail_with(TDA_EINVAL, "NULL device pointer");
+  if (ldh < h->N) return fail_with(TDA_EINVAL, "ldh < N");
+  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED)
+    return fail_with(TDA_EINVAL, "unknown precision");
+  if (precision == TDA_PREC_MIXED && h->precision != TDA_PREC_MIXED)
+    return fail_with(TDA_ESTATE, "mixed evaluation needs a handle built with TDA_PREC_MIXED");
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(order_after_previous(h, s));
+  if (precision == TDA_PREC_FP64)
+    TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
+  else
+    TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s));
+  return mark_done(h, s);
+}
+
+extern "C" tda_status tda_loglik(tda_handle h, const double *d, const double *H, int64_t B,
+                                 int64_t ldh, double *out, void *hip_stream) {
+  if (!h) return fail_with(TDA_EINVAL, "NULL handle");
+  return tda_loglik_ex(h, d, H, B, ldh, out, h->precision, hip_stream);
+}
+
+// ---------------------------------------------------------------- mixed precision
+
+namespace {
+
+// Work list in XCD-aware order: hardware dispatches workgroup g to XCD g % 8, so the
+// entries of one block (all template groups) are queued on the same XCD, where they
+// share that block's operator panel in L2; blocks are dealt to XCDs round-robin and
+// each XCD queue runs its largest blocks first.
+struct BlockJob {
+  int32_t item, block, ntg;
+  int64_t k;  // work weight (K of the block)
+};
+
+std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
+  constexpr int NX = 8;
+  std::vector<std::vector<BlockJob>> q(NX);
+  for (size_t n = 0; n < jobs.size(); ++n) q[n % NX].push_back(jobs[n]);
+  std::vector<std::vector<int4>> lists(NX);
+  size_t longest = 0;
+  for (int x = 0; x < NX; ++x) {
+    std::stable_sort(q[x].begin(), q[x].end(),
+                     [](const BlockJob &a, const BlockJob &b) { return a.k > b.k; });
+    for (const BlockJob &j : q[x])
+      for (int t = 0; t < j.ntg; ++t) lists[x].push_back(int4{j.item, j.block, t, 0});
+    longest = std::max(longest, lists[x].size());
+  }
+  std::vector<int4> out(longest * NX, int4{0, -1, 0, 0});
+  for (int x = 0; x < NX; ++x)
+    for (size_t k = 0; k < lists[x].size(); ++k) out[k * NX + x] = lists[x][k];
+  return out;
+}
+
+constexpr int kRefineWG = 512;
+
+}  // namespace
+
+static tda_status build_mixed(tda_ctx *h) {
+  const int64_t nct = h->n_pad / 32;
+  h->w64_off_h.resize(nct);
+  h->w64_rb_h.resize(nct);
+  std::vector<TrsmTile> tiles(nct);
+  int64_t off = 0;
+  for (int64_t ct = 0; ct < nct; ++ct) {
+    const int32_t blk = (int32_t)(ct * 32 / TB);
+    const int32_t last = h->blk_last_h[blk];
+    h->w64_off_h[ct] = off;
+    h->w64_rb_h[ct] = blk * TB;
+    tiles[ct] = TrsmTile{0, (int32_t)(ct * 32), blk, last + 1, off};
+    off += (int64_t)(last + 1 - blk) * TB * 32;
+  }
+  TDA_TRY(h->alloc(h->w64_d, (size_t)off * sizeof(double)));
+  TDA_TRY(upload(h, h->w64_off_d, h->w64_off_h.data(), nct * sizeof(int64_t)));
+  TDA_TRY(upload(h, h->w64_rb_d, h->w64_rb_h.data(), nct * sizeof(int32_t)));
+  // W = L^-1 by the FP64 solve against identity columns (rows above a column are zero
+  // and skipped).
+  TrsmItem it{};
+  it.panels = (const double *)h->panels_d.p;
+  it.panel_off = (const int64_t *)h->panel_off_d.p;
+  it.blk_first = (const int32_t *)h->blk_first_d.p;
+  it.idx = (const int32_t *)h->idx_d.p;
+  it.scratch = (double *)h->w64_d.p;
+  it.B = (int32_t)h->n_pad;
+  it.mode = MODE_IDENTITY;
+  TDA_TRY(upload(h, h->ws_items, &it, sizeof it));
+  TDA_TRY(upload(h, h->ws_tiles, tiles.data(), tiles.size() * sizeof(TrsmTile)));
+  HIP_TRY(launch_trsm_f64((const TrsmItem *)h->ws_items.p, (const TrsmTile *)h->ws_tiles.p, nct, 0));
+  // BF16 hi/lo copies in fragment layouts
+  h->wa_off_h.resize(h->nblk);
+  h->wb_off_h.resize(h->nblk);
+  int64_t wa = 0, wb = 0, max_k = 0;
+  for (int32_t i = 0; i < h->nblk; ++i) {
+    const int64_t ka = (int64_t)(i + 1 - h->blk_first_h[i]) * TB;
+    const int64_t kb = (int64_t)(h->blk_last_h[i] + 1 - i) * TB;
+    h->wa_off_h[i] = wa;
+    h->wb_off_h[i] = wb;
+    wa += ka * TB;
+    wb += kb * TB;
+    max_k = std::max(max_k, std::max(ka, kb));
+  }
+  TDA_TRY(upload(h, h->wa_off_d, h->wa_off_h.data(), h->nblk * sizeof(int64_t)));
+  TDA_TRY(upload(h, h->wb_off_d, h->wb_off_h.data(), h->nblk * sizeof(int64_t)));
+  TDA_TRY(h->alloc(h->wa_hi, (size_t)wa * 2));
+  TDA_TRY(h->alloc(h->wa_lo, (size_t)wa * 2));
+  TDA_TRY(h->alloc(h->wb_hi, (size_t)wb * 2));
+  TDA_TRY(h->alloc(h->wb_lo, (size_t)wb * 2));
+  HIP_TRY(launch_split_w((const double *)h->w64_d.p, (const int64_t *)h->w64_off_d.p,
+                         (const int32_t *)h->w64_rb_d.p, (const int32_t *)h->blk_first_d.p,
+                         (const int32_t *)h->blk_last_d.p, h->nblk, (uint16_t *)h->wa_hi.p,
+                         (uint16_t *)h->wa_lo.p, (const int64_t *)h->wa_off_d.p,
+                         (uint16_t *)h->wb_hi.p, (uint16_t *)h->wb_lo.p,
+                         (const int64_t *)h->wb_off_d.p, max_k, 0, 0));
+  // circulant eigenvalues and twiddles per segment
+  int64_t msum = 0;
+  for (const Seg &g : h->segs) msum += g.m;
+  TDA_TRY(h->alloc(h->lam_d, (size_t)msum * sizeof(double)));
+  TDA_TRY(h->alloc(h->tw_d, (size_t)2 * msum * sizeof(double)));
+  h->segdev_h.clear();
+  int64_t mo = 0;
+  for (const Seg &g : h->segs) {
+    double *lam = (double *)h->lam_d.p + mo;
+    double *tw = (double *)h->tw_d.p + 2 * mo;
+    HIP_TRY(launch_lambda((const double *)h->acf_d.p, g.length, g.m, tw, lam, 0));
+    SegDev sd{};
+    sd.offset = g.offset;
+    sd.length = g.length;
+    sd.row0 = g.row0;
+    sd.m = g.m;
+    sd.log2m = g.log2m;
+    sd.lam = lam;
+    sd.tw = tw;
+    h->segdev_h.push_back(sd);
+    h->max_m = std::max(h->max_m, g.m);
+    mo += g.m;
+  }
+  TDA_TRY(upload(h, h->segdev_d, h->segdev_h.data(), h->segdev_h.size() * sizeof(SegDev)));
+  HIP_TRY(hipDeviceSynchronize());
+  return TDA_OK;
+}
+
+static tda_status set_data_impl(tda_ctx *h, const double *d, hipStream_t s) {
+  TDA_TRY(h->alloc(h->dbar_d, (size_t)h->n_pad * sizeof(double)));
+  TDA_TRY(h->alloc(h->yd_d, (size_t)h->n_pad * sizeof(double)));
+  TDA_TRY(h->alloc(h->ydpos_d, (size_t)h->N * sizeof(double)));
+  TDA_TRY(h->alloc(h->qdd_d, sizeof(double)));
+  HIP_TRY(launch_data_whiten((const double *)h->w64_d.p, (const int64_t *)h->w64_off_d.p,
+                             (const int32_t *)h->w64_rb_d.p, (const int32_t *)h->blk_first_d.p,
+                             (const int32_t *)h->blk_last_d.p, (const int32_t *)h->idx_d.p,
+                             (int32_t)h->n_pad, h->N, d, (double *)h->dbar_d.p,
+                             (double *)h->yd_d.p, (double *)h->ydpos_d.p, (double *)h->qdd_d.p, s));
+  h->data_ptr = d;
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_set_data(tda_handle h, const double *d, void *hip_stream) {
+  if (!h) return fail_with(TDA_EINVAL, "NULL handle");
+  if (!h->factored) return fail_with(TDA_ESTATE, "tda_set_data before tda_factor");
+  if (!d) return fail_with(TDA_EINVAL, "NULL data");
+  if (h->precision != TDA_PREC_MIXED) return TDA_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(order_after_previous(h, s));
+  TDA_TRY(set_data_impl(h, d, s));
+  return mark_done(h, s);
+}
+
+// Per-call operand workspace of one mixed item.
+struct MixWs {
+  uint16_t *hs_hi, *hs_lo, *w0_hi, *w0_lo;
+  float *y0;
+};
+
+static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int64_t B,
+                             int64_t Bp, const MixWs &ws) {
+  MixItem mi{};
+  mi.wa_hi = (const uint16_t *)h->wa_hi.p;
+  mi.wa_lo = (const uint16_t *)h->wa_lo.p;
+  mi.wb_hi = (const uint16_t *)h->wb_hi.p;
+  mi.wb_lo = (const uint16_t *)h->wb_lo.p;
+  mi.wa_off = (const int64_t *)h->wa_off_d.p;
+  mi.wb_off = (const int64_t *)h->wb_off_d.p;
+  mi.blk_first = (const int32_t *)h->blk_first_d.p;
+  mi.blk_last = (const int32_t *)h->blk_last_d.p;
+  mi.idx = (const int32_t *)h->idx_d.p;
+  mi.H = H;
+  mi.ldh = ldh;
+  mi.hs_hi = ws.hs_hi;
+  mi.hs_lo = ws.hs_lo;
+  mi.w0_hi = ws.w0_hi;
+  mi.w0_lo = ws.w0_lo;
+  mi.y0 = ws.y0;
+  mi.B = (int32_t)B;
+  mi.Bp = (int32_t)Bp;
+  mi.nblk = h->nblk;
+  mi.n_pad = (int32_t)h->n_pad;
+  return mi;
+}
+
+static RefItem make_ref_item(const tda_ctx *h, const double *H, int64_t ldh, int64_t B,
+                             const float *y0, double *out) {
+  RefItem ri{};
+  ri.segs = (const SegDev *)h->segdev_d.p;
+  ri.n_segs = (int32_t)h->segdev_h.size();
+  ri.B = (int32_t)B;
+  ri.pos2row = (const int32_t *)h->pos2row_d.p;
+  ri.y0 = y0;
+  ri.H = H;
+  ri.ldh = ldh;
+  ri.yd_pos = (const double *)h->ydpos_d.p;
+  ri.qdd = (const double *)h->qdd_d.p;
+  ri.out = out;
+  ri.cterm = h->cterm();
+  ri.n_pad = (int32_t)h->n_pad;
+  return ri;
+}
+
+static void add_block_jobs(const tda_ctx *h, int32_t item, int32_t ntg, bool transposed,
+                           std::vector<BlockJob> &jobs) {
+  for (int32_t i = 0; i < h->nblk; ++i) {
+    const int64_t k = transposed ? (int64_t)(h->blk_last_h[i] + 1 - i)
+                                 : (int64_t)(i + 1 - h->blk_first_h[i]);
+    jobs.push_back(BlockJob{item, i, ntg, k});
+  }
+}
+
+static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
+                               int64_t ldh, double *out, hipStream_t s) {
+  if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
+  const int64_t Bp = (B + MT - 1) / MT * MT;
+  const int32_t ntg = (int32_t)(Bp / MT);
+  const size_t el = (size_t)Bp * h->n_pad;
+  TDA_TRY(h->alloc(h->ws_hs_hi, el * 2));
+  TDA_TRY(h->alloc(h->ws_hs_lo, el * 2));
+  TDA_TRY(h->alloc(h->ws_w0_hi, el * 2));
+  TDA_TRY(h->alloc(h->ws_w0_lo, el * 2));
+  TDA_TRY(h->alloc(h->ws_y0, el * 4));
+  TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
+  MixWs ws{(uint16_t *)h->ws_hs_hi.p, (uint16_t *)h->ws_hs_lo.p, (uint16_t *)h->ws_w0_hi.p,
+           (uint16_t *)h->ws_w0_lo.p, (float *)h->ws_y0.p};
+  const MixItem mi = make_mix_item(h, H, ldh, B, Bp, ws);
+  const RefItem ri = make_ref_item(h, H, ldh, B, ws.y0, out);
+  std::vector<BlockJob> jf, jb;
+  add_block_jobs(h, 0, ntg, false, jf);
+  add_block_jobs(h, 0, ntg, true, jb);
+  const std::vector<int4> wf = xcd_order(jf), wb = xcd_order(jb);
+  std::vector<int2> wr(B);
+  for (int64_t b = 0; b < B; ++b) wr[b] = int2{0, (int32_t)b};
+  const size_t total = 4 * 256 + sizeof mi + sizeof ri + (wf.size() + wb.size()) * sizeof(int4) +
+                       wr.size() * sizeof(int2);
+  HIP_TRY(h->ring.reserve(total));
+  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr;
+  HIP_TRY(h->ring.push(&mi, sizeof mi, s, &d_mi));
+  HIP_TRY(h->ring.push(&ri, sizeof ri, s, &d_ri));
+  HIP_TRY(h->ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
+  HIP_TRY(h->ring.push(wb.data(), wb.size() * sizeof(int4), s, &d_wb));
+  HIP_TRY(h->ring.push(wr.data(), wr.size() * sizeof(int2), s, &d_wr));
+  {
+    TimedScope ts("split_h", s);
+    HIP_TRY(launch_split_h((const MixItem *)d_mi, 0, Bp, h->n_pad, s));
+  }
+  {
+    TimedScope ts("trmm_fwd", s);
+    HIP_TRY(launch_trmm_fwd((const MixItem *)d_mi, (const int4 *)d_wf, (int64_t)wf.size(), s));
+  }
+  {
+    TimedScope ts("trmm_bwd", s);
+    HIP_TRY(launch_trmm_bwd((const MixItem *)d_mi, (const int4 *)d_wb, (int64_t)wb.size(), s));
+  }
+  {
+    TimedScope ts("refine_fft", s);
+    HIP_TRY(launch_refine((const RefItem *)d_ri, (const int2 *)d_wr, B, (double *)h->ws_fft.p,
+                          2 * h->max_m, kRefineWG, s));
+  }
+  HIP_TRY(h->ring.seal(s));
+  return TDA_OK;
+}
+
+// ---------------------------------------------------------------- batched multi-item evaluation
+
+namespace {
+
+}  // namespace
+
+struct tda::MultiCtx {
+  std::mutex mu;
+  tda_ctx pool;  // used only for its allocator and buffers
+  DescRing ring;
+  hipEvent_t done = nullptr;
+};
+
+namespace {
+
+MultiCtx *multi_ctx(int dev) {
+  static std::mutex g;
+  static std::vector<MultiCtx *> ctxs;
+  std::lock_guard<std::mutex> lk(g);
+  if ((int)ctxs.size() <= dev) ctxs.resize(dev + 1, nullptr);
+  if (!ctxs[dev]) ctxs[dev] = new MultiCtx();
+  return ctxs[dev];
+}
+
+tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
+                      int64_t n_items, int32_t precision, hipStream_t s, bool order_handles);
+
+}  // namespace
+
+namespace tda {
+MultiCtx *multi_ctx_create() { return new MultiCtx(); }
+void multi_ctx_destroy(MultiCtx *mc) {
+  if (!mc) return;
+  mc->pool.release_all();
+  mc->ring.destroy();
+  if (mc->done) (void)hipEventDestroy(mc->done);
+  delete mc;
+}
+tda_status multi_eval(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
+                      int64_t n_items, int32_t precision, hipStream_t s) {
+  return multi_impl(mc, items, hrows, n_items, precision, s, false);
+}
+int handle_device(tda_handle h) { return h->device; }
+int64_t handle_n(tda_handle h) { return h->N; }
+size_t handle_bytes(tda_handle h) { return h->held; }
+bool handle_ready(tda_handle h, int32_t precision) {
+  return h->factored && (precision == TDA_PREC_FP64 || h->precision == TDA_PREC_MIXED);
+}
+tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s) {
+  if (h->precision != TDA_PREC_MIXED || h->data_ptr == d) return TDA_OK;
+  return set_data_impl(h, d, s);
+}
+tda_status set_error(tda_status st, const char *msg) { return fail_with(st, "%s", msg); }
+}  // namespace tda
+
+extern "C" tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, int32_t precision,
+                                       void *hip_stream) {
+  if (n_items < 0 || (n_items > 0 && !items)) return fail_with(TDA_EINVAL, "bad item list");
+  if (n_items == 0) return TDA_OK;
+  if (!items[0].h) return fail_with(TDA_EINVAL, "item 0: NULL handle");
+  MultiCtx *mc = multi_ctx(items[0].h->device);
+  std::lock_guard<std::mutex> lk(mc->mu);
+  DeviceGuard guard(items[0].h->device);
+  return multi_impl(mc, items, nullptr, n_items, precision, (hipStream_t)hip_stream, true);
+}
+
+namespace {
+tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
+                      int64_t n_items, int32_t precision, hipStream_t s, bool order_handles) {
+  if (n_items == 0) return TDA_OK;
+  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED)
+    return fail_with(TDA_EINVAL, "unknown precision");
+  const int dev = items[0].h ? items[0].h->device : -1;
+  std::vector<double *> group_out;
+  std::vector<int64_t> group_B;
+  std::vector<int32_t> group_of(n_items);
+  std::vector<int64_t> part_off(n_items);
+  int64_t parts = 0, max_B = 0;
+  for (int64_t k = 0; k < n_items; ++k) {
+    const tda_work &w = items[k];
+    if (!w.h) return fail_with(TDA_EINVAL, "item %lld: NULL handle", (long long)k);
+    if (!w.h->factored) return fail_with(TDA_ESTATE, "item %lld: handle not factored", (long long)k);
+    if (w.h->device != dev) return fail_with(TDA_EINVAL, "items on different devices");
+    if (w.B < 0 || w.B > ((int64_t)1 << 30)) return fail_with(TDA_EINVAL, "item %lld: bad B", (long long)k);
+    if (w.B > 0 && (!w.d || !(w.H || (hrows && hrows[k])) || !w.out))
+      return fail_with(TDA_EINVAL, "item %lld: NULL pointer", (long long)k);
+    if (w.ldh < w.h->N) return fail_with(TDA_EINVAL, "item %lld: ldh < N", (long long)k);
+    if (precision == TDA_PREC_MIXED && w.h->precision != TDA_PREC_MIXED)
+      return fail_with(TDA_ESTATE, "item %lld: handle not built for mixed precision", (long long)k);
+    int32_t g = -1;
+    for (size_t q = 0; q < group_out.size(); ++q)
+      if (group_out[q] == w.out) g = (int32_t)q;
+    if (g < 0) {
+      g = (int32_t)group_out.size();
+      group_out.push_back(w.out);
+      group_B.push_back(w.B);
+    } else if (group_B[g] != w.B) {
+      return fail_with(TDA_EINVAL, "items sharing an output must have equal B");
+    }
+    group_of[k] = g;
+    part_off[k] = parts;
+    parts += w.B;
+    max_B = std::max(max_B, w.B);
+    if (precision == TDA_PREC_MIXED)
+      for (int64_t q = 0; q < k; ++q)
+        if (items[q].h == w.h && items[q].d != w.d)
+          return fail_with(TDA_EINVAL, "one handle used with two data vectors in one call");
+  }
+  if (max_B == 0) return TDA_OK;
+  tda_ctx &P = mc->pool;
+  if (!mc->done) HIP_TRY(hipEventCreateWithFlags(&mc->done, hipEventDisableTiming));
+  HIP_TRY(hipStreamWaitEvent(s, mc->done, 0));
+  for (int64_t k = 0; k < n_items; ++k) {
+    if (order_handles) TDA_TRY(order_after_previous(items[k].h, s));
+    if (precision == TDA_PREC_MIXED && items[k].B > 0 && items[k].d != items[k].h->data_ptr)
+      TDA_TRY(set_data_impl(items[k].h, items[k].d, s));
+  }
+  TDA_TRY(P.alloc(P.ws_work, (size_t)parts * sizeof(double)));
+  double *partbuf = (double *)P.ws_work.p;
+  std::vector<void *> blobs;
+  if (precision == TDA_PREC_FP64) {
+    std::vector<TrsmItem> its(n_items);
+    std::vector<TrsmTile> tiles;
+    int64_t scratch = 0;
+    for (int64_t k = 0; k < n_items; ++k) {
+      const tda_work &w = items[k];
+      tda_ctx *h = w.h;
+      TrsmItem &it = its[k];
+      it.panels = (const double *)h->panels_d.p;
+      it.panel_off = (const int64_t *)h->panel_off_d.p;
+      it.blk_first = (const int32_t *)h->blk_first_d.p;
+      it.idx = (const int32_t *)h->idx_d.p;
+      it.d = w.d;
+      it.H = w.H;
+      it.ldh = w.ldh;
+      it.Hrows = hrows ? hrows[k] : nullptr;
+      it.out = partbuf + part_off[k];
+      it.cterm = h->cterm();
+      it.B = (int32_t)w.B;
+      it.mode = MODE_LOGLIK;
+      const int64_t nt = (w.B + BC - 1) / BC;
+      for (int64_t t = 0; t < nt; ++t)
+        tiles.push_back(TrsmTile{(int32_t)k, (int32_t)(t * BC), 0, h->nblk,
+                                 scratch + t * h->n_pad * BC});
+      it.scratch = (double *)(intptr_t)scratch;  // offset; rebased below
+      scratch += nt * h->n_pad * BC;
+    }
+    TDA_TRY(P.alloc(P.ws_scratch, (size_t)scratch * sizeof(double)));
+    for (int64_t k = 0; k < n_items; ++k) its[k].scratch = (double *)P.ws_scratch.p;
+    // longest sweeps first
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const TrsmTile &a, const TrsmTile &b) {
+      return items[a.item].h->n_pad > items[b.item].h->n_pad;
+    });
+    HIP_TRY(mc->ring.reserve(2048 + its.size() * sizeof(TrsmItem) + tiles.size() * sizeof(TrsmTile) +
+                             n_items * 16 + group_out.size() * 16));
+    void *d_its, *d_tiles;
+    HIP_TRY(mc->ring.push(its.data(), its.size() * sizeof(TrsmItem), s, &d_its));
+    HIP_TRY(mc->ring.push(tiles.data(), tiles.size() * sizeof(TrsmTile), s, &d_tiles));
+    TimedScope ts("trsm_f64", s);
+    HIP_TRY(launch_trsm_f64((const TrsmItem *)d_its, (const TrsmTile *)d_tiles,
+                            (int64_t)tiles.size(), s));
+  } else {
+    std::vector<MixItem> mis(n_items);
+    std::vector<RefItem> ris(n_items);
+    std::vector<BlockJob> jf, jb;
+    std::vector<int2> wr;
+    size_t el_total = 0;
+    int64_t max_m = 0;
+    std::vector<size_t> el_off(n_items);
+    for (int64_t k = 0; k < n_items; ++k) {
+      const int64_t Bp = (items[k].B + MT - 1) / MT * MT;
+      el_off[k] = el_total;
+      el_total += (size_t)Bp * items[k].h->n_pad;
+      max_m = std::max(max_m, items[k].h->max_m);
+    }
+    TDA_TRY(P.alloc(P.ws_hs_hi, el_total * 2));
+    TDA_TRY(P.alloc(P.ws_hs_lo, el_total * 2));
+    TDA_TRY(P.alloc(P.ws_w0_hi, el_total * 2));
+    TDA_TRY(P.alloc(P.ws_w0_lo, el_total * 2));
+    TDA_TRY(P.alloc(P.ws_y0, el_total * 4));
+    TDA_TRY(P.alloc(P.ws_fft, (size_t)kRefineWG * max_m * 16));
+    for (int64_t k = 0; k < n_items; ++k) {
+      const tda_work &w = items[k];
+      const int64_t Bp = (w.B + MT - 1) / MT * MT;
+      MixWs ws{(uint16_t *)P.ws_hs_hi.p + el_off[k], (uint16_t *)P.ws_hs_lo.p + el_off[k],
+               (uint16_t *)P.ws_w0_hi.p + el_off[k], (uint16_t *)P.ws_w0_lo.p + el_off[k],
+               (float *)P.ws_y0.p + el_off[k]};
+      mis[k] = make_mix_item(w.h, w.H, w.ldh, w.B, Bp, ws);
+      ris[k] = make_ref_item(w.h, w.H, w.ldh, w.B, ws.y0, partbuf + part_off[k]);
+      mis[k].Hrows = ris[k].Hrows = hrows ? hrows[k] : nullptr;
+      if (w.B == 0) continue;
+      add_block_jobs(w.h, (int32_t)k, (int32_t)(Bp / MT), false, jf);
+      add_block_jobs(w.h, (int32_t)k, (int32_t)(Bp / MT), true, jb);
+      for (int64_t b = 0; b < w.B; ++b) wr.push_back(int2{(int32_t)k, (int32_t)b});
+    }
+    const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
+    HIP_TRY(mc->ring.reserve(4096 + n_items * (sizeof(MixItem) + sizeof(RefItem)) +
+                             (wf.size() + wbk.size()) * sizeof(int4) + wr.size() * sizeof(int2) +
+                             n_items * 16 + group_out.size() * 16));
+    void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr;
+    HIP_TRY(mc->ring.push(mis.data(), mis.size() * sizeof(MixItem), s, &d_mi));
+    HIP_TRY(mc->ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
+    HIP_TRY(mc->ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
+    HIP_TRY(mc->ring.push(wbk.data(), wbk.size() * sizeof(int4), s, &d_wb));
+    HIP_TRY(mc->ring.push(wr.data(), wr.size() * sizeof(int2), s, &d_wr));
+    {
+      TimedScope ts("split_h", s);
+      for (int64_t k = 0; k < n_items; ++k)
+        if (items[k].B > 0)
+          HIP_TRY(launch_split_h((const MixItem *)d_mi, (int32_t)k, mis[k].Bp, items[k].h->n_pad, s));
+    }
+    {
+      TimedScope ts("trmm_fwd", s);
+      HIP_TRY(launch_trmm_fwd((const MixItem *)d_mi, (const int4 *)d_wf, (int64_t)wf.size(), s));
+    }
+    {
+      TimedScope ts("trmm_bwd", s);
+      HIP_TRY(launch_trmm_bwd((const MixItem *)d_mi, (const int4 *)d_wb, (int64_t)wbk.size(), s));
+    }
+    {
+      TimedScope ts("refine_fft", s);
+      HIP_TRY(launch_refine((const RefItem *)d_ri, (const int2 *)d_wr, (int64_t)wr.size(),
+                            (double *)P.ws_fft.p, 2 * max_m, kRefineWG, s));
+    }
+  }
+  // network sums per output array, in item order
+  void *d_off, *d_grp, *d_outs, *d_Bs;
+  HIP_TRY(mc->ring.push(part_off.data(), n_items * sizeof(int64_t), s, &d_off));
+  HIP_TRY(mc->ring.push(group_of.data(), n_items * sizeof(int32_t), s, &d_grp));
+  HIP_TRY(mc->ring.push(group_out.data(), group_out.size() * sizeof(double *), s, &d_outs));
+  HIP_TRY(mc->ring.push(group_B.data(), group_B.size() * sizeof(int64_t), s, &d_Bs));
+  HIP_TRY(launch_combine(partbuf, (const int64_t *)d_off, (const int32_t *)d_grp, n_items,
+                         (double *const *)d_outs, (const int64_t *)d_Bs,
+                         (int64_t)group_out.size(), max_B, s));
+  HIP_TRY(mc->ring.seal(s));
+  HIP_TRY(hipEventRecord(mc->done, s));
+  if (order_handles)
+    for (int64_t k = 0; k < n_items; ++k) TDA_TRY(mark_done(items[k].h, s));
+  return TDA_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------- kernel timing
+
+namespace {
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<tda_kernel_time> totals;
+};
+TimingState &timing() {
+  static TimingState t;
+  return t;
+}
+hipEvent_t pool_event(TimingState &t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+}  // namespace
+
+namespace tda {
+TimedScope::TimedScope(const char *n, hipStream_t s) : name(n), stream(s), slot(-1) {
+  TimingState &t = timing();
+  if (!t.on) return;
+  std::lock_guard<std::mutex> lk(t.mu);
+  TimingState::Rec r{n, pool_event(t), pool_event(t)};
+  (void)hipEventRecord(r.a, s);
+  t.pending.push_back(r);
+  slot = (int)t.pending.size() - 1;
+}
+TimedScope::~TimedScope() {
+  if (slot < 0) return;
+  TimingState &t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  if (slot < (int)t.pending.size()) (void)hipEventRecord(t.pending[slot].b, stream);
+}
+}  // namespace tda
+
+extern "C" tda_status tda_timing_enable(int32_t on) {
+  timing().on = on != 0;
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_timing_read(tda_kernel_time *out, int32_t max, int32_t *n,
+                                      int32_t reset) {
+  TimingState &t = timing();
+  std::lock_guard<std::mutex> lk(t.mu);
+  for (auto &r : t.pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    tda_kernel_time *slot = nullptr;
+    for (auto &k : t.totals)
+      if (r.name == k.name) slot = &k;
+    if (!slot) {
+      tda_kernel_time k{};
+      snprintf(k.name, sizeof k.name, "%s", r.name.c_str());
+      t.totals.push_back(k);
+      slot = &t.totals.back();
+    }
+    slot->count += 1;
+    slot->total_ms += ms;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.pending.clear();
+  const int32_t cnt = (int32_t)std::min<size_t>(t.totals.size(), max > 0 ? max : 0);
+  for (int32_t k = 0; k < cnt; ++k) out[k] = t.totals[k];
+  if (n) *n = (int32_t)t.totals.size();
+  if (reset) t.totals.clear();
+  return TDA_OK;
+}
+
+// ---------------------------------------------------------------- info / destroy / strings
+
+extern "C" tda_status tda_info(tda_handle h, tda_info_t *info) {
+  if (!h || !info) return fail_with(TDA_EINVAL, "NULL argument");
+  info->n = h->N;
+  info->n_eff = h->n_eff;
+  info->n_pad = h->n_pad;
+  info->n_segments = (int64_t)h->segs.size();
+  info->logdet = h->logdet;
+  info->fail_row = h->fail_row;
+  info->fail_segment = h->fail_segment;
+  info->factored = h->factored ? 1 : 0;
+  info->precision = h->precision;
+  info->data_set = h->data_ptr ? 1 : 0;
+  info->device_bytes = h->held;
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_destroy(tda_handle h) {
+  if (!h) return TDA_OK;
+  {
+    DeviceGuard guard(h->device);
+    hipDeviceSynchronize();
+    h->release_all();
+    if (h->done) hipEventDestroy(h->done);
+    h->ring.destroy();
+  }
+  delete h;
+  return TDA_OK;
+}
+
+extern "C" const char *tda_status_str(tda_status s) {
+  switch (s) {
+    case TDA_OK: return "TDA_OK";
+    case TDA_EINVAL: return "TDA_EINVAL: invalid argument";
+    case TDA_ENOTSPD: return "TDA_ENOTSPD: covariance not positive definite";
+    case TDA_ENOMEM: return "TDA_ENOMEM: out of device memory or budget";
+    case TDA_ESTATE: return "TDA_ESTATE: call out of order";
+    case TDA_ENODEV: return "TDA_ENODEV: no HIP device";
+    case TDA_EHIP: return "TDA_EHIP: HIP runtime error";
+    case TDA_EINTERNAL: return "TDA_EINTERNAL: internal error";
+    case TDA_EAGAIN: return "TDA_EAGAIN: not admitted now, retry";
+  }
+  return "unknown status";
+}
+
+extern "C" const char *tda_last_error(void) { return g_err.c_str(); }
+
+namespace {
+void set_kernel_attributes() { tda::register_kernel_attributes(); }
+}  // namespace

@@ -1,0 +1,175 @@
+// Internal declarations shared by the libtda translation units (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tda.h"
+
+namespace tda {
+
+// Row padding unit and block size of the FP64 triangular solve (rows per block row).
+constexpr int TB = 256;
+// Panel width of the FP64 Cholesky.
+constexpr int CP = 128;
+// Columns (templates) per workgroup of the FP64 triangular solve.
+constexpr int BC = 32;
+// Mixed path: templates per workgroup tile of the BF16x3 products.
+constexpr int MT = 128;
+
+// ---------------------------------------------------------------- device-side work descriptors
+
+// One (handle, data, templates) evaluation of the FP64 solve.
+struct TrsmItem {
+  const double *panels;     // packed panels (see pack_panels)
+  const int64_t *panel_off; // [nblk] element offset of each block row's panel
+  const int32_t *blk_first; // [nblk] first block row of the segment containing the block row
+  const int32_t *idx;       // [n_pad] sample index of each padded row, -1 = padding
+  const double *d;          // data (MODE_LOGLIK)
+  const double *H;          // templates, row stride ldh (MODE_LOGLIK)
+  int64_t ldh;
+  const double *const *Hrows; // optional per-template row pointers (overrides H, ldh)
+  double *out;              // [B] results (MODE_LOGLIK)
+  double *scratch;          // solution rows of every column tile of this item
+  double cterm;             // -1/2 logdet - N_eff/2 log 2 pi
+  int32_t B;                // templates (MODE_LOGLIK) or columns (MODE_IDENTITY)
+  int32_t mode;
+};
+
+enum { MODE_LOGLIK = 0, MODE_IDENTITY = 1 };
+
+// One workgroup of the FP64 solve: 32 columns of one item over block rows [blk_begin, blk_end).
+struct TrsmTile {
+  int32_t item;
+  int32_t c0;
+  int32_t blk_begin;
+  int32_t blk_end;
+  int64_t w_off;  // offset (doubles) of this tile's rows in item.scratch; row r at (r - blk_begin*TB)*BC
+};
+
+// Mixed path, per item.
+struct MixItem {
+  // whitening operator copies (BF16 hi/lo, fragment layouts)
+  const uint16_t *wa_hi, *wa_lo;   // W, row blocks, lower part
+  const uint16_t *wb_hi, *wb_lo;   // W^T, column blocks
+  const int64_t *wa_off, *wb_off;  // [nblk] element offsets
+  const int32_t *blk_first;        // [nblk]
+  const int32_t *blk_last;         // [nblk] last block row of the segment (inclusive)
+  const int32_t *idx;              // [n_pad]
+  // operands / results
+  const double *H;
+  int64_t ldh;
+  const double *const *Hrows;      // optional per-template row pointers
+  uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][n_pad/16][64][8]
+  uint16_t *w0_hi, *w0_lo;         // split W h, same layout as hs
+  float *y0;                       // [Bp][n_pad]
+  double *out;
+  int32_t B, Bp;                   // templates, padded to a multiple of MT
+  int32_t nblk;
+  int32_t n_pad;
+};
+
+// Refinement (FP64 FFT Toeplitz quadratic form), per item.
+struct SegDev {
+  int64_t offset, length;  // sample range of the segment
+  int64_t row0;            // first padded row
+  int64_t m;               // circulant length (power of two >= 2 length)
+  int32_t log2m;
+  int32_t pad0;
+  const double *lam;       // [m] circulant eigenvalues
+  const double *tw;        // [2m] cos/sin of 2 pi r / m
+};
+
+struct RefItem {
+  const SegDev *segs;
+  int32_t n_segs;
+  int32_t B;
+  const int32_t *pos2row;  // [N] padded row of each sample, -1 = excluded
+  const float *y0;         // [Bp][n_pad]
+  const double *H;
+  int64_t ldh;
+  const double *const *Hrows;
+  const double *yd_pos;    // [N] C^-1 d scattered to sample positions (0 at excluded)
+  const double *qdd;       // scalar
+  double *out;
+  double cterm;
+  int32_t n_pad;
+  int32_t pad0;
+};
+
+// Row b of the templates of an item (explicit row table, or base + b * ldh).
+template <class Item>
+__device__ __forceinline__ const double *template_row(const Item &it, int64_t b) {
+  return it.Hrows ? it.Hrows[b] : it.H + b * it.ldh;
+}
+
+// ---------------------------------------------------------------- kernel timing
+// When enabled, timed_begin/timed_end bracket a launch with events on its stream.
+struct TimedScope {
+  const char *name;
+  hipStream_t stream;
+  int slot;
+  TimedScope(const char *n, hipStream_t s);
+  ~TimedScope();
+};
+
+// ---------------------------------------------------------------- launchers (kernels_*.hip)
+
+hipError_t launch_assemble(const double *acf, const int32_t *idx, int64_t n_keep, int64_t n_pad,
+                           double *A, hipStream_t s);
+hipError_t launch_cholesky(double *A, int64_t n, double *dinv, double *logdiag, int32_t *fail,
+                           hipStream_t s);
+hipError_t launch_diag_inverse(const double *A, int64_t n, const double *dinv128, double *dinv256,
+                               hipStream_t s);
+hipError_t launch_pack_panels(const double *A, int64_t n, int64_t row0, const double *dinv256,
+                              double *panels, const int64_t *panel_off_host, int32_t blk0,
+                              int32_t nblk_seg, hipStream_t s);
+hipError_t launch_sum_logdet(const double *logdiag, int64_t count, double *logdet, hipStream_t s);
+hipError_t launch_trsm_f64(const TrsmItem *items, const TrsmTile *tiles, int64_t n_tiles,
+                           hipStream_t s);
+hipError_t launch_trsm_f64_single(const TrsmItem &it, int32_t nblk, int64_t n_tiles,
+                                  hipStream_t s);
+hipError_t launch_combine(const double *parts, const int64_t *part_off, const int32_t *group_of,
+                          int64_t n_items, double *const *outs, const int64_t *Bs,
+                          int64_t n_groups, int64_t max_B, hipStream_t s);
+void register_kernel_attributes();
+hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hipStream_t s);
+
+// mixed
+hipError_t launch_split_w(const double *w64, const int64_t *w64_off, const int32_t *w64_rb,
+                          const int32_t *blk_first, const int32_t *blk_last, int32_t nblk,
+                          uint16_t *wa_hi, uint16_t *wa_lo, const int64_t *wa_off,
+                          uint16_t *wb_hi, uint16_t *wb_lo, const int64_t *wb_off,
+                          int64_t max_k, int64_t unused, hipStream_t s);
+hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const int32_t *w64_rb,
+                              const int32_t *blk_first, const int32_t *blk_last, const int32_t *idx,
+                              int32_t n_pad, int64_t N, const double *d, double *dbar, double *yd,
+                              double *yd_pos, double *qdd, hipStream_t s);
+hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
+                         hipStream_t s);
+hipError_t launch_split_h(const MixItem *items, int32_t item_id, int64_t Bp, int64_t n_pad,
+                          hipStream_t s);
+hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s);
+hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s);
+hipError_t launch_refine(const RefItem *items, const int2 *work, int64_t n_work, double *scratch,
+                         int64_t scratch_per_wg, int32_t n_wg, hipStream_t s);
+
+// ---------------------------------------------------------------- internal entry points (tda_api.hip)
+struct MultiCtx;
+MultiCtx *multi_ctx_create();
+void multi_ctx_destroy(MultiCtx *mc);
+// Batched evaluation with a private workspace; hrows (optional) gives per-item device
+// arrays of template row pointers.  Caller serialises use of one MultiCtx.
+tda_status multi_eval(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
+                      int64_t n_items, int32_t precision, hipStream_t s);
+int handle_device(tda_handle h);
+int64_t handle_n(tda_handle h);
+size_t handle_bytes(tda_handle h);
+bool handle_ready(tda_handle h, int32_t precision);
+tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s);
+tda_status set_error(tda_status st, const char *msg);
+
+}  // namespace tda

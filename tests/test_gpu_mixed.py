@@ -1,0 +1,126 @@
+"""Mixed-precision HIP path (BF16x3 whitening products + FP64 FFT refinement) and the
+multi-item batched path, against the FP64 oracle through the C ABI.
+
+Mixed tolerance: |logL_mixed - logL_oracle| <= 1e-3 (the accuracy target of the
+mixed path).  The refined quadratic form never exceeds the exact one, so
+logL_mixed >= logL_oracle - 1e-6 (variational bound; 1e-6 covers FP64 rounding).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL_MIXED = 1e-3
+TOL_F64 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def tda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_06010_amd as tda
+    tda.load_library()
+    return tda
+
+
+def _check_mixed(got, want):
+    err = got - want
+    assert np.max(np.abs(err)) <= TOL_MIXED, np.max(np.abs(err))
+    assert np.min(err) >= -TOL_F64, np.min(err)
+
+
+@pytest.mark.parametrize("N,n_gaps,B,segments,eps", [
+    (1024, 0, 32, None, 1e-6),
+    (3000, 2, 200, None, 1e-6),
+    (2600, 1, 130, [(0, 1000), (1200, 1300), (2550, 50)], 1e-6),
+    (4096, 0, 64, None, 1e-6),
+    (2048, 0, 16, None, 1e-4),
+])
+def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
+    from gpu_util import to_dev
+    import torch
+    print(f"case N={N} gaps={n_gaps} B={B} segments={segments}", flush=True)
+    inst = synth.random_rhs_case(200 + N + B, N, 1, n_gaps, B, eps=eps, segments=segments)
+    h = tda.Handle(inst.acf, N, inst.masks[0], segments, precision="mixed").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    got = h.loglik(d, H).cpu().numpy()
+    f64 = h.loglik(d, H, precision="fp64").cpu().numpy()
+    f = oracle.factor(inst.acf, N, inst.masks[0], segments)
+    want = oracle.loglik(f, inst.d[0], inst.H)
+    assert np.max(np.abs(f64 - want)) <= TOL_F64
+    _check_mixed(got, want)
+    # data cache: new data pointer is picked up, same pointer reuses the cache
+    d2 = to_dev(inst.d[0][::-1].copy())
+    got2 = h.loglik(d2, H).cpu().numpy()
+    want2 = oracle.loglik(f, inst.d[0][::-1].copy(), inst.H)
+    _check_mixed(got2, want2)
+    torch.cuda.synchronize()
+    h.close()
+
+
+def test_mixed_invariants(tda):
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(31, 2000, 1, 2, 150)
+    h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision="mixed").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    base = h.loglik(d, H).cpu().numpy()
+    m = torch.from_numpy(inst.masks[0].astype(bool)).cuda()
+    d2, H2 = d.clone(), H.clone()
+    d2[m] = float("nan"); H2[:, m] = float("nan")
+    np.testing.assert_array_equal(h.loglik(d2, H2).cpu().numpy(), base)
+    # batch composition does not change a template's result (fixed tile shapes)
+    sub = h.loglik(d, H[:7].contiguous()).cpu().numpy()
+    np.testing.assert_array_equal(sub, base[:7])
+    H3 = H.clone(); H3[4, 100] = float("nan")
+    r3 = h.loglik(d, H3).cpu().numpy()
+    assert np.isnan(r3[4]) and np.all(np.isfinite(np.delete(r3, 4)))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_multi_ragged_instances(tda, precision):
+    """Ragged batch: instances of different N, gaps and detector counts in one call."""
+    from gpu_util import to_dev
+    import torch
+    rng = np.random.default_rng(41)
+    specs = [(1500, 2, 1, 40), (3000, 1, 0, 70), (800, 1, 2, 130), (2300, 2, 1, 33)]
+    items, wants, outs, keep = [], [], [], []
+    for k, (N, n_det, n_gaps, B) in enumerate(specs):
+        inst = synth.random_rhs_case(500 + k, N, n_det, n_gaps, B)
+        out = torch.empty(B, dtype=torch.float64, device="cuda")
+        Hd = to_dev(inst.H)
+        fs = []
+        for det in range(n_det):
+            h = tda.Handle(inst.acf, N, inst.masks[det], precision=precision).factor()
+            dd = to_dev(inst.d[det])
+            items.append((h, dd, Hd, out))
+            keep.append((h, dd))
+            fs.append(oracle.factor(inst.acf, N, inst.masks[det]))
+        wants.append(oracle.loglik_network(fs, inst.d, inst.H))
+        outs.append(out)
+        keep.append(Hd)
+    tda.loglik_multi(items, precision=precision)
+    torch.cuda.synchronize()
+    for out, want in zip(outs, wants):
+        got = out.cpu().numpy()
+        if precision == "fp64":
+            assert np.max(np.abs(got - want)) <= TOL_F64
+        else:
+            _check_mixed(got, want)
+
+
+def test_multi_matches_single(tda):
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(77, 2048, 2, 1, 96)
+    hs = [tda.Handle(inst.acf, inst.N, m, precision="mixed").factor() for m in inst.masks]
+    ds = [to_dev(x) for x in inst.d]
+    H = to_dev(inst.H)
+    out = torch.empty(96, dtype=torch.float64, device="cuda")
+    for prec in ("fp64", "mixed"):
+        tda.loglik_multi([(hs[0], ds[0], H, out), (hs[1], ds[1], H, out)], precision=prec)
+        single = hs[0].loglik(ds[0], H, precision=prec) + hs[1].loglik(ds[1], H, precision=prec)
+        np.testing.assert_allclose(out.cpu().numpy(), single.cpu().numpy(), rtol=0, atol=1e-9)
