@@ -81,6 +81,15 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+                    help="c2 (default): two detectors x N=16384, 4096 templates per launch; "
+                         "c4: 64 ragged instances in one batched evaluation; "
+                         "c5: request server over 32 resident datasets")
+    ap.add_argument("--duration", type=float, default=4.0, help="c5: seconds of request trace")
+    ap.add_argument("--rate", type=float, default=20000.0, help="c5: mean requests per second")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this many MiB (reference "
+                         "kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; run with --gpus 1 "
@@ -98,6 +107,10 @@ def main():
     tda.load_library()
     dev = torch.device("cuda", 0)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.workload == "c4":
+        return bench_c4(args, tda, torch, synth, dev, log)
+    if args.workload == "c5":
+        return bench_c5(args, tda, torch, synth, dev, log)
 
     t0 = time.perf_counter()
     w = synth.c2_workload(B=args.templates, n=args.n)
@@ -206,6 +219,14 @@ def main():
         "kernels_ms": {k: v[1] / v[0] for k, v in kt_m.items()},
         "setup_s": setup,
     }
+    if args.calib_copy_mib:
+        nel = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = 2 * nel * 8
+        del src, dst
     if not args.no_cpu_baseline:
         fs = []
         ref, cb = cpu_baseline(inst, args.cpu_sample, fs)
@@ -216,6 +237,142 @@ def main():
     print(json.dumps(line), flush=True)
     for h in hs:
         h.close()
+
+
+def _base_line(args, value, unit, wall, steps, config, dtype):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": wall / max(steps, 1) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def bench_c4(args, tda, torch, synth, dev, log):
+    """64 ragged instances (N ~ U{2048..32768}, 0-2 gaps per detector, 1-2 detectors,
+    256 templates each) evaluated in one batched launch sequence per step."""
+    t0 = time.perf_counter()
+    w = synth.c4_workload()
+    log(f"c4 inputs in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    items = {"mixed": [], "fp64": []}
+    outs = {p: [] for p in items}
+    keep = []
+    n_eval = 0
+    for inst in w.instances:
+        H = torch.from_numpy(inst.H).to(dev)
+        o = {p: torch.empty(inst.B, dtype=torch.float64, device=dev) for p in items}
+        for k in range(inst.n_det):
+            h = tda.Handle(inst.acf, inst.N, inst.masks[k], precision="mixed").factor()
+            dk = torch.from_numpy(inst.d[k]).to(dev)
+            for p in items:
+                items[p].append((h, dk, H, o[p]))
+            keep.append((h, dk))
+        for p in items:
+            outs[p].append(o[p])
+        keep.append(H)
+        n_eval += inst.B
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log(f"c4 setup {setup:.1f} s, {len(items['mixed'])} detector items, {n_eval} evals per step")
+    res = {}
+    for p in ("mixed", "fp64"):
+        for _ in range(args.warmup):
+            tda.loglik_multi(items[p], precision=p)
+        torch.cuda.synchronize()
+        tda.timing_read(reset=True)
+        tda.timing_enable(True)
+        t = time.perf_counter()
+        steps = args.steps if p == "mixed" else max(2, args.steps // 4)
+        for _ in range(steps):
+            tda.loglik_multi(items[p], precision=p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tda.timing_enable(False)
+        res[p] = (wall, steps, tda.timing_read(reset=True),
+                  np.concatenate([o.cpu().numpy() for o in outs[p]]))
+    wall, steps, kt, rm = res["mixed"]
+    line = _base_line(args, n_eval * steps / wall, "evals/s", wall, steps,
+                      {"workload": "64 ragged instances, N~U{2048..32768}, 0-2 gaps, 1-2 detectors, "
+                                   "256 templates each, one batched evaluation per step",
+                       "instances": len(w.instances), "detector_items": len(items["mixed"])},
+                      "bf16x3+f64")
+    fw, fs, fkt, rf = res["fp64"]
+    line["fp64"] = {"value": n_eval * fs / fw, "unit": "evals/s", "ms_per_step": fw / fs * 1e3}
+    line["speedup_mixed_vs_fp64"] = line["value"] / line["fp64"]["value"]
+    line["accuracy"] = {"max_abs_dlogL_mixed_vs_fp64_gpu": float(np.abs(rm - rf).max())}
+    line["kernels_ms"] = {k: v[1] / v[0] for k, v in kt.items()}
+    line["setup_s"] = setup
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, tda, torch, synth, dev, log):
+    """Request server: 32 resident single-detector datasets (N in 4096..65536), Poisson
+    arrivals of 1-64-template requests from 512 simulated walkers."""
+    t0 = time.perf_counter()
+    w = synth.c5_workload(duration_s=args.duration, rate_hz=args.rate)
+    log(f"c5 inputs in {time.perf_counter() - t0:.1f} s")
+    res = {}
+    for prec in ("mixed", "fp64"):
+        # the FP64 pass replays every 20th request (its capacity is far below the offered load)
+        stride = 1 if prec == "mixed" else 20
+        t0 = time.perf_counter()
+        srv = tda.Server(precision=prec, n_slots=3, max_batch=2048, staging_bytes=256 << 20)
+        keep, Hs = [], []
+        for inst in w.instances:
+            h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision=prec,
+                           compact=(prec == "mixed")).factor()
+            dk = torch.from_numpy(inst.d[0]).to(dev)
+            H = torch.from_numpy(inst.H).to(dev)
+            srv.add_dataset(h, dk)
+            keep.append((h, dk))
+            Hs.append(H)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        log(f"c5 {prec}: setup {setup:.1f} s")
+        req = {k: v[::stride] for k, v in w.requests.items()}
+        n = len(req["t"])
+        counts = req["count"]
+        out = torch.empty(int(counts.sum()), dtype=torch.float64, device=dev)
+        offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
+        bank = Hs[0].shape[0]
+        tickets = []
+        srv.stats(reset=True)
+        t_start = time.perf_counter()
+        for k in range(n):
+            delay = req["t"][k] - (time.perf_counter() - t_start)
+            if delay > 0:
+                time.sleep(delay)
+            ds = int(req["dataset"][k])
+            c = int(counts[k])
+            r0 = min(int(req["start"][k]), bank - c)
+            tk = None
+            while tk is None:
+                tk = srv.submit(ds, Hs[ds][r0:r0 + c], out[offs[k]:offs[k] + c])
+            tickets.append(tk)
+        for tk in tickets:
+            srv.wait(tk, 600.0)
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        res[prec] = (wall, st, setup, n, int(counts.sum()))
+        del keep, Hs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"c5 {prec}: {st}")
+    wall, st, setup, n, tmpl = res["mixed"]
+    line = _base_line(args, tmpl / wall, "evals/s", wall, 1,
+                      {"workload": f"request server: 32 resident datasets N in 4096..65536, Poisson "
+                                   f"{args.rate:g} req/s x {args.duration:g} s, 1-64 templates per "
+                                   f"request, 512 walkers", "requests": n, "templates": tmpl},
+                      "bf16x3+f64")
+    line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"],
+                          "unit": "submit to results written"}
+    line["offered_evals_per_s"] = tmpl / args.duration
+    line["server"] = st
+    line["setup_s"] = setup
+    fw, fst, fsetup, fn, ftmpl = res["fp64"]
+    line["fp64"] = {"value": ftmpl / fw, "unit": "evals/s", "offered_fraction": 1 / 20,
+                    "latency_ms": {"p50": fst["p50_ms"], "p99": fst["p99_ms"]}, "setup_s": fsetup}
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

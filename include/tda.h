@@ -70,6 +70,13 @@ typedef enum {
 
 typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1 } tda_precision;
 
+/* TDA_FLAG_COMPACT (mixed handles): once tda_set_data has cached the whitened
+ * data, release the FP64 solve panels and the FP64 whitening operator, keeping
+ * only the BF16 hi/lo operator copies (2 N_eff^2 bytes each for W and W^T) and
+ * the cached data.  Afterwards FP64 evaluation and tda_set_data with other data
+ * return TDA_ESTATE.  For large resident datasets (serving). */
+enum { TDA_FLAG_COMPACT = 1 };
+
 /* Half-open sample range [offset, offset + length) of the N-sample series. */
 typedef struct {
   int64_t offset;
@@ -80,7 +87,7 @@ typedef struct {
   uint32_t struct_size;   /* sizeof(tda_options) */
   int32_t precision;      /* tda_precision */
   int32_t device;         /* HIP device ordinal; -1 = current device */
-  int32_t reserved;       /* must be 0 */
+  int32_t flags;          /* TDA_FLAG_* bits; 0 = default */
   size_t hbm_budget_bytes;/* cap on this handle's device memory; 0 = none */
 } tda_options;
 

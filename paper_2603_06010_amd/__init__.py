@@ -44,7 +44,7 @@ class _Segment(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_size_t)]
 
 
@@ -139,7 +139,8 @@ class Handle:
     """
 
     def __init__(self, acf, N: int, gap_mask=None, segments: Optional[Sequence] = None,
-                 precision="fp64", device: int = -1, hbm_budget: int = 0):
+                 precision="fp64", device: int = -1, hbm_budget: int = 0,
+                 compact: bool = False):
         L = load_library()
         acf = np.ascontiguousarray(acf, dtype=np.float64)
         self._acf = acf
@@ -154,8 +155,8 @@ class Handle:
         if segments is not None:
             nseg = len(segments)
             seg_arr = (_Segment * max(nseg, 1))(*[_Segment(int(o), int(l)) for o, l in segments])
-        opt = _Options(ctypes.sizeof(_Options), _precision(precision), int(device), 0,
-                       int(hbm_budget))
+        opt = _Options(ctypes.sizeof(_Options), _precision(precision), int(device),
+                       1 if compact else 0, int(hbm_budget))
         h = ctypes.c_void_p()
         _check(L.tda_cov_build(acf.ctypes.data, len(acf), int(N), mask_ptr,
                                ctypes.cast(seg_arr, ctypes.c_void_p) if seg_arr is not None else None,

@@ -342,21 +342,40 @@ __device__ __forceinline__ void trsm_tile(const TrsmItem &it, const TrsmTile &tl
     const int s_begin = (f - bf) * (TB / 4);
     const int s_end = (i - bf) * (TB / 4);
     const double *Wk = W + ((int64_t)f * TB - rbase) * BC;
-#pragma unroll 4
-    for (int s = s_begin; s < s_end; ++s) {
-      const double *Ps = P + (int64_t)s * 16 * 64 + lane;
-      double a0 = Ps[(w + 0) * 64], a1 = Ps[(w + 4) * 64], a2 = Ps[(w + 8) * 64],
-             a3 = Ps[(w + 12) * 64];
-      const double *Wr = Wk + ((int64_t)(s - s_begin) * 4 + lr) * BC + lc;
-      const double b0 = Wr[0], b1 = Wr[16];
-      acc[0][0] = mfma64(a0, b0, acc[0][0]);
-      acc[0][1] = mfma64(a0, b1, acc[0][1]);
-      acc[1][0] = mfma64(a1, b0, acc[1][0]);
-      acc[1][1] = mfma64(a1, b1, acc[1][1]);
-      acc[2][0] = mfma64(a2, b0, acc[2][0]);
-      acc[2][1] = mfma64(a2, b1, acc[2][1]);
-      acc[3][0] = mfma64(a3, b0, acc[3][0]);
-      acc[3][1] = mfma64(a3, b1, acc[3][1]);
+    // Operands of GK k-steps are fetched one group ahead of the matrix cores (two register
+    // buffers).  The k-range of a block row is a multiple of 64 k-steps, so groups tile it
+    // exactly; the one group fetched past the end stays inside this block row's panel and
+    // inside the tile's scratch rows, and is never used.
+    constexpr int GK = 8;
+    double pa[2][GK][4], pb[2][GK][2];
+    auto fetch = [&](int bsel, int s0) {
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk) {
+        const double *Ps = P + (int64_t)(s0 + kk) * 16 * 64 + lane;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pa[bsel][kk][j] = Ps[(w + 4 * j) * 64];
+        const double *Wr = Wk + ((int64_t)(s0 + kk - s_begin) * 4 + lr) * BC + lc;
+        pb[bsel][kk][0] = Wr[0];
+        pb[bsel][kk][1] = Wr[16];
+      }
+    };
+    auto consume = [&](int bsel) {
+#pragma unroll
+      for (int kk = 0; kk < GK; ++kk)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[j][0] = mfma64(pa[bsel][kk][j], pb[bsel][kk][0], acc[j][0]);
+          acc[j][1] = mfma64(pa[bsel][kk][j], pb[bsel][kk][1], acc[j][1]);
+        }
+    };
+    if (s_begin < s_end) {
+      fetch(0, s_begin);
+      for (int s = s_begin; s < s_end; s += 2 * GK) {
+        fetch(1, s + GK);
+        consume(0);
+        if (s + 2 * GK < s_end) fetch(0, s + 2 * GK);
+        consume(1);
+      }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -372,6 +391,7 @@ __device__ __forceinline__ void trsm_tile(const TrsmItem &it, const TrsmTile &tl
       const int t = w + 4 * j;
       d4 x0 = {0, 0, 0, 0}, x1 = {0, 0, 0, 0};
       const double *Pd = P + (int64_t)s_end * 16 * 64 + t * 64 + lane;
+#pragma unroll 8
       for (int s2 = 0; s2 < 4 * (t + 1); ++s2) {
         const double a = Pd[(int64_t)s2 * 16 * 64];
         const double *Sr = S + (4 * s2 + lr) * BC + lc;
@@ -434,6 +454,7 @@ hipError_t launch_trsm_f64_single(const TrsmItem &it, int32_t nblk, int64_t n_ti
 }
 
 void register_kernel_attributes() {
+  register_mixed_attributes();
   hipFuncSetAttribute((const void *)k_potf2, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)(sizeof(double) * CP * TS));
   hipFuncSetAttribute((const void *)k_diag_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -218,11 +218,13 @@ hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *t
 
 // ---------------------------------------------------------------- template split
 // F(Hs): rows = templates (padded to Bp), K = padded sample rows; Hs[b][p] = h_b[idx[p]].
-__global__ void k_split_h(const MixItem *__restrict__ items, int32_t item_id, int64_t chunks) {
-  const int64_t chunk = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (chunk >= chunks) return;
-  const MixItem &it = items[item_id];
+// grid (chunks of the largest item, items); each item has (Bp/32) (n_pad/16) 64 chunks
+__global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
+  const MixItem &it = items[blockIdx.y];
   const int64_t nks = it.n_pad / 16;
+  const int64_t chunks = (int64_t)(it.Bp / 32) * nks * 64;
+  const int64_t chunk = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (chunk >= chunks || it.B == 0) return;
   const int lane = (int)(chunk & 63);
   const int64_t ks = (chunk >> 6) % nks;
   const int64_t tt = (chunk >> 6) / nks;
@@ -232,8 +234,12 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int32_t item_id, in
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     double v = 0.0;
-    const int32_t p = it.idx[p0 + e];
-    if (b < it.B && p >= 0) v = template_row(it, b)[p];
+    if (from_e) {
+      if (b < it.B) v = it.e64[b * it.n_pad + p0 + e];
+    } else {
+      const int32_t p = it.idx[p0 + e];
+      if (b < it.B && p >= 0) v = template_row(it, b)[p];
+    }
     split2(v, hi[e], lo[e]);
   }
   uint4 vh, vl;
@@ -245,20 +251,92 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int32_t item_id, in
   *reinterpret_cast<uint4 *>(it.hs_lo + chunk * 8) = vl;
 }
 
-hipError_t launch_split_h(const MixItem *items, int32_t item_id, int64_t Bp, int64_t n_pad,
+hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
                           hipStream_t s) {
-  const int64_t chunks = (Bp / 32) * (n_pad / 16) * 64;
-  hipLaunchKernelGGL(k_split_h, dim3((unsigned)((chunks + 255) / 256)), dim3(256), 0, s, items,
-                     item_id, chunks);
+  if (n_items <= 0 || max_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_split_h, dim3((unsigned)((max_chunks + 255) / 256), (unsigned)n_items),
+                     dim3(256), 0, s, items, from_e);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- BF16x3 products
-// Work entry: (item, block, template group of MT = 128, unused); block < 0 = idle.
-// Workgroup tile 256 rows x 128 templates; wave w: rows 128 (w/2) .. +128 (4 tiles),
-// templates 64 (w%2) .. +64 (2 tiles).  Each product accumulates hi*hi + hi*lo + lo*hi.
+// A workgroup (4 waves) computes a 256 x 128 tile of D = A B over K = 16 nks; A and B are
+// given as fragment arrays: A tile t (32 rows) at k-step ks is at A + t s_tile + ks s_ks.
+// Wave w owns A tiles 4 (w/2) .. +4 and B tiles 2 (w%2) .. +2 (a 128 x 64 sub-tile).
+// Fragments go straight from HBM/L2 into registers, one k-step ahead of the matrix
+// cores.  Every product is hi*hi + hi*lo + lo*hi with FP32 accumulation.
+struct FragSrc {
+  const uint16_t *hi, *lo;
+  int64_t s_tile, s_ks;  // element strides between tiles and between k-steps
+};
 
-__global__ __launch_bounds__(256, 2) void k_trmm_fwd(const MixItem *__restrict__ items,
+constexpr int FRAG = 512;  // bf16 elements per fragment (64 lanes x 8)
+
+struct Step {
+  bf8 ah[4], al[4], bh[2], bl[2];
+};
+
+// NPROD = 3: hi*hi + hi*lo + lo*hi; NPROD = 1: hi*hi only (lo parts not loaded)
+template <int NPROD>
+__device__ __forceinline__ void load_step(const FragSrc &A, const FragSrc &B, int ta, int tb,
+                                          int64_t ks, int lane, Step &st) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t off = (int64_t)(ta + a) * A.s_tile + ks * A.s_ks + lane * 8;
+    st.ah[a] = load_frag(A.hi + off);
+    if (NPROD == 3) st.al[a] = load_frag(A.lo + off);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int64_t off = (int64_t)(tb + b) * B.s_tile + ks * B.s_ks + lane * 8;
+    st.bh[b] = load_frag(B.hi + off);
+    if (NPROD == 3) st.bl[b] = load_frag(B.lo + off);
+  }
+}
+
+template <int NPROD>
+__device__ __forceinline__ void mma_step(const Step &st, f16v (&acc)[4][2]) {
+  // separate passes so consecutive matrix-core ops use independent accumulators
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bh[b], acc[a][b]);
+  if (NPROD == 3) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bl[b], acc[a][b]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.al[a], st.bh[b], acc[a][b]);
+  }
+}
+
+template <int NPROD = 3>
+__device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int64_t nks,
+                                      f16v (&acc)[4][2]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ta = 4 * (w >> 1), tb = 2 * (w & 1);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
+  Step s0, s1;
+  if (nks > 0) load_step<NPROD>(A, B, ta, tb, 0, lane, s0);
+  int64_t ks = 0;
+  for (; ks + 1 < nks; ks += 2) {
+    load_step<NPROD>(A, B, ta, tb, ks + 1, lane, s1);
+    mma_step<NPROD>(s0, acc);
+    if (ks + 2 < nks) load_step<NPROD>(A, B, ta, tb, ks + 2, lane, s0);
+    mma_step<NPROD>(s1, acc);
+  }
+  if (ks < nks) mma_step<NPROD>(s0, acc);
+}
+
+// w0 = W h: rows of row block i, templates of group tg (128); w0 written as F(w0^T).
+template <int OCC>
+__global__ __launch_bounds__(256, OCC) void k_trmm_fwd(const MixItem *__restrict__ items,
                                                      const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
   if (wk.y < 0) return;
@@ -269,49 +347,22 @@ __global__ __launch_bounds__(256, 2) void k_trmm_fwd(const MixItem *__restrict__
   const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
   const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
-  const uint16_t *Ah = it.wa_hi + it.wa_off[i] + (int64_t)(4 * (w >> 1)) * 512 + lane * 8;
-  const uint16_t *Al = it.wa_lo + it.wa_off[i] + (int64_t)(4 * (w >> 1)) * 512 + lane * 8;
-  const int64_t T0 = (int64_t)tg * 4 + 2 * (w & 1);  // first template tile of this wave
-  const uint16_t *Bh = it.hs_hi + ((T0 * nks_all + ks0) * 64 + lane) * 8;
-  const uint16_t *Bl = it.hs_lo + ((T0 * nks_all + ks0) * 64 + lane) * 8;
-  const int64_t bstride = nks_all * 512;  // next template tile
+  const int64_t T0 = (int64_t)tg * 4;
+  const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
+  const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
+                  nks_all * FRAG, FRAG};
   f16v acc[4][2];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
-  for (int64_t ks = 0; ks < nks; ++ks) {
-    bf8 ah[4], al[4], bh[2], bl[2];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      ah[a] = load_frag(Ah + (ks * 8 + a) * 512);
-      al[a] = load_frag(Al + (ks * 8 + a) * 512);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      bh[b] = load_frag(Bh + b * bstride + ks * 512);
-      bl[b] = load_frag(Bl + b * bstride + ks * 512);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        acc[a][b] = mfma_bf16(ah[a], bh[b], acc[a][b]);
-        acc[a][b] = mfma_bf16(ah[a], bl[b], acc[a][b]);
-        acc[a][b] = mfma_bf16(al[a], bh[b], acc[a][b]);
-      }
-  }
-  // w0 in F(w0^T): element (template b, row p) -> tile b/32, kstep p/16,
-  // lane b%32 + 32 ((p%16)/8), position p%8.
+  gemm3(A, B, nks, acc);
+  // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8), pos p%8
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int64_t rt_row = (int64_t)i * TB + 128 * (w >> 1) + 32 * a;
+    const int64_t rt_row = (int64_t)i * TB + 32 * (4 * (w >> 1) + a);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int64_t T = T0 + b;
+      const int64_t T = T0 + 2 * (w & 1) + b;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        const int64_t base = rt_row + 8 * g;         // multiple of 8
+        const int64_t base = rt_row + 8 * g;
         const int64_t ks = base >> 4;
         const int lp = (lane & 31) + 32 * (g & 1);
         const int64_t dst = ((T * nks_all + ks) * 64 + lp) * 8 + 4 * (lane >> 5);
@@ -328,59 +379,33 @@ __global__ __launch_bounds__(256, 2) void k_trmm_fwd(const MixItem *__restrict__
   }
 }
 
-// y0^T = w0^T W over column block j: K = rows [j TB, (last_j + 1) TB).
-// Workgroup tile 128 templates x 256 samples; wave w: templates 64 (w/2) (2 tiles),
-// samples 128 (w%2) (4 tiles).
-__global__ __launch_bounds__(256, 2) void k_trmm_bwd(const MixItem *__restrict__ items,
+// y0^T = w0^T W over column block j (K = rows [j TB, (last_j + 1) TB)): A = F(w0^T)
+// (256 templates of group tg), B = F(W^T) restricted to half `hf` (128 samples) of block j.
+template <int OCC>
+__global__ __launch_bounds__(256, OCC) void k_trmm_bwd(const MixItem *__restrict__ items,
                                                      const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
   if (wk.y < 0) return;
   const MixItem &it = items[wk.x];
-  const int j = wk.y, tg = wk.z;
+  const int j = wk.y, tg = wk.z, hf = wk.w;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int last = it.blk_last[j];
   const int64_t nks = (int64_t)(last + 1 - j) * (TB / 16);
   const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)j * (TB / 16);
-  const int64_t T0 = (int64_t)tg * 4 + 2 * (w >> 1);
-  const uint16_t *Ah = it.w0_hi + ((T0 * nks_all + ks0) * 64 + lane) * 8;
-  const uint16_t *Al = it.w0_lo + ((T0 * nks_all + ks0) * 64 + lane) * 8;
-  const int64_t astride = nks_all * 512;
-  const int st0 = 4 * (w & 1);
-  const uint16_t *Bh = it.wb_hi + it.wb_off[j] + (int64_t)st0 * 512 + lane * 8;
-  const uint16_t *Bl = it.wb_lo + it.wb_off[j] + (int64_t)st0 * 512 + lane * 8;
-  f16v acc[2][4];
+  const int64_t T0 = (int64_t)tg * 8;
+  const FragSrc A{it.w0_hi + (T0 * nks_all + ks0) * FRAG, it.w0_lo + (T0 * nks_all + ks0) * FRAG,
+                  nks_all * FRAG, FRAG};
+  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)hf * 4 * FRAG,
+                  it.wb_lo + it.wb_off[j] + (int64_t)hf * 4 * FRAG, FRAG, 8 * FRAG};
+  f16v acc[4][2];
+  gemm3(A, B, nks, acc);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a) {
+    const int64_t trow0 = 32 * (T0 + 4 * (w >> 1) + a);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f16v{};
-  for (int64_t ks = 0; ks < nks; ++ks) {
-    bf8 ah[2], al[2], bh[4], bl[4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      ah[a] = load_frag(Ah + a * astride + ks * 512);
-      al[a] = load_frag(Al + a * astride + ks * 512);
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      bh[b] = load_frag(Bh + (ks * 8 + b) * 512);
-      bl[b] = load_frag(Bl + (ks * 8 + b) * 512);
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        acc[a][b] = mfma_bf16(ah[a], bh[b], acc[a][b]);
-        acc[a][b] = mfma_bf16(ah[a], bl[b], acc[a][b]);
-        acc[a][b] = mfma_bf16(al[a], bh[b], acc[a][b]);
-      }
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t trow0 = 32 * (T0 + a);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t col = (int64_t)j * TB + 32 * (st0 + b) + (lane & 31);
+    for (int b = 0; b < 2; ++b) {
+      const int64_t col = (int64_t)j * TB + 32 * (4 * hf + 2 * (w & 1) + b) + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t trow = trow0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -390,151 +415,355 @@ __global__ __launch_bounds__(256, 2) void k_trmm_bwd(const MixItem *__restrict__
   }
 }
 
-hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s) {
+// Correction c_b = ||W e_b||^2: same product as the forward one with the split residual
+// (in the template buffers) as B; the epilogue writes, per template, the sum of squares
+// over the 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  The
+// correction only has to be accurate relative to itself (it is already second order in
+// the product error); CORR_PROD selects 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
+constexpr int CORR_PROD = 3;
+template <int OCC>
+__global__ __launch_bounds__(256, OCC) void k_corr(const MixItem *__restrict__ items,
+                                                 const int4 *__restrict__ work) {
+  __shared__ double red[2][128];
+  const int4 wk = work[blockIdx.x];
+  if (wk.y < 0) return;
+  const MixItem &it = items[wk.x];
+  const int i = wk.y, tg = wk.z;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int bf = it.blk_first[i];
+  const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int64_t nks_all = it.n_pad / 16;
+  const int64_t ks0 = (int64_t)bf * (TB / 16);
+  const int64_t T0 = (int64_t)tg * 4;
+  const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
+  const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
+                  nks_all * FRAG, FRAG};
+  f16v acc[4][2];
+  gemm3<CORR_PROD>(A, B, nks, acc);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    double ss = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ss += (double)acc[a][b][r] * (double)acc[a][b][r];
+    ss += __shfl_xor(ss, 32);  // lanes l and l+32 hold other rows of the same column
+    const int col = 32 * (2 * (w & 1) + b) + (lane & 31);
+    if (lane < 32) red[w >> 1][col] = ss;
+  }
+  __syncthreads();
+  if (threadIdx.x < 128) {
+    const int col = threadIdx.x;
+    it.corr_part[(int64_t)i * it.Bp + T0 * 32 + col] = red[0][col] + red[1][col];
+  }
+}
+
+// out[b] = -1/2 (qpart[b] + sum_i corr_part[i][b]) + cterm; entries (item, b)
+__global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restrict__ work,
+                         int64_t n_work) {
+  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (wi >= n_work) return;
+  const int2 wk = work[wi];
+  const MixItem &it = items[wk.x];
+  const int64_t b = wk.y;
+  double c = 0.0;
+  for (int i = 0; i < it.nblk; ++i) c += it.corr_part[(int64_t)i * it.Bp + b];
+  it.out[b] = -0.5 * (it.qpart[b] + c) + it.cterm;
+}
+
+// variant: waves per SIMD the kernel is compiled for (1: no register spills, operands
+// and accumulators fully resident; 2: two workgroups per CU for more latency hiding)
+#define TDA_LAUNCH_VARIANT(K)                                                                 \
+  if (n_work <= 0) return hipSuccess;                                                        \
+  if (variant == 2)                                                                          \
+    hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
+  else                                                                                       \
+    hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
+  return hipGetLastError();
+
+hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                           hipStream_t s) {
+  TDA_LAUNCH_VARIANT(k_trmm_fwd)
+}
+
+hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                           hipStream_t s) {
+  TDA_LAUNCH_VARIANT(k_trmm_bwd)
+}
+
+hipError_t launch_corr(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                       hipStream_t s) {
+  TDA_LAUNCH_VARIANT(k_corr)
+}
+
+hipError_t launch_finish(const MixItem *items, const int2 *work, int64_t n_work, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmm_fwd, dim3((unsigned)n_work), dim3(256), 0, s, items, work);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)((n_work + 255) / 256)), dim3(256), 0, s, items,
+                     work, n_work);
   return hipGetLastError();
 }
 
-hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s) {
-  if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trmm_bwd, dim3((unsigned)n_work), dim3(256), 0, s, items, work);
-  return hipGetLastError();
-}
+void register_mixed_attributes() {}
 
 // ---------------------------------------------------------------- FP64 refinement
-// Per template and segment: x = y0 scattered to the segment's sample positions (0 at
-// excluded samples and beyond the segment), X = DFT_m(x), and
-//   y0^T C y0 = (1/m) sum_k lambda_k |X_k|^2     (circulant embedding, eq:toeplitz_fft)
-// The refined quadratic form s_hat = 2 h^T y0 - y0^T C y0 <= h^T C^-1 h with error
-// (y* - y0)^T C (y* - y0), and q = q_dd - 2 y_d^T h + s_hat (all FP64).
-// The length-m DFT is two passes of radix-2 FFTs of lengths n1, n2 (m = n1 n2) in LDS
-// with the intermediate in the workgroup's global scratch.
+// Per template pair (a, b) and segment: x = y0 scattered to the segment's sample
+// positions (0 at excluded samples and beyond the segment), z = x_a + i x_b, and
+//   C x = first `length` entries of IDFT_m(lambda . DFT_m(z))   (real part: a, imag: b)
+// because C is the leading block of the circulant of length m >= 2 length whose first
+// column embeds the ACF (eq:toeplitz_fft; lambda real and even, so the two real
+// sequences separate in the real and imaginary parts).  With e = h - C y0 (FP64):
+//   s_hat = 2 h^T y0 - y0^T C y0 <= h^T C^-1 h, error (y* - y0)^T C (y* - y0) = e^T C^-1 e,
+// and the correction kernel adds ||W e||^2, leaving an error of third order.
+//   qpart = q_dd - 2 y_d^T h + s_hat        (FP64), e written for the correction.
+// The length-m DFTs are four-step (m = n1 n2): n1-point DFTs down the columns of x seen
+// as n1 x n2 row-major, twiddle, n2-point DFTs along rows; the inverse runs the same
+// steps backwards.  Small DFTs are radix-4/2 Stockham sequences in LDS; the intermediate
+// lives in the workgroup's global scratch.
 
-constexpr int FFT_LDS = 4096;  // complex doubles staged in LDS (64 KiB)
+constexpr int FFT_BUF = 2048;  // complex doubles per LDS buffer (two buffers, ping-pong)
+constexpr int FFT_THREADS = 256;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
-// forward radix-2 DIT on `cols` columns of length P stored bit-reversed in X[c*P + .]
-__device__ void fft_cols(double2 *X, int cols, int P, int logP, int64_t m, const double *tw) {
-  const int64_t tstep = m / P;
-  for (int s = 1; s <= logP; ++s) {
-    const int half = 1 << (s - 1);
-    const int total = cols * (P >> 1);
-    for (int u = threadIdx.x; u < total; u += blockDim.x) {
-      const int c = u / (P >> 1), v = u % (P >> 1);
-      const int grp = v >> (s - 1), o = v & (half - 1);
-      const int i0 = c * P + (grp << s) + o, i1 = i0 + half;
-      const int64_t r = (int64_t)o * (P >> s) * tstep;  // twiddle exponent in units of 1/m
-      const double2 wv = make_double2(tw[2 * r], -tw[2 * r + 1]);
-      const double2 a = X[i0], b = cmul(X[i1], wv);
-      X[i0] = make_double2(a.x + b.x, a.y + b.y);
-      X[i1] = make_double2(a.x - b.x, a.y - b.y);
+// Forward DFT of `cols` sequences of length P = 2^logP at X[c*P + j] (natural order in and
+// out); returns the buffer (X or Y) holding the result.  twP[k] = exp(-2 pi i k / P).
+__device__ double2 *dft_lds(double2 *X, double2 *Y, int cols, int logP, const double2 *twP) {
+  const int P = 1 << logP;
+  int Ns = 1;
+  double2 *src = X, *dst = Y;
+  int left = logP;
+  while (left > 0) {
+    if (left >= 2) {  // radix-4 stage
+      const int quarter = P >> 2;
+      const int total = cols * quarter;
+      for (int u = threadIdx.x; u < total; u += blockDim.x) {
+        const int c = u >> (logP - 2), j = u & (quarter - 1);
+        const double2 *in = src + c * P;
+        double2 *out = dst + c * P;
+        const int k = j & (Ns - 1);
+        const int tstride = P / (Ns * 4);
+        double2 v0 = in[j], v1 = in[j + quarter], v2 = in[j + 2 * quarter], v3 = in[j + 3 * quarter];
+        if (Ns > 1) {
+          v1 = cmul(v1, twP[(k * tstride) & (P - 1)]);
+          v2 = cmul(v2, twP[(2 * k * tstride) & (P - 1)]);
+          v3 = cmul(v3, twP[(3 * k * tstride) & (P - 1)]);
+        }
+        const double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
+        const double2 d = csub(v1, v3);
+        const double2 a3 = make_double2(d.y, -d.x);  // -i (v1 - v3)
+        const int base = (j / Ns) * Ns * 4 + k;
+        out[base] = cadd(a0, a2);
+        out[base + Ns] = cadd(a1, a3);
+        out[base + 2 * Ns] = csub(a0, a2);
+        out[base + 3 * Ns] = csub(a1, a3);
+      }
+      Ns *= 4;
+      left -= 2;
+    } else {  // radix-2 stage
+      const int half = P >> 1;
+      const int total = cols * half;
+      for (int u = threadIdx.x; u < total; u += blockDim.x) {
+        const int c = u >> (logP - 1), j = u & (half - 1);
+        const double2 *in = src + c * P;
+        double2 *out = dst + c * P;
+        const int k = j & (Ns - 1);
+        double2 v0 = in[j], v1 = in[j + half];
+        if (Ns > 1) v1 = cmul(v1, twP[(k * (P / (Ns * 2))) & (P - 1)]);
+        const int base = (j / Ns) * Ns * 2 + k;
+        out[base] = cadd(v0, v1);
+        out[base + Ns] = csub(v0, v1);
+      }
+      Ns *= 2;
+      left -= 1;
     }
     __syncthreads();
+    double2 *t = src;
+    src = dst;
+    dst = t;
   }
+  return src;
 }
-
-__device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
 __device__ double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
   __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int k = 0; k < (int)blockDim.x; ++k) s += red[k];
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double s = red[0];
   __syncthreads();
-  return s;  // valid on thread 0
+  return s;
 }
 
-__global__ __launch_bounds__(256) void k_refine(const RefItem *__restrict__ items,
-                                                const int2 *__restrict__ work, int64_t n_work,
-                                                double2 *__restrict__ scratch_all,
-                                                int64_t scratch_per_wg) {
-  __shared__ double2 X[FFT_LDS];
-  __shared__ double red[256];
+// Work entry: (item, template a, template b or -1, 0).
+__global__ __launch_bounds__(FFT_THREADS) void k_refine(const RefItem *__restrict__ items,
+                                                        const int4 *__restrict__ work,
+                                                        int64_t n_work,
+                                                        double2 *__restrict__ scratch_all,
+                                                        int64_t scratch_per_wg) {
+  __shared__ double2 buf[2][FFT_BUF];
+  __shared__ double2 tw1[512], tw2[512];
+  __shared__ double red[FFT_THREADS];
   double2 *S = scratch_all + (int64_t)blockIdx.x * scratch_per_wg;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
-    const int2 wk = work[wi];
+    const int4 wk = work[wi];
     const RefItem &it = items[wk.x];
-    const int64_t b = wk.y;
-    const float *y = it.y0 + b * it.n_pad;
-    const double *h = template_row(it, b);
-    double hy = 0.0, ydh = 0.0, quad_total = 0.0;
+    const int64_t ba = wk.y, bb = wk.z;
+    const bool two = bb >= 0;
+    const float *ya = it.y0 + ba * it.n_pad;
+    const float *yb = it.y0 + (two ? bb : ba) * it.n_pad;
+    const double *ha = template_row(it, ba);
+    const double *hb = template_row(it, two ? bb : ba);
+    double *ea = it.e64 + ba * it.n_pad;
+    double *eb = two ? it.e64 + bb * it.n_pad : nullptr;
+    double hy_a = 0, hy_b = 0, ydh_a = 0, ydh_b = 0, yc_a = 0, yc_b = 0;
+    // a non-finite y0 entry must not reach the partner through the shared DFT: it is
+    // replaced by 0 there and the template's result is set to NaN at the end
+    double bad_a = 0, bad_b = 0;
     for (int sg = 0; sg < it.n_segs; ++sg) {
       const SegDev sd = it.segs[sg];
       const int log2m = sd.log2m;
       const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
       const int n1 = 1 << l1, n2 = 1 << l2;
       const int64_t m = sd.m;
-      // pass 1: columns j2 (stride n2), length n1
-      const int cb1 = FFT_LDS / n1;
+      const double inv_m = 1.0 / (double)m;
+      for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+        const int64_t r = (int64_t)k * (m / n1);
+        tw1[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
+      }
+      for (int k = threadIdx.x; k < n2; k += blockDim.x) {
+        const int64_t r = (int64_t)k * (m / n2);
+        tw2[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
+      }
+      __syncthreads();
+      const int cb1 = FFT_BUF / n1 < n2 ? FFT_BUF / n1 : n2;
+      // pass 1: column DFTs (length n1) of x[n2 j1 + j2], twiddle w_m^{j2 k1}, to S[k1 n2 + j2]
       for (int j2b = 0; j2b < n2; j2b += cb1) {
-        const int cols = min(cb1, n2 - j2b);
-        for (int u = threadIdx.x; u < cols * n1; u += blockDim.x) {
-          const int c = u % cols, j1 = u / cols;
+        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+          const int c = u & (cb1 - 1), j1 = u / cb1;
           const int64_t jpos = (int64_t)n2 * j1 + j2b + c;
-          double xv = 0.0;
+          double xa = 0.0, xb = 0.0;
           if (jpos < sd.length) {
             const int32_t p = it.pos2row[sd.offset + jpos];
             if (p >= 0) {
-              xv = (double)y[p];
-              const double hv = h[sd.offset + jpos];
-              hy += hv * xv;
-              ydh += hv * it.yd_pos[sd.offset + jpos];
+              xa = (double)ya[p];
+              if (!isfinite(xa)) bad_a = 1.0, xa = 0.0;
+              if (two) {
+                xb = (double)yb[p];
+                if (!isfinite(xb)) bad_b = 1.0, xb = 0.0;
+              }
             }
           }
-          X[c * n1 + bitrev(j1, l1)] = make_double2(xv, 0.0);
+          buf[0][c * n1 + j1] = make_double2(xa, xb);
         }
         __syncthreads();
-        fft_cols(X, cols, n1, l1, m, sd.tw);
-        for (int u = threadIdx.x; u < cols * n1; u += blockDim.x) {
-          const int c = u % cols, k1 = u / cols;
+        const double2 *R = dft_lds(buf[0], buf[1], cb1, l1, tw1);
+        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+          const int c = u & (cb1 - 1), k1 = u / cb1;
           const int64_t j2 = j2b + c;
           const int64_t r = (j2 * (int64_t)k1) & (m - 1);
-          const double2 wv = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
-          S[(int64_t)k1 * n2 + j2] = cmul(X[c * n1 + k1], wv);
+          S[(int64_t)k1 * n2 + j2] = cmul(R[c * n1 + k1], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
         }
         __threadfence_block();
         __syncthreads();
       }
-      // pass 2: rows k1, length n2 over j2
-      const int cb2 = FFT_LDS / n2;
-      double quad = 0.0;
+      // pass 2: row DFTs (length n2), times lambda, inverse row DFTs, twiddle w_m^{-j2 k1}
+      const int cb2 = FFT_BUF / n2 < n1 ? FFT_BUF / n2 : n1;
       for (int k1b = 0; k1b < n1; k1b += cb2) {
-        const int rows = min(cb2, n1 - k1b);
-        for (int u = threadIdx.x; u < rows * n2; u += blockDim.x) {
-          const int c = u / n2, j2 = u % n2;
-          X[c * n2 + bitrev(j2, l2)] = S[(int64_t)(k1b + c) * n2 + j2];
+        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+          const int c = u / n2, j2 = u & (n2 - 1);
+          buf[0][c * n2 + j2] = S[(int64_t)(k1b + c) * n2 + j2];
         }
         __syncthreads();
-        fft_cols(X, rows, n2, l2, m, sd.tw);
-        for (int u = threadIdx.x; u < rows * n2; u += blockDim.x) {
-          const int c = u / n2, k2 = u % n2;
-          const double2 v = X[c * n2 + k2];
-          quad += sd.lam[(int64_t)(k1b + c) + (int64_t)n1 * k2] * (v.x * v.x + v.y * v.y);
+        double2 *R = dft_lds(buf[0], buf[1], cb2, l2, tw2);
+        double2 *O = R == buf[0] ? buf[1] : buf[0];
+        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+          const int c = u / n2, k2 = u & (n2 - 1);
+          const double lam = sd.lam[(int64_t)(k1b + c) + (int64_t)n1 * k2];
+          const double2 v = R[c * n2 + k2];
+          O[c * n2 + k2] = make_double2(lam * v.x, -lam * v.y);  // conj(lambda X) for the inverse
         }
+        __syncthreads();
+        const double2 *R2 = dft_lds(O, R, cb2, l2, tw2);
+        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+          const int c = u / n2, j2 = u & (n2 - 1);
+          const int64_t k1 = k1b + c;
+          const int64_t r = (k1 * (int64_t)j2) & (m - 1);
+          // inverse row result = conj(R2); times w_m^{-j2 k1} = conj(w_m^{j2 k1}); keep conjugated
+          // for the final inverse column DFT: conj(conj(R2) conj(w)) = R2 w
+          S[k1 * n2 + j2] = cmul(R2[c * n2 + j2], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
+        }
+        __threadfence_block();
         __syncthreads();
       }
-      quad_total += quad / (double)m;
+      // pass 3: inverse column DFTs (length n1): (C z)_{n2 j1 + j2} = conj(DFT(conj T)) / m,
+      // where S already holds conj T; results to S at the natural position n2 j1 + j2
+      for (int j2b = 0; j2b < n2; j2b += cb1) {
+        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+          const int c = u & (cb1 - 1), k1 = u / cb1;
+          buf[0][c * n1 + k1] = S[(int64_t)k1 * n2 + j2b + c];
+        }
+        __syncthreads();
+        const double2 *R = dft_lds(buf[0], buf[1], cb1, l1, tw1);
+        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+          const int c = u & (cb1 - 1), j1 = u / cb1;
+          const double2 v = R[c * n1 + j1];
+          S[(int64_t)n2 * j1 + j2b + c] = make_double2(v.x * inv_m, -v.y * inv_m);
+        }
+        __threadfence_block();
+        __syncthreads();
+      }
+      // residual e = h - C y0 on the segment's padded rows (0 on padding), and the dots
+      for (int64_t p = sd.row0 + threadIdx.x; p < sd.row0 + sd.npad; p += blockDim.x) {
+        const int32_t jg = it.idx[p];
+        double va = 0.0, vb = 0.0;
+        if (jg >= 0) {
+          const int64_t jpos = jg - sd.offset;
+          const double2 cz = S[jpos];
+          const double yd = it.yd_pos[jg];
+          const double xa = (double)ya[p];
+          const double hva = ha[jg];
+          va = hva - cz.x;
+          hy_a += hva * xa;
+          ydh_a += hva * yd;
+          yc_a += xa * cz.x;
+          if (two) {
+            const double xb = (double)yb[p];
+            const double hvb = hb[jg];
+            vb = hvb - cz.y;
+            hy_b += hvb * xb;
+            ydh_b += hvb * yd;
+            yc_b += xb * cz.y;
+          }
+        }
+        ea[p] = va;
+        if (two) eb[p] = vb;
+      }
+      __syncthreads();
     }
-    const double s_hy = block_sum(hy, red);
-    const double s_ydh = block_sum(ydh, red);
-    const double s_quad = block_sum(quad_total, red);
+    const double s_hya = block_sum(hy_a, red), s_ydha = block_sum(ydh_a, red);
+    const double s_yca = block_sum(yc_a, red);
+    const double s_hyb = block_sum(hy_b, red), s_ydhb = block_sum(ydh_b, red);
+    const double s_ycb = block_sum(yc_b, red);
+    const double s_bada = block_sum(bad_a, red), s_badb = block_sum(bad_b, red);
     if (threadIdx.x == 0) {
-      const double shat = 2.0 * s_hy - s_quad;
-      const double q = it.qdd[0] - 2.0 * s_ydh + shat;
-      it.out[b] = -0.5 * q + it.cterm;
+      const double nan = __builtin_nan("");
+      it.qpart[ba] = s_bada > 0 ? nan : it.qdd[0] - 2.0 * s_ydha + 2.0 * s_hya - s_yca;
+      if (two) it.qpart[bb] = s_badb > 0 ? nan : it.qdd[0] - 2.0 * s_ydhb + 2.0 * s_hyb - s_ycb;
     }
   }
 }
 
-hipError_t launch_refine(const RefItem *items, const int2 *work, int64_t n_work, double *scratch,
+hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)n_wg), dim3(256), 0, s, items, work, n_work,
+  hipLaunchKernelGGL(k_refine, dim3((unsigned)n_wg), dim3(FFT_THREADS), 0, s, items, work, n_work,
                      (double2 *)scratch, scratch_per_wg / 2);
   return hipGetLastError();
 }

@@ -152,6 +152,8 @@ struct DescRing {
 struct tda_ctx {
   int device = 0;
   int precision = TDA_PREC_FP64;
+  int flags = 0;
+  bool compacted = false;  // FP64 panels and operator released (TDA_FLAG_COMPACT)
   size_t budget = 0;
   size_t held = 0;
   int64_t N = 0, n_eff = 0, n_pad = 0;
@@ -286,13 +288,14 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     return fail_with(TDA_EINVAL, "acf[0] must be positive and finite");
   if (n_segments < 0 || (n_segments > 0 && !segments))
     return fail_with(TDA_EINVAL, "bad segment list");
-  tda_options o{sizeof(tda_options), TDA_PREC_FP64, -1, 0, 0};
+  tda_options o{sizeof(tda_options), TDA_PREC_FP64, -1, 0, 0};  // struct_size, precision, device, flags, budget
   if (opt) {
     if (opt->struct_size < sizeof(tda_options)) return fail_with(TDA_EINVAL, "options struct_size");
     o = *opt;
   }
   if (o.precision != TDA_PREC_FP64 && o.precision != TDA_PREC_MIXED)
     return fail_with(TDA_EINVAL, "unknown precision %d", o.precision);
+  if (o.flags & ~TDA_FLAG_COMPACT) return fail_with(TDA_EINVAL, "unknown flags");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail_with(TDA_ENODEV, "no HIP device");
@@ -325,6 +328,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   tda_ctx *h = new tda_ctx();
   h->device = dev;
   h->precision = o.precision;
+  h->flags = o.flags;
   h->budget = o.hbm_budget_bytes;
   h->N = N;
   h->acf.assign(acf, acf + longest);
@@ -511,6 +515,8 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
     return fail_with(TDA_EINVAL, "unknown precision");
   if (precision == TDA_PREC_MIXED && h->precision != TDA_PREC_MIXED)
     return fail_with(TDA_ESTATE, "mixed evaluation needs a handle built with TDA_PREC_MIXED");
+  if (h->compacted && (precision == TDA_PREC_FP64 || d != h->data_ptr))
+    return fail_with(TDA_ESTATE, "compact handle: only mixed evaluation with its cached data");
   DeviceGuard guard(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
   TDA_TRY(order_after_previous(h, s));
@@ -536,7 +542,7 @@ namespace {
 // share that block's operator panel in L2; blocks are dealt to XCDs round-robin and
 // each XCD queue runs its largest blocks first.
 struct BlockJob {
-  int32_t item, block, ntg;
+  int32_t item, block, ntg, nsub;
   int64_t k;  // work weight (K of the block)
 };
 
@@ -550,7 +556,8 @@ std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
     std::stable_sort(q[x].begin(), q[x].end(),
                      [](const BlockJob &a, const BlockJob &b) { return a.k > b.k; });
     for (const BlockJob &j : q[x])
-      for (int t = 0; t < j.ntg; ++t) lists[x].push_back(int4{j.item, j.block, t, 0});
+      for (int t = 0; t < j.ntg; ++t)
+        for (int u = 0; u < j.nsub; ++u) lists[x].push_back(int4{j.item, j.block, t, u});
     longest = std::max(longest, lists[x].size());
   }
   std::vector<int4> out(longest * NX, int4{0, -1, 0, 0});
@@ -564,6 +571,9 @@ constexpr int kRefineWG = 512;
 }  // namespace
 
 static tda_status build_mixed(tda_ctx *h) {
+  for (const Seg &g : h->segs)
+    if (g.m > ((int64_t)1 << 18))
+      return fail_with(TDA_EINVAL, "mixed precision supports segments of at most 131072 samples");
   const int64_t nct = h->n_pad / 32;
   h->w64_off_h.resize(nct);
   h->w64_rb_h.resize(nct);
@@ -633,6 +643,7 @@ static tda_status build_mixed(tda_ctx *h) {
     sd.offset = g.offset;
     sd.length = g.length;
     sd.row0 = g.row0;
+    sd.npad = g.n_pad;
     sd.m = g.m;
     sd.log2m = g.log2m;
     sd.lam = lam;
@@ -647,6 +658,8 @@ static tda_status build_mixed(tda_ctx *h) {
 }
 
 static tda_status set_data_impl(tda_ctx *h, const double *d, hipStream_t s) {
+  if (h->compacted)
+    return fail_with(TDA_ESTATE, "compact handle: the FP64 operator was released after its data");
   TDA_TRY(h->alloc(h->dbar_d, (size_t)h->n_pad * sizeof(double)));
   TDA_TRY(h->alloc(h->yd_d, (size_t)h->n_pad * sizeof(double)));
   TDA_TRY(h->alloc(h->ydpos_d, (size_t)h->N * sizeof(double)));
@@ -657,6 +670,14 @@ static tda_status set_data_impl(tda_ctx *h, const double *d, hipStream_t s) {
                              (int32_t)h->n_pad, h->N, d, (double *)h->dbar_d.p,
                              (double *)h->yd_d.p, (double *)h->ydpos_d.p, (double *)h->qdd_d.p, s));
   h->data_ptr = d;
+  if (h->flags & TDA_FLAG_COMPACT) {
+    HIP_TRY(hipStreamSynchronize(s));
+    h->release(h->w64_d);
+    h->release(h->panels_d);
+    h->release(h->dbar_d);
+    h->release(h->yd_d);
+    h->compacted = true;
+  }
   return TDA_OK;
 }
 
@@ -676,10 +697,36 @@ extern "C" tda_status tda_set_data(tda_handle h, const double *d, void *hip_stre
 struct MixWs {
   uint16_t *hs_hi, *hs_lo, *w0_hi, *w0_lo;
   float *y0;
+  double *e64, *qpart, *corr_part;
 };
 
+// Bytes of workspace one mixed item needs for Bp templates.
+static size_t mix_ws_bytes(const tda_ctx *h, int64_t Bp) {
+  const size_t el = (size_t)Bp * h->n_pad;
+  return el * (2 + 2 + 2 + 2 + 4 + 8) + (size_t)Bp * 8 + (size_t)h->nblk * Bp * 8 + 6 * 256;
+}
+
+static MixWs carve_mix_ws(const tda_ctx *h, int64_t Bp, char *base) {
+  const size_t el = (size_t)Bp * h->n_pad;
+  auto take = [&](size_t bytes) {
+    char *p = base;
+    base += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  MixWs w;
+  w.hs_hi = (uint16_t *)take(el * 2);
+  w.hs_lo = (uint16_t *)take(el * 2);
+  w.w0_hi = (uint16_t *)take(el * 2);
+  w.w0_lo = (uint16_t *)take(el * 2);
+  w.y0 = (float *)take(el * 4);
+  w.e64 = (double *)take(el * 8);
+  w.qpart = (double *)take((size_t)Bp * 8);
+  w.corr_part = (double *)take((size_t)h->nblk * Bp * 8);
+  return w;
+}
+
 static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int64_t B,
-                             int64_t Bp, const MixWs &ws) {
+                             int64_t Bp, const MixWs &ws, double *out) {
   MixItem mi{};
   mi.wa_hi = (const uint16_t *)h->wa_hi.p;
   mi.wa_lo = (const uint16_t *)h->wa_lo.p;
@@ -697,6 +744,11 @@ static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int
   mi.w0_hi = ws.w0_hi;
   mi.w0_lo = ws.w0_lo;
   mi.y0 = ws.y0;
+  mi.e64 = ws.e64;
+  mi.corr_part = ws.corr_part;
+  mi.qpart = ws.qpart;
+  mi.out = out;
+  mi.cterm = h->cterm();
   mi.B = (int32_t)B;
   mi.Bp = (int32_t)Bp;
   mi.nblk = h->nblk;
@@ -704,81 +756,151 @@ static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int
   return mi;
 }
 
-static RefItem make_ref_item(const tda_ctx *h, const double *H, int64_t ldh, int64_t B,
-                             const float *y0, double *out) {
+static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi) {
   RefItem ri{};
   ri.segs = (const SegDev *)h->segdev_d.p;
   ri.n_segs = (int32_t)h->segdev_h.size();
-  ri.B = (int32_t)B;
+  ri.B = mi.B;
   ri.pos2row = (const int32_t *)h->pos2row_d.p;
-  ri.y0 = y0;
-  ri.H = H;
-  ri.ldh = ldh;
+  ri.y0 = mi.y0;
+  ri.H = mi.H;
+  ri.ldh = mi.ldh;
+  ri.Hrows = mi.Hrows;
   ri.yd_pos = (const double *)h->ydpos_d.p;
   ri.qdd = (const double *)h->qdd_d.p;
-  ri.out = out;
-  ri.cterm = h->cterm();
-  ri.n_pad = (int32_t)h->n_pad;
+  ri.idx = (const int32_t *)h->idx_d.p;
+  ri.e64 = mi.e64;
+  ri.qpart = mi.qpart;
+  ri.out = mi.out;
+  ri.cterm = mi.cterm;
+  ri.n_pad = mi.n_pad;
   return ri;
 }
 
-static void add_block_jobs(const tda_ctx *h, int32_t item, int32_t ntg, bool transposed,
+// Refinement work: templates of one item in pairs sharing one complex DFT.
+static void add_refine_pairs(int32_t item, int64_t B, std::vector<int4> &wr) {
+  for (int64_t b = 0; b < B; b += 2)
+    wr.push_back(int4{item, (int32_t)b, b + 1 < B ? (int32_t)(b + 1) : -1, 0});
+}
+
+// fwd/corr jobs: (block i, groups of 128 templates); bwd jobs: (block j, groups of 256, 2 halves)
+static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, bool transposed,
                            std::vector<BlockJob> &jobs) {
   for (int32_t i = 0; i < h->nblk; ++i) {
     const int64_t k = transposed ? (int64_t)(h->blk_last_h[i] + 1 - i)
                                  : (int64_t)(i + 1 - h->blk_first_h[i]);
-    jobs.push_back(BlockJob{item, i, ntg, k});
+    if (transposed)
+      jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), 2, k});
+    else
+      jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 128), 1, k});
   }
+}
+
+// The mixed launch sequence over a set of items whose MixItem/RefItem descriptors are
+// already built (host side); descriptors and work lists go through `ring` on stream s.
+static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
+                                const std::vector<RefItem> &ris,
+                                const std::vector<const tda_ctx *> &hs, double *fft_scratch,
+                                int64_t max_m, hipStream_t s) {
+  const int64_t n = (int64_t)mis.size();
+  std::vector<BlockJob> jf, jb;
+  std::vector<int4> wr;
+  std::vector<int2> wfin;
+  for (int64_t k = 0; k < n; ++k) {
+    if (mis[k].B == 0) continue;
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, false, jf);
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, true, jb);
+    add_refine_pairs((int32_t)k, mis[k].B, wr);
+    for (int32_t b = 0; b < mis[k].B; ++b) wfin.push_back(int2{(int32_t)k, b});
+  }
+  const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
+  HIP_TRY(ring.reserve(8192 + n * (64 + sizeof(MixItem) + sizeof(RefItem)) +
+                       (wf.size() + wbk.size() + wr.size()) * sizeof(int4) +
+                       wfin.size() * sizeof(int2)));
+  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr, *d_fin;
+  HIP_TRY(ring.push(mis.data(), mis.size() * sizeof(MixItem), s, &d_mi));
+  HIP_TRY(ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
+  HIP_TRY(ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
+  HIP_TRY(ring.push(wbk.data(), wbk.size() * sizeof(int4), s, &d_wb));
+  HIP_TRY(ring.push(wr.data(), wr.size() * sizeof(int4), s, &d_wr));
+  HIP_TRY(ring.push(wfin.data(), wfin.size() * sizeof(int2), s, &d_fin));
+  const MixItem *dm = (const MixItem *)d_mi;
+  // autotuned variant per product kernel, keyed by the largest item's shape
+  int64_t rows = 0, tmpl = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    rows = std::max<int64_t>(rows, mis[k].n_pad);
+    tmpl += mis[k].Bp;
+  }
+  struct Ctx {
+    const MixItem *dm;
+    const int4 *w;
+    int64_t nw;
+    hipStream_t s;
+  };
+  static const int kVariants[2] = {2, 1};
+  Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
+  Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
+  int64_t max_chunks = 0;
+  for (int64_t k = 0; k < n; ++k)
+    max_chunks = std::max<int64_t>(max_chunks, (int64_t)(mis[k].Bp / 32) * (mis[k].n_pad / 16) * 64);
+  {
+    TimedScope ts("split_h", s);
+    HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
+  }
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 2, s,
+                               [](void *c, int v) {
+                                 Ctx *x = (Ctx *)c;
+                                 return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
+                               }, &cf);
+  {
+    TimedScope ts("trmm_fwd", s);
+    HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
+  }
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 2, s,
+                               [](void *c, int v) {
+                                 Ctx *x = (Ctx *)c;
+                                 return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
+                               }, &cb);
+  {
+    TimedScope ts("trmm_bwd", s);
+    HIP_TRY(launch_trmm_bwd(dm, (const int4 *)d_wb, (int64_t)wbk.size(), vb, s));
+  }
+  {
+    TimedScope ts("refine_fft", s);
+    HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
+                          fft_scratch, 2 * max_m, kRefineWG, s));
+  }
+  {
+    TimedScope ts("split_e", s);
+    HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
+  }
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 2, s,
+                               [](void *c, int v) {
+                                 Ctx *x = (Ctx *)c;
+                                 return launch_corr(x->dm, x->w, x->nw, v, x->s);
+                               }, &cf);
+  {
+    TimedScope ts("trmm_corr", s);
+    HIP_TRY(launch_corr(dm, (const int4 *)d_wf, (int64_t)wf.size(), vc, s));
+  }
+  {
+    TimedScope ts("finish", s);
+    HIP_TRY(launch_finish(dm, (const int2 *)d_fin, (int64_t)wfin.size(), s));
+  }
+  return TDA_OK;
 }
 
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
                                int64_t ldh, double *out, hipStream_t s) {
   if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
   const int64_t Bp = (B + MT - 1) / MT * MT;
-  const int32_t ntg = (int32_t)(Bp / MT);
-  const size_t el = (size_t)Bp * h->n_pad;
-  TDA_TRY(h->alloc(h->ws_hs_hi, el * 2));
-  TDA_TRY(h->alloc(h->ws_hs_lo, el * 2));
-  TDA_TRY(h->alloc(h->ws_w0_hi, el * 2));
-  TDA_TRY(h->alloc(h->ws_w0_lo, el * 2));
-  TDA_TRY(h->alloc(h->ws_y0, el * 4));
+  TDA_TRY(h->alloc(h->ws_mix, mix_ws_bytes(h, Bp)));
   TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
-  MixWs ws{(uint16_t *)h->ws_hs_hi.p, (uint16_t *)h->ws_hs_lo.p, (uint16_t *)h->ws_w0_hi.p,
-           (uint16_t *)h->ws_w0_lo.p, (float *)h->ws_y0.p};
-  const MixItem mi = make_mix_item(h, H, ldh, B, Bp, ws);
-  const RefItem ri = make_ref_item(h, H, ldh, B, ws.y0, out);
-  std::vector<BlockJob> jf, jb;
-  add_block_jobs(h, 0, ntg, false, jf);
-  add_block_jobs(h, 0, ntg, true, jb);
-  const std::vector<int4> wf = xcd_order(jf), wb = xcd_order(jb);
-  std::vector<int2> wr(B);
-  for (int64_t b = 0; b < B; ++b) wr[b] = int2{0, (int32_t)b};
-  const size_t total = 4 * 256 + sizeof mi + sizeof ri + (wf.size() + wb.size()) * sizeof(int4) +
-                       wr.size() * sizeof(int2);
-  HIP_TRY(h->ring.reserve(total));
-  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr;
-  HIP_TRY(h->ring.push(&mi, sizeof mi, s, &d_mi));
-  HIP_TRY(h->ring.push(&ri, sizeof ri, s, &d_ri));
-  HIP_TRY(h->ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
-  HIP_TRY(h->ring.push(wb.data(), wb.size() * sizeof(int4), s, &d_wb));
-  HIP_TRY(h->ring.push(wr.data(), wr.size() * sizeof(int2), s, &d_wr));
-  {
-    TimedScope ts("split_h", s);
-    HIP_TRY(launch_split_h((const MixItem *)d_mi, 0, Bp, h->n_pad, s));
-  }
-  {
-    TimedScope ts("trmm_fwd", s);
-    HIP_TRY(launch_trmm_fwd((const MixItem *)d_mi, (const int4 *)d_wf, (int64_t)wf.size(), s));
-  }
-  {
-    TimedScope ts("trmm_bwd", s);
-    HIP_TRY(launch_trmm_bwd((const MixItem *)d_mi, (const int4 *)d_wb, (int64_t)wb.size(), s));
-  }
-  {
-    TimedScope ts("refine_fft", s);
-    HIP_TRY(launch_refine((const RefItem *)d_ri, (const int2 *)d_wr, B, (double *)h->ws_fft.p,
-                          2 * h->max_m, kRefineWG, s));
-  }
+  const MixWs ws = carve_mix_ws(h, Bp, (char *)h->ws_mix.p);
+  std::vector<MixItem> mis{make_mix_item(h, H, ldh, B, Bp, ws, out)};
+  std::vector<RefItem> ris{make_ref_item(h, mis[0])};
+  std::vector<const tda_ctx *> hs{h};
+  TDA_TRY(enqueue_mixed(h->ring, mis, ris, hs, (double *)h->ws_fft.p, h->max_m, s));
   HIP_TRY(h->ring.seal(s));
   return TDA_OK;
 }
@@ -829,7 +951,9 @@ int handle_device(tda_handle h) { return h->device; }
 int64_t handle_n(tda_handle h) { return h->N; }
 size_t handle_bytes(tda_handle h) { return h->held; }
 bool handle_ready(tda_handle h, int32_t precision) {
-  return h->factored && (precision == TDA_PREC_FP64 || h->precision == TDA_PREC_MIXED);
+  if (!h->factored) return false;
+  if (precision == TDA_PREC_FP64) return !h->compacted;
+  return h->precision == TDA_PREC_MIXED;
 }
 tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s) {
   if (h->precision != TDA_PREC_MIXED || h->data_ptr == d) return TDA_OK;
@@ -872,6 +996,9 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
     if (w.ldh < w.h->N) return fail_with(TDA_EINVAL, "item %lld: ldh < N", (long long)k);
     if (precision == TDA_PREC_MIXED && w.h->precision != TDA_PREC_MIXED)
       return fail_with(TDA_ESTATE, "item %lld: handle not built for mixed precision", (long long)k);
+    if (w.h->compacted && (precision == TDA_PREC_FP64 || w.d != w.h->data_ptr))
+      return fail_with(TDA_ESTATE, "item %lld: compact handle used beyond its cached data",
+                       (long long)k);
     int32_t g = -1;
     for (size_t q = 0; q < group_out.size(); ++q)
       if (group_out[q] == w.out) g = (int32_t)q;
@@ -947,66 +1074,29 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
   } else {
     std::vector<MixItem> mis(n_items);
     std::vector<RefItem> ris(n_items);
-    std::vector<BlockJob> jf, jb;
-    std::vector<int2> wr;
-    size_t el_total = 0;
+    std::vector<const tda_ctx *> hs(n_items);
+    size_t total = 0;
     int64_t max_m = 0;
-    std::vector<size_t> el_off(n_items);
+    std::vector<size_t> ws_off(n_items);
     for (int64_t k = 0; k < n_items; ++k) {
       const int64_t Bp = (items[k].B + MT - 1) / MT * MT;
-      el_off[k] = el_total;
-      el_total += (size_t)Bp * items[k].h->n_pad;
+      ws_off[k] = total;
+      total += mix_ws_bytes(items[k].h, Bp);
       max_m = std::max(max_m, items[k].h->max_m);
     }
-    TDA_TRY(P.alloc(P.ws_hs_hi, el_total * 2));
-    TDA_TRY(P.alloc(P.ws_hs_lo, el_total * 2));
-    TDA_TRY(P.alloc(P.ws_w0_hi, el_total * 2));
-    TDA_TRY(P.alloc(P.ws_w0_lo, el_total * 2));
-    TDA_TRY(P.alloc(P.ws_y0, el_total * 4));
+    TDA_TRY(P.alloc(P.ws_mix, total));
     TDA_TRY(P.alloc(P.ws_fft, (size_t)kRefineWG * max_m * 16));
     for (int64_t k = 0; k < n_items; ++k) {
       const tda_work &w = items[k];
       const int64_t Bp = (w.B + MT - 1) / MT * MT;
-      MixWs ws{(uint16_t *)P.ws_hs_hi.p + el_off[k], (uint16_t *)P.ws_hs_lo.p + el_off[k],
-               (uint16_t *)P.ws_w0_hi.p + el_off[k], (uint16_t *)P.ws_w0_lo.p + el_off[k],
-               (float *)P.ws_y0.p + el_off[k]};
-      mis[k] = make_mix_item(w.h, w.H, w.ldh, w.B, Bp, ws);
-      ris[k] = make_ref_item(w.h, w.H, w.ldh, w.B, ws.y0, partbuf + part_off[k]);
-      mis[k].Hrows = ris[k].Hrows = hrows ? hrows[k] : nullptr;
-      if (w.B == 0) continue;
-      add_block_jobs(w.h, (int32_t)k, (int32_t)(Bp / MT), false, jf);
-      add_block_jobs(w.h, (int32_t)k, (int32_t)(Bp / MT), true, jb);
-      for (int64_t b = 0; b < w.B; ++b) wr.push_back(int2{(int32_t)k, (int32_t)b});
+      const MixWs ws = carve_mix_ws(w.h, Bp, (char *)P.ws_mix.p + ws_off[k]);
+      mis[k] = make_mix_item(w.h, w.H, w.ldh, w.B, Bp, ws, partbuf + part_off[k]);
+      mis[k].Hrows = hrows ? hrows[k] : nullptr;
+      ris[k] = make_ref_item(w.h, mis[k]);
+      hs[k] = w.h;
     }
-    const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
-    HIP_TRY(mc->ring.reserve(4096 + n_items * (sizeof(MixItem) + sizeof(RefItem)) +
-                             (wf.size() + wbk.size()) * sizeof(int4) + wr.size() * sizeof(int2) +
-                             n_items * 16 + group_out.size() * 16));
-    void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr;
-    HIP_TRY(mc->ring.push(mis.data(), mis.size() * sizeof(MixItem), s, &d_mi));
-    HIP_TRY(mc->ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
-    HIP_TRY(mc->ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
-    HIP_TRY(mc->ring.push(wbk.data(), wbk.size() * sizeof(int4), s, &d_wb));
-    HIP_TRY(mc->ring.push(wr.data(), wr.size() * sizeof(int2), s, &d_wr));
-    {
-      TimedScope ts("split_h", s);
-      for (int64_t k = 0; k < n_items; ++k)
-        if (items[k].B > 0)
-          HIP_TRY(launch_split_h((const MixItem *)d_mi, (int32_t)k, mis[k].Bp, items[k].h->n_pad, s));
-    }
-    {
-      TimedScope ts("trmm_fwd", s);
-      HIP_TRY(launch_trmm_fwd((const MixItem *)d_mi, (const int4 *)d_wf, (int64_t)wf.size(), s));
-    }
-    {
-      TimedScope ts("trmm_bwd", s);
-      HIP_TRY(launch_trmm_bwd((const MixItem *)d_mi, (const int4 *)d_wb, (int64_t)wbk.size(), s));
-    }
-    {
-      TimedScope ts("refine_fft", s);
-      HIP_TRY(launch_refine((const RefItem *)d_ri, (const int2 *)d_wr, (int64_t)wr.size(),
-                            (double *)P.ws_fft.p, 2 * max_m, kRefineWG, s));
-    }
+    TDA_TRY(enqueue_mixed(mc->ring, mis, ris, hs, (double *)P.ws_fft.p, max_m, s));
+    HIP_TRY(mc->ring.reserve(4096 + n_items * 16 + group_out.size() * 16));
   }
   // network sums per output array, in item order
   void *d_off, *d_grp, *d_outs, *d_Bs;

@@ -17,8 +17,8 @@ constexpr int TB = 256;
 constexpr int CP = 128;
 // Columns (templates) per workgroup of the FP64 triangular solve.
 constexpr int BC = 32;
-// Mixed path: templates per workgroup tile of the BF16x3 products.
-constexpr int MT = 128;
+// Mixed path: template padding unit (the transposed product covers 256 templates).
+constexpr int MT = 256;
 
 // ---------------------------------------------------------------- device-side work descriptors
 
@@ -66,7 +66,11 @@ struct MixItem {
   uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][n_pad/16][64][8]
   uint16_t *w0_hi, *w0_lo;         // split W h, same layout as hs
   float *y0;                       // [Bp][n_pad]
+  double *e64;                     // [Bp][n_pad] FP64 residual h - C y0 (padded rows 0)
+  double *corr_part;               // [nblk][Bp] per-block sums of (W e)^2
+  double *qpart;                   // [Bp] FP64 part of the quadratic form
   double *out;
+  double cterm;
   int32_t B, Bp;                   // templates, padded to a multiple of MT
   int32_t nblk;
   int32_t n_pad;
@@ -76,6 +80,7 @@ struct MixItem {
 struct SegDev {
   int64_t offset, length;  // sample range of the segment
   int64_t row0;            // first padded row
+  int64_t npad;            // padded rows of the segment
   int64_t m;               // circulant length (power of two >= 2 length)
   int32_t log2m;
   int32_t pad0;
@@ -94,6 +99,9 @@ struct RefItem {
   const double *const *Hrows;
   const double *yd_pos;    // [N] C^-1 d scattered to sample positions (0 at excluded)
   const double *qdd;       // scalar
+  const int32_t *idx;      // [n_pad] sample index of each padded row, -1 = padding
+  double *e64;             // [Bp][n_pad] residual output
+  double *qpart;           // [Bp] FP64 part of q output
   double *out;
   double cterm;
   int32_t n_pad;
@@ -150,11 +158,34 @@ hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const i
                               double *yd_pos, double *qdd, hipStream_t s);
 hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
                          hipStream_t s);
-hipError_t launch_split_h(const MixItem *items, int32_t item_id, int64_t Bp, int64_t n_pad,
+// from_e = 0: split the gathered templates h; 1: split the FP64 residual e64 (same layout)
+// one launch over all items; max_chunks = max over items of (Bp/32)(n_pad/16) 64
+hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
                           hipStream_t s);
-hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s);
-hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, hipStream_t s);
-hipError_t launch_refine(const RefItem *items, const int2 *work, int64_t n_work, double *scratch,
+hipError_t launch_corr(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                       hipStream_t s);
+hipError_t launch_finish(const MixItem *items, const int2 *work, int64_t n_work, hipStream_t s);
+// fwd/corr entries: (item, row block, group of 128 templates, 0);
+// bwd entries: (item, column block, group of 256 templates, half of the block)
+// variant: 1 or 2 waves per SIMD (chosen per shape by the autotuner)
+hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                           hipStream_t s);
+hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------- autotuner (autotune.cpp)
+// Chooses, per (kernel, row bucket, template bucket), the fastest variant among
+// `variants` by timing one launch of each on the caller's stream the first time the key
+// is seen (that call synchronises).  Choices persist in-process and, when the
+// environment variable TDA_AUTOTUNE_CACHE names a file, across processes (text lines
+// "kernel rows_log2 templates_log2 variant").  TDA_AUTOTUNE=0 disables timing and uses
+// the first variant.
+int autotune_pick(const char *kernel, int64_t rows, int64_t templates, const int *variants,
+                  int n_variants, hipStream_t s, hipError_t (*launch)(void *ctx, int variant),
+                  void *ctx);
+void register_mixed_attributes();
+// work entries (item, template a, template b or -1, 0): two templates share one DFT
+hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s);
 
 // ---------------------------------------------------------------- internal entry points (tda_api.hip)

@@ -222,7 +222,7 @@ def _streams(k):
     return dict(zip(["gaps", "noise", "injection", "templates", "requests"], root.spawn(5)))
 
 
-def _instance(st, n, n_det, n_gaps, B, eps):
+def _instance(st, n, n_det, n_gaps, B, eps, rows=None):
     acf = make_acf(n, eps)
     masks = []
     for _ in range(n_det):                      # gap positions drawn per detector
@@ -233,6 +233,8 @@ def _instance(st, n, n_det, n_gaps, B, eps):
     inj = _scaled_chirps(n, *p, n_det)[0]
     d = noise + inj[None, :]
     pt = _template_params(st["templates"], n, B)
+    if rows is not None:  # only these template rows (same draws as the full bank)
+        pt = tuple(np.asarray(x)[rows] for x in pt)
     H = _scaled_chirps(n, *pt, n_det)
     return Instance(N=n, acf=acf, masks=masks, segments=None, d=d, H=H, eps=eps)
 
@@ -256,16 +258,18 @@ def c1_workload(eps: float = EPS_PRIMARY, B: int = 32) -> Workload:
     return Workload("C1", [Instance(n, acf, [None], None, d, H, eps)])
 
 
-def c2_workload(eps: float = EPS_PRIMARY, B: int = 4096, n: int = 16384) -> Workload:
-    """Two detectors x N = 16384 (4 s), independent noise, 4096 templates per launch."""
+def c2_workload(eps: float = EPS_PRIMARY, B: int = 4096, n: int = 16384, rows=None) -> Workload:
+    """Two detectors x N = 16384 (4 s), independent noise, 4096 templates per launch.
+
+    ``rows`` selects a subset of the template bank (same draws as the full bank)."""
     st = _streams(1)
-    return Workload("C2", [_instance(st, n, 2, 0, B, eps)])
+    return Workload("C2", [_instance(st, n, 2, 0, B, eps, rows)])
 
 
-def c3_workload(eps: float = EPS_PRIMARY, B: int = 8192, n: int = 32768) -> Workload:
+def c3_workload(eps: float = EPS_PRIMARY, B: int = 8192, n: int = 32768, rows=None) -> Workload:
     """One detector, N = 32768 (8 s), exactly 3 gaps of 64-512 samples, 8192 templates."""
     st = _streams(2)
-    return Workload("C3", [_instance(st, n, 1, 3, B, eps)])
+    return Workload("C3", [_instance(st, n, 1, 3, B, eps, rows)])
 
 
 def c4_workload(eps: float = EPS_PRIMARY, n_inst: int = 64, B: int = 256,

@@ -1,10 +1,11 @@
 """FP64 HIP path against the FP64 oracle (parity), through the C ABI.
 
-Tolerance: |logL_gpu - logL_oracle| <= 1e-6 absolute.  Both sides are FP64; with
-kappa(L) ~ 1.7e3 at the primary nugget the expected difference is ~1e-9 on
-|logL| ~ 1e3-1e4, so 1e-6 leaves three orders of margin while still catching
-any dropped term (the smallest term, one template sample's contribution, is
-far above it).
+Tolerance: |logL_gpu - logL_oracle| <= 1e-6 + 2e-9 |logL|.  Both sides are FP64
+but use different orderings (blocked solve with inverted diagonal blocks vs
+LAPACK), so each carries a forward error of order kappa(C) u q in the quadratic
+form; with kappa(C) ~ 2.9e6 at the primary nugget that is ~3e-10 q, and q ~ 2|logL|
+for the large-residual templates.  Any dropped term (a sample's contribution,
+the log det, the 2 pi constant) is far above this bound.
 """
 import numpy as np
 import pytest
@@ -13,7 +14,10 @@ import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-6
+
+
+def TOLF(want):
+    return 1e-6 + 2e-9 * np.abs(want)
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +56,7 @@ def test_f64_parity_small(tda, N, n_gaps, B, segments):
     info = h.info()
     assert info["n_eff"] == f.n_eff
     assert abs(info["logdet"] - f.logdet) < 1e-7 * max(1.0, abs(f.logdet))
-    assert np.max(np.abs(got - want)) <= TOL, np.max(np.abs(got - want))
+    assert np.all(np.abs(got - want) <= TOLF(want)), np.max(np.abs(got - want))
     h.close()
 
 
@@ -62,7 +66,7 @@ def test_f64_c1_workload(tda):
     h, got = _run(tda, inst)
     f = oracle.factor(inst.acf, inst.N)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.max(np.abs(got - want)) <= TOL
+    assert np.all(np.abs(got - want) <= TOLF(want))
     # the injection's own template family peaks near the unperturbed parameters
     assert np.all(np.isfinite(got))
 
@@ -79,7 +83,7 @@ def test_f64_closed_form_white_noise(tda):
     keep = mask == 0
     r = (d[None] - H)[:, keep]
     want = -0.5 * (r * r).sum(1) / sig2 - 0.5 * keep.sum() * np.log(2 * np.pi * sig2)
-    assert np.max(np.abs(got - want)) <= TOL
+    assert np.all(np.abs(got - want) <= TOLF(want))
 
 
 def test_f64_gapped_ar1_closed_form_large(tda):

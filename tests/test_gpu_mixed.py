@@ -3,7 +3,8 @@ multi-item batched path, against the FP64 oracle through the C ABI.
 
 Mixed tolerance: |logL_mixed - logL_oracle| <= 1e-3 (the accuracy target of the
 mixed path).  The refined quadratic form never exceeds the exact one, so
-logL_mixed >= logL_oracle - 1e-6 (variational bound; 1e-6 covers FP64 rounding).
+logL_mixed >= logL_oracle - tol_f64 (variational bound; tol_f64 = 1e-6 + 2e-9|logL|
+covers the FP64 forward error of both sides, see test_gpu_f64).
 """
 import numpy as np
 import pytest
@@ -13,7 +14,10 @@ import synth
 
 pytestmark = pytest.mark.gpu
 TOL_MIXED = 1e-3
-TOL_F64 = 1e-6
+
+
+def TOLF(want):
+    return 1e-6 + 2e-9 * np.abs(want)
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +33,7 @@ def tda():
 def _check_mixed(got, want):
     err = got - want
     assert np.max(np.abs(err)) <= TOL_MIXED, np.max(np.abs(err))
-    assert np.min(err) >= -TOL_F64, np.min(err)
+    assert np.all(err >= -TOLF(want)), np.min(err)
 
 
 @pytest.mark.parametrize("N,n_gaps,B,segments,eps", [
@@ -50,7 +54,7 @@ def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
     f64 = h.loglik(d, H, precision="fp64").cpu().numpy()
     f = oracle.factor(inst.acf, N, inst.masks[0], segments)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.max(np.abs(f64 - want)) <= TOL_F64
+    assert np.all(np.abs(f64 - want) <= TOLF(want))
     _check_mixed(got, want)
     # data cache: new data pointer is picked up, same pointer reuses the cache
     d2 = to_dev(inst.d[0][::-1].copy())
@@ -72,9 +76,10 @@ def test_mixed_invariants(tda):
     d2, H2 = d.clone(), H.clone()
     d2[m] = float("nan"); H2[:, m] = float("nan")
     np.testing.assert_array_equal(h.loglik(d2, H2).cpu().numpy(), base)
-    # batch composition does not change a template's result (fixed tile shapes)
+    # batch composition changes a template's result only at rounding level (templates
+    # share complex DFTs in pairs)
     sub = h.loglik(d, H[:7].contiguous()).cpu().numpy()
-    np.testing.assert_array_equal(sub, base[:7])
+    np.testing.assert_allclose(sub, base[:7], rtol=0, atol=1e-8)
     H3 = H.clone(); H3[4, 100] = float("nan")
     r3 = h.loglik(d, H3).cpu().numpy()
     assert np.isnan(r3[4]) and np.all(np.isfinite(np.delete(r3, 4)))
@@ -107,7 +112,7 @@ def test_multi_ragged_instances(tda, precision):
     for out, want in zip(outs, wants):
         got = out.cpu().numpy()
         if precision == "fp64":
-            assert np.max(np.abs(got - want)) <= TOL_F64
+            assert np.all(np.abs(got - want) <= TOLF(want))
         else:
             _check_mixed(got, want)
 
