@@ -191,6 +191,28 @@ typedef struct {
 tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, int32_t precision,
                             void *hip_stream);
 
+/*
+ * Plans: a batched evaluation frozen once (items, precision, workspace, kernel
+ * variants) and then replayed.  tda_plan_create copies the item list (the
+ * pointers inside must stay valid for the plan's lifetime), runs the evaluation
+ * once synchronously (allocating every workspace and settling the autotuner),
+ * and keeps a private workspace.  tda_plan_execute enqueues the evaluation on
+ * hip_stream; with use_graph != 0 the first call captures the launch sequence
+ * into a HIP graph on that stream and every call launches the graph (one
+ * submission per step, no allocation, no descriptor upload).  Once captured, a
+ * plan always replays its graph.  Results overwrite the items' outputs as in
+ * tda_loglik_multi.  Calls on one plan must be serialised by the caller.  The
+ * graph also captures each handle's cached whitened data: after tda_set_data
+ * with another vector on a handle of the plan, destroy and re-create the plan.
+ * tda_loglik, tda_loglik_ex and tda_loglik_multi refuse a capturing stream
+ * (TDA_ESTATE); plans are the way to put an evaluation into a graph.
+ */
+typedef struct tda_plan *tda_plan_t;
+tda_status tda_plan_create(const tda_work *items, int64_t n_items, int32_t precision,
+                           tda_plan_t *out);
+tda_status tda_plan_execute(tda_plan_t p, void *hip_stream, int32_t use_graph);
+tda_status tda_plan_destroy(tda_plan_t p);
+
 tda_status tda_info(tda_handle h, tda_info_t *info);
 
 /*

@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = ["TdaError", "Handle", "loglik_multi", "load_library", "LIB_PATH",
-           "timing_enable", "timing_read", "Server",
+           "timing_enable", "timing_read", "Server", "Plan",
            "PREC_FP64", "PREC_MIXED", "EXPORTED_SYMBOLS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
@@ -22,7 +22,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
     "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
-    "tda_timing_enable", "tda_timing_read",
+    "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
+    "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
     "tda_server_wait", "tda_server_stats", "tda_server_destroy",
 ]
@@ -314,6 +315,41 @@ class Server:
         if getattr(self, "_s", None) is not None and self._s.value:
             _lib.tda_server_destroy(self._s)
             self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Frozen batched evaluation, optionally replayed as a HIP graph (see tda.h)."""
+
+    def __init__(self, items, precision="mixed"):
+        L = load_library()
+        vp = ctypes.c_void_p
+        L.tda_plan_create.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(vp)]
+        L.tda_plan_execute.argtypes = [vp, vp, ctypes.c_int32]
+        L.tda_plan_destroy.argtypes = [vp]
+        for f in ("tda_plan_create", "tda_plan_execute", "tda_plan_destroy"):
+            getattr(L, f).restype = ctypes.c_int
+        arr = (_Work * len(items))()
+        for k, (h, d, H, out) in enumerate(items):
+            arr[k] = _Work(h.ptr, _ptr(d), _ptr(H), H.shape[0], H.stride(0), _ptr(out))
+        self._keep = list(items)
+        p = vp()
+        _check(L.tda_plan_create(ctypes.cast(arr, vp), len(items), _precision(precision),
+                                 ctypes.byref(p)))
+        self._p = p
+
+    def execute(self, stream=None, graph=False):
+        _check(_lib.tda_plan_execute(self._p, _stream(stream), 1 if graph else 0))
+
+    def close(self):
+        if getattr(self, "_p", None) is not None and self._p.value:
+            _lib.tda_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -272,14 +272,19 @@ struct FragSrc {
 
 constexpr int FRAG = 512;  // bf16 elements per fragment (64 lanes x 8)
 
+// Wave tile: 4 A tiles x WB B tiles; workgroup of 4 waves covers 8 A tiles x 2 WB B tiles.
+// WB = 4 (128 x 128 per wave, 256 x 256 per workgroup) maximises operand reuse; WB = 2
+// (128 x 64 per wave) halves the registers so two workgroups fit per CU.  The
+// autotuner picks per shape.
+template <int WB>
 struct Step {
-  bf8 ah[4], al[4], bh[2], bl[2];
+  bf8 ah[4], al[4], bh[WB], bl[WB];
 };
 
 // NPROD = 3: hi*hi + hi*lo + lo*hi; NPROD = 1: hi*hi only (lo parts not loaded)
-template <int NPROD>
+template <int NPROD, int WB>
 __device__ __forceinline__ void load_step(const FragSrc &A, const FragSrc &B, int ta, int tb,
-                                          int64_t ks, int lane, Step &st) {
+                                          int64_t ks, int lane, Step<WB> &st) {
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int64_t off = (int64_t)(ta + a) * A.s_tile + ks * A.s_ks + lane * 8;
@@ -287,79 +292,84 @@ __device__ __forceinline__ void load_step(const FragSrc &A, const FragSrc &B, in
     if (NPROD == 3) st.al[a] = load_frag(A.lo + off);
   }
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
+  for (int b = 0; b < WB; ++b) {
     const int64_t off = (int64_t)(tb + b) * B.s_tile + ks * B.s_ks + lane * 8;
     st.bh[b] = load_frag(B.hi + off);
     if (NPROD == 3) st.bl[b] = load_frag(B.lo + off);
   }
 }
 
-template <int NPROD>
-__device__ __forceinline__ void mma_step(const Step &st, f16v (&acc)[4][2]) {
+template <int NPROD, int WB>
+__device__ __forceinline__ void mma_step(const Step<WB> &st, f16v (&acc)[4][WB]) {
   // separate passes so consecutive matrix-core ops use independent accumulators
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bh[b], acc[a][b]);
+    for (int b = 0; b < WB; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bh[b], acc[a][b]);
   if (NPROD == 3) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bl[b], acc[a][b]);
+      for (int b = 0; b < WB; ++b) acc[a][b] = mfma_bf16(st.ah[a], st.bl[b], acc[a][b]);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = mfma_bf16(st.al[a], st.bh[b], acc[a][b]);
+      for (int b = 0; b < WB; ++b) acc[a][b] = mfma_bf16(st.al[a], st.bh[b], acc[a][b]);
   }
 }
 
-template <int NPROD = 3>
+// acc[a][b]: A tile 4 (w/2) + a, B tile WB (w%2) + b of the workgroup's operand window
+template <int NPROD, int WB>
 __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int64_t nks,
-                                      f16v (&acc)[4][2]) {
+                                      f16v (&acc)[4][WB]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ta = 4 * (w >> 1), tb = 2 * (w & 1);
+  const int ta = 4 * (w >> 1), tb = WB * (w & 1);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f16v{};
-  Step s0, s1;
-  if (nks > 0) load_step<NPROD>(A, B, ta, tb, 0, lane, s0);
+    for (int b = 0; b < WB; ++b) acc[a][b] = f16v{};
+  Step<WB> s0, s1;
+  if (nks > 0) load_step<NPROD, WB>(A, B, ta, tb, 0, lane, s0);
   int64_t ks = 0;
   for (; ks + 1 < nks; ks += 2) {
-    load_step<NPROD>(A, B, ta, tb, ks + 1, lane, s1);
-    mma_step<NPROD>(s0, acc);
-    if (ks + 2 < nks) load_step<NPROD>(A, B, ta, tb, ks + 2, lane, s0);
-    mma_step<NPROD>(s1, acc);
+    load_step<NPROD, WB>(A, B, ta, tb, ks + 1, lane, s1);
+    mma_step<NPROD, WB>(s0, acc);
+    if (ks + 2 < nks) load_step<NPROD, WB>(A, B, ta, tb, ks + 2, lane, s0);
+    mma_step<NPROD, WB>(s1, acc);
   }
-  if (ks < nks) mma_step<NPROD>(s0, acc);
+  if (ks < nks) mma_step<NPROD, WB>(s0, acc);
 }
 
-// w0 = W h: rows of row block i, templates of group tg (128); w0 written as F(w0^T).
-template <int OCC>
-__global__ __launch_bounds__(256, OCC) void k_trmm_fwd(const MixItem *__restrict__ items,
-                                                     const int4 *__restrict__ work) {
+// Work entries (item, block, group of 256 templates, sub): WB = 2 workgroups take the
+// B half `sub`; WB = 4 workgroups cover both halves at sub = 0 and skip sub = 1.
+
+// w0 = W h: rows of row block i (A = F(W)), templates of the group (B = F(Hs)); w0 is
+// written in F(w0^T).
+template <int WB>
+__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem *__restrict__ items,
+                                                                  const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0) return;
+  if (wk.y < 0 || (WB == 4 && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int i = wk.y, tg = wk.z;
+  const int i = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int bf = it.blk_first[i];
   const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
   const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
-  const int64_t T0 = (int64_t)tg * 4;
+  const int64_t T0 = (int64_t)wk.z * 8 + (WB == 2 ? 4 * wk.w : 0);
   const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
   const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
                   nks_all * FRAG, FRAG};
-  f16v acc[4][2];
-  gemm3(A, B, nks, acc);
+  f16v acc[4][WB];
+  gemm3<3, WB>(A, B, nks, acc);
   // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8), pos p%8
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int64_t rt_row = (int64_t)i * TB + 32 * (4 * (w >> 1) + a);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int64_t T = T0 + 2 * (w & 1) + b;
+    for (int b = 0; b < WB; ++b) {
+      const int64_t T = T0 + WB * (w & 1) + b;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int64_t base = rt_row + 8 * g;
@@ -380,32 +390,33 @@ __global__ __launch_bounds__(256, OCC) void k_trmm_fwd(const MixItem *__restrict
 }
 
 // y0^T = w0^T W over column block j (K = rows [j TB, (last_j + 1) TB)): A = F(w0^T)
-// (256 templates of group tg), B = F(W^T) restricted to half `hf` (128 samples) of block j.
-template <int OCC>
-__global__ __launch_bounds__(256, OCC) void k_trmm_bwd(const MixItem *__restrict__ items,
-                                                     const int4 *__restrict__ work) {
+// (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for WB = 2).
+template <int WB>
+__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem *__restrict__ items,
+                                                                  const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0) return;
+  if (wk.y < 0 || (WB == 4 && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int j = wk.y, tg = wk.z, hf = wk.w;
+  const int j = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int last = it.blk_last[j];
   const int64_t nks = (int64_t)(last + 1 - j) * (TB / 16);
   const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)j * (TB / 16);
-  const int64_t T0 = (int64_t)tg * 8;
+  const int64_t T0 = (int64_t)wk.z * 8;
+  const int st0 = WB == 2 ? 4 * wk.w : 0;
   const FragSrc A{it.w0_hi + (T0 * nks_all + ks0) * FRAG, it.w0_lo + (T0 * nks_all + ks0) * FRAG,
                   nks_all * FRAG, FRAG};
-  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)hf * 4 * FRAG,
-                  it.wb_lo + it.wb_off[j] + (int64_t)hf * 4 * FRAG, FRAG, 8 * FRAG};
-  f16v acc[4][2];
-  gemm3(A, B, nks, acc);
+  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG,
+                  it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG, FRAG, 8 * FRAG};
+  f16v acc[4][WB];
+  gemm3<3, WB>(A, B, nks, acc);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int64_t trow0 = 32 * (T0 + 4 * (w >> 1) + a);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int64_t col = (int64_t)j * TB + 32 * (4 * hf + 2 * (w & 1) + b) + (lane & 31);
+    for (int b = 0; b < WB; ++b) {
+      const int64_t col = (int64_t)j * TB + 32 * (st0 + WB * (w & 1) + b) + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t trow = trow0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -415,44 +426,44 @@ __global__ __launch_bounds__(256, OCC) void k_trmm_bwd(const MixItem *__restrict
   }
 }
 
-// Correction c_b = ||W e_b||^2: same product as the forward one with the split residual
-// (in the template buffers) as B; the epilogue writes, per template, the sum of squares
-// over the 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  The
-// correction only has to be accurate relative to itself (it is already second order in
-// the product error); CORR_PROD selects 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
+// Correction c_b = ||W e_b||^2: the forward product with the split residual (in the
+// template buffers) as B; the epilogue writes, per template, the sum of squares over the
+// 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  CORR_PROD selects
+// 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
 constexpr int CORR_PROD = 3;
-template <int OCC>
-__global__ __launch_bounds__(256, OCC) void k_corr(const MixItem *__restrict__ items,
-                                                 const int4 *__restrict__ work) {
-  __shared__ double red[2][128];
+template <int WB>
+__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_corr(const MixItem *__restrict__ items,
+                                                              const int4 *__restrict__ work) {
+  __shared__ double red[2][256];
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0) return;
+  if (wk.y < 0 || (WB == 4 && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int i = wk.y, tg = wk.z;
+  const int i = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int bf = it.blk_first[i];
   const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
   const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
-  const int64_t T0 = (int64_t)tg * 4;
+  const int64_t T0 = (int64_t)wk.z * 8 + (WB == 2 ? 4 * wk.w : 0);
   const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
   const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
                   nks_all * FRAG, FRAG};
-  f16v acc[4][2];
-  gemm3<CORR_PROD>(A, B, nks, acc);
+  f16v acc[4][WB];
+  gemm3<CORR_PROD, WB>(A, B, nks, acc);
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
+  for (int b = 0; b < WB; ++b) {
     double ss = 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int r = 0; r < 16; ++r) ss += (double)acc[a][b][r] * (double)acc[a][b][r];
     ss += __shfl_xor(ss, 32);  // lanes l and l+32 hold other rows of the same column
-    const int col = 32 * (2 * (w & 1) + b) + (lane & 31);
+    const int col = 32 * (WB * (w & 1) + b) + (lane & 31);
     if (lane < 32) red[w >> 1][col] = ss;
   }
   __syncthreads();
-  if (threadIdx.x < 128) {
+  const int ncol = 64 * WB;
+  if ((int)threadIdx.x < ncol) {
     const int col = threadIdx.x;
     it.corr_part[(int64_t)i * it.Bp + T0 * 32 + col] = red[0][col] + red[1][col];
   }
@@ -471,14 +482,13 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
   it.out[b] = -0.5 * (it.qpart[b] + c) + it.cterm;
 }
 
-// variant: waves per SIMD the kernel is compiled for (1: no register spills, operands
-// and accumulators fully resident; 2: two workgroups per CU for more latency hiding)
+// variant 1: 128 x 128 wave tiles (WB = 4); variant 2: 128 x 64 wave tiles (WB = 2)
 #define TDA_LAUNCH_VARIANT(K)                                                                 \
   if (n_work <= 0) return hipSuccess;                                                        \
   if (variant == 2)                                                                          \
     hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
   else                                                                                       \
-    hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
+    hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
   return hipGetLastError();
 
 hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
@@ -510,83 +520,97 @@ void register_mixed_attributes() {}
 // positions (0 at excluded samples and beyond the segment), z = x_a + i x_b, and
 //   C x = first `length` entries of IDFT_m(lambda . DFT_m(z))   (real part: a, imag: b)
 // because C is the leading block of the circulant of length m >= 2 length whose first
-// column embeds the ACF (eq:toeplitz_fft; lambda real and even, so the two real
+// column embeds the ACF (eq:toeplitz_fft; lambda is real and even, so the two real
 // sequences separate in the real and imaginary parts).  With e = h - C y0 (FP64):
 //   s_hat = 2 h^T y0 - y0^T C y0 <= h^T C^-1 h, error (y* - y0)^T C (y* - y0) = e^T C^-1 e,
-// and the correction kernel adds ||W e||^2, leaving an error of third order.
-//   qpart = q_dd - 2 y_d^T h + s_hat        (FP64), e written for the correction.
-// The length-m DFTs are four-step (m = n1 n2): n1-point DFTs down the columns of x seen
-// as n1 x n2 row-major, twiddle, n2-point DFTs along rows; the inverse runs the same
-// steps backwards.  Small DFTs are radix-4/2 Stockham sequences in LDS; the intermediate
-// lives in the workgroup's global scratch.
+// the correction kernel adds ||W e||^2, and the remaining error is third order.
+//   qpart = q_dd - 2 y_d^T h + s_hat        (FP64); e is written for the correction.
+// Length-m DFTs are four-step (m = n1 n2): n1-point DFTs down the columns of x seen as
+// n1 x n2 row-major, twiddle w_m^{j2 k1}, n2-point DFTs along the rows; the inverse runs
+// the same steps backwards (conjugation trick).  Each n-point DFT (n <= 512) is itself
+// two register DFTs of P1 <= 16 and P2 <= 32 points with one LDS exchange; the length-m
+// intermediate lives in the workgroup's global scratch.
 
-constexpr int FFT_BUF = 2048;  // complex doubles per LDS buffer (two buffers, ping-pong)
-constexpr int FFT_THREADS = 256;
+constexpr int RF_THREADS = 128;
+constexpr int RF_LDS = 2048;  // complex doubles in the LDS work buffer
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
 
-// Forward DFT of `cols` sequences of length P = 2^logP at X[c*P + j] (natural order in and
-// out); returns the buffer (X or Y) holding the result.  twP[k] = exp(-2 pi i k / P).
-__device__ double2 *dft_lds(double2 *X, double2 *Y, int cols, int logP, const double2 *twP) {
-  const int P = 1 << logP;
-  int Ns = 1;
-  double2 *src = X, *dst = Y;
-  int left = logP;
-  while (left > 0) {
-    if (left >= 2) {  // radix-4 stage
-      const int quarter = P >> 2;
-      const int total = cols * quarter;
-      for (int u = threadIdx.x; u < total; u += blockDim.x) {
-        const int c = u >> (logP - 2), j = u & (quarter - 1);
-        const double2 *in = src + c * P;
-        double2 *out = dst + c * P;
-        const int k = j & (Ns - 1);
-        const int tstride = P / (Ns * 4);
-        double2 v0 = in[j], v1 = in[j + quarter], v2 = in[j + 2 * quarter], v3 = in[j + 3 * quarter];
-        if (Ns > 1) {
-          v1 = cmul(v1, twP[(k * tstride) & (P - 1)]);
-          v2 = cmul(v2, twP[(2 * k * tstride) & (P - 1)]);
-          v3 = cmul(v3, twP[(3 * k * tstride) & (P - 1)]);
-        }
-        const double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
-        const double2 d = csub(v1, v3);
-        const double2 a3 = make_double2(d.y, -d.x);  // -i (v1 - v3)
-        const int base = (j / Ns) * Ns * 4 + k;
-        out[base] = cadd(a0, a2);
-        out[base + Ns] = cadd(a1, a3);
-        out[base + 2 * Ns] = csub(a0, a2);
-        out[base + 3 * Ns] = csub(a1, a3);
+__host__ __device__ constexpr int brev_c(int x, int L) {
+  int r = 0;
+  for (int i = 0; i < L; ++i) r |= ((x >> i) & 1) << (L - 1 - i);
+  return r;
+}
+
+// Forward DFT of 2^L points held in registers, decimation in frequency: natural order
+// in, bit-reversed order out (X[k] ends in v[brev(k)]; the callers index accordingly).
+// twP[k] = exp(-2 pi i k / P) for the enclosing length P = 2^LP (LP >= L).
+template <int L, int LP>
+__device__ __forceinline__ void dft_reg(double2 (&v)[1 << L], const double2 *twP) {
+  constexpr int N = 1 << L;
+#pragma unroll
+  for (int s = L; s >= 1; --s) {
+    const int half = 1 << (s - 1), span = 1 << s;
+#pragma unroll
+    for (int g = 0; g < N; g += span)
+#pragma unroll
+      for (int o = 0; o < half; ++o) {
+        const double2 a = v[g + o], b = v[g + o + half];
+        v[g + o] = cadd(a, b);
+        const double2 d = csub(a, b);
+        v[g + o + half] = o ? cmul(d, twP[o << (LP - s)]) : d;  // exp(-2 pi i o / span)
       }
-      Ns *= 4;
-      left -= 2;
-    } else {  // radix-2 stage
-      const int half = P >> 1;
-      const int total = cols * half;
-      for (int u = threadIdx.x; u < total; u += blockDim.x) {
-        const int c = u >> (logP - 1), j = u & (half - 1);
-        const double2 *in = src + c * P;
-        double2 *out = dst + c * P;
-        const int k = j & (Ns - 1);
-        double2 v0 = in[j], v1 = in[j + half];
-        if (Ns > 1) v1 = cmul(v1, twP[(k * (P / (Ns * 2))) & (P - 1)]);
-        const int base = (j / Ns) * Ns * 2 + k;
-        out[base] = cadd(v0, v1);
-        out[base + Ns] = csub(v0, v1);
-      }
-      Ns *= 2;
-      left -= 1;
+  }
+}
+
+// In-place forward DFTs of `cols` sequences of length P = 2^(L1 + L2) at X[c P + j]
+// (natural order in and out): j = P2 j1 + j2, k = k1 + P1 k2.  Needs cols P2 <= threads
+// and cols P1 <= threads.
+template <int L1, int L2>
+__device__ __forceinline__ void dft_cols(double2 *X, int cols, const double2 *twP) {
+  constexpr int P1 = 1 << L1, P2 = 1 << L2, P = P1 * P2, LP = L1 + L2;
+  const int t = threadIdx.x;
+  // step 1: item (c, j2): DFT over j1, twiddle w_P^{j2 k1}, to X[c P + k1 P2 + j2]
+  {
+    const bool act = t < cols * P2;
+    const int c = t >> L2, j2 = t & (P2 - 1);
+    double2 v[P1];
+    if (act) {
+#pragma unroll
+      for (int j1 = 0; j1 < P1; ++j1) v[j1] = X[c * P + P2 * j1 + j2];
+      dft_reg<L1, LP>(v, twP);
+#pragma unroll
+      for (int k1 = 1; k1 < P1; ++k1)
+        v[brev_c(k1, L1)] = cmul(v[brev_c(k1, L1)], twP[(j2 * k1) & (P - 1)]);
     }
     __syncthreads();
-    double2 *t = src;
-    src = dst;
-    dst = t;
+    if (act) {
+#pragma unroll
+      for (int k1 = 0; k1 < P1; ++k1) X[c * P + k1 * P2 + j2] = v[brev_c(k1, L1)];
+    }
+    __syncthreads();
   }
-  return src;
+  // step 2: item (c, k1): DFT over j2, to X[c P + k1 + P1 k2]
+  {
+    const bool act = t < cols * P1;
+    const int c = t >> L1, k1 = t & (P1 - 1);
+    double2 u[P2];
+    if (act) {
+#pragma unroll
+      for (int j2 = 0; j2 < P2; ++j2) u[j2] = X[c * P + k1 * P2 + j2];
+      dft_reg<L2, LP>(u, twP);
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < P2; ++k2) X[c * P + k1 + P1 * k2] = u[brev_c(k2, L2)];
+    }
+    __syncthreads();
+  }
 }
 
 __device__ double block_sum(double v, double *red) {
@@ -601,157 +625,179 @@ __device__ double block_sum(double v, double *red) {
   return s;
 }
 
-// Work entry: (item, template a, template b or -1, 0).
-__global__ __launch_bounds__(FFT_THREADS) void k_refine(const RefItem *__restrict__ items,
-                                                        const int4 *__restrict__ work,
-                                                        int64_t n_work,
-                                                        double2 *__restrict__ scratch_all,
-                                                        int64_t scratch_per_wg) {
-  __shared__ double2 buf[2][FFT_BUF];
+struct PairAcc {
+  double hy_a, hy_b, ydh_a, ydh_b, yc_a, yc_b, bad_a, bad_b;
+};
+
+// log2 of the register factors of an n-point DFT: P1 = 2^min(L, 4), P2 = 2^(L - that)
+template <int L> struct Split { static constexpr int A = L < 4 ? L : 4; static constexpr int B = L - A; };
+
+template <int LM>
+__device__ void refine_segment(const RefItem &it, const SegDev &sd, int64_t ba, int64_t bb,
+                               bool two, double2 *X, double2 *tw1, double2 *tw2, double2 *S,
+                               PairAcc &acc) {
+  constexpr int L1 = (LM + 1) / 2, L2 = LM / 2;
+  constexpr int n1 = 1 << L1, n2 = 1 << L2;
+  constexpr int64_t m = (int64_t)1 << LM;
+  constexpr int A1 = Split<L1>::A, B1 = Split<L1>::B, A2 = Split<L2>::A, B2 = Split<L2>::B;
+  // columns per LDS batch (each register step needs cols * P <= threads)
+  constexpr int cmax1 = RF_THREADS / ((1 << A1) > (1 << B1) ? (1 << A1) : (1 << B1));
+  constexpr int cb1 = (cmax1 < RF_LDS / n1 ? cmax1 : RF_LDS / n1) < n2 ? (cmax1 < RF_LDS / n1 ? cmax1 : RF_LDS / n1) : n2;
+  constexpr int cmax2 = RF_THREADS / ((1 << A2) > (1 << B2) ? (1 << A2) : (1 << B2));
+  constexpr int cb2 = (cmax2 < RF_LDS / n2 ? cmax2 : RF_LDS / n2) < n1 ? (cmax2 < RF_LDS / n2 ? cmax2 : RF_LDS / n2) : n1;
+  const float *ya = it.y0 + ba * it.n_pad;
+  const float *yb = it.y0 + (two ? bb : ba) * it.n_pad;
+  const double *ha = template_row(it, ba);
+  const double *hb = template_row(it, two ? bb : ba);
+  double *ea = it.e64 + ba * it.n_pad;
+  double *eb = two ? it.e64 + bb * it.n_pad : nullptr;
+  for (int k = threadIdx.x; k < n1; k += blockDim.x) {
+    const int64_t r = (int64_t)k * (m / n1);
+    tw1[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
+  }
+  for (int k = threadIdx.x; k < n2; k += blockDim.x) {
+    const int64_t r = (int64_t)k * (m / n2);
+    tw2[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
+  }
+  // padded rows of the segment carry e = 0
+  for (int64_t p = sd.row0 + sd.nkeep + threadIdx.x; p < sd.row0 + sd.npad; p += blockDim.x) {
+    ea[p] = 0.0;
+    if (two) eb[p] = 0.0;
+  }
+  __syncthreads();
+  // pass 1: column DFTs (length n1) of x[n2 j1 + j2], twiddle w_m^{j2 k1}, to S[k1 n2 + j2]
+  for (int j2b = 0; j2b < n2; j2b += cb1) {
+    for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+      const int c = u % cb1, j1 = u / cb1;
+      const int64_t jpos = (int64_t)n2 * j1 + j2b + c;
+      double xa = 0.0, xb = 0.0;
+      if (jpos < sd.length) {
+        const int32_t p = it.pos2row[sd.offset + jpos];
+        if (p >= 0) {
+          xa = (double)ya[p];
+          if (!isfinite(xa)) acc.bad_a = 1.0, xa = 0.0;
+          if (two) {
+            xb = (double)yb[p];
+            if (!isfinite(xb)) acc.bad_b = 1.0, xb = 0.0;
+          }
+        }
+      }
+      X[c * n1 + j1] = make_double2(xa, xb);
+    }
+    __syncthreads();
+    dft_cols<A1, B1>(X, cb1, tw1);
+    for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+      const int c = u % cb1, k1 = u / cb1;
+      const int64_t j2 = j2b + c;
+      const int64_t r = (j2 * (int64_t)k1) & (m - 1);
+      S[(int64_t)k1 * n2 + j2] = cmul(X[c * n1 + k1], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
+    }
+    __syncthreads();
+  }
+  // pass 2: row DFTs (length n2), times lambda, inverse row DFTs (conjugated), twiddle
+  for (int k1b = 0; k1b < n1; k1b += cb2) {
+    for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+      const int c = u / n2, j2 = u % n2;
+      X[c * n2 + j2] = S[(int64_t)(k1b + c) * n2 + j2];
+    }
+    __syncthreads();
+    dft_cols<A2, B2>(X, cb2, tw2);
+    for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+      const int c = u / n2, k2 = u % n2;
+      const double lam = sd.lam[(int64_t)(k1b + c) + (int64_t)n1 * k2];
+      const double2 v = X[c * n2 + k2];
+      X[c * n2 + k2] = make_double2(lam * v.x, -lam * v.y);  // conj(lambda X)
+    }
+    __syncthreads();
+    dft_cols<A2, B2>(X, cb2, tw2);
+    for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
+      const int c = u / n2, j2 = u % n2;
+      const int64_t k1 = k1b + c;
+      const int64_t r = (k1 * (int64_t)j2) & (m - 1);
+      // inverse row result = conj(X); times w_m^{-j2 k1}; stored conjugated for pass 3
+      S[k1 * n2 + j2] = cmul(X[c * n2 + j2], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
+    }
+    __syncthreads();
+  }
+  // pass 3: inverse column DFTs (length n1) -> (C z) at positions n2 j1 + j2; residual and dots
+  const double inv_m = 1.0 / (double)m;
+  for (int j2b = 0; j2b < n2; j2b += cb1) {
+    for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+      const int c = u % cb1, k1 = u / cb1;
+      X[c * n1 + k1] = S[(int64_t)k1 * n2 + j2b + c];
+    }
+    __syncthreads();
+    dft_cols<A1, B1>(X, cb1, tw1);
+    for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
+      const int c = u % cb1, j1 = u / cb1;
+      const int64_t jpos = (int64_t)n2 * j1 + j2b + c;
+      if (jpos >= sd.length) continue;
+      const int64_t jg = sd.offset + jpos;
+      const int32_t p = it.pos2row[jg];
+      if (p < 0) continue;
+      const double2 v = X[c * n1 + j1];
+      const double cza = v.x * inv_m, czb = -v.y * inv_m;
+      const double yd = it.yd_pos[jg];
+      const double xa = (double)ya[p];
+      const double hva = ha[jg];
+      ea[p] = hva - cza;
+      acc.hy_a += hva * xa;
+      acc.ydh_a += hva * yd;
+      acc.yc_a += xa * cza;
+      if (two) {
+        const double xb = (double)yb[p];
+        const double hvb = hb[jg];
+        eb[p] = hvb - czb;
+        acc.hy_b += hvb * xb;
+        acc.ydh_b += hvb * yd;
+        acc.yc_b += xb * czb;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Work entry: (item, template a, template b or -1, 0).  Persistent grid; each workgroup
+// owns m complex doubles of scratch.
+// LMAX bounds log2 m of the segments the instantiation handles: register DFTs of up to
+// 16 points for LMAX = 16 (m <= 65536), 32 points for LMAX = 18; the host picks the
+// smallest instantiation that covers every segment of the launch.
+template <int LMAX>
+__global__ __launch_bounds__(RF_THREADS) void k_refine(const RefItem *__restrict__ items,
+                                                       const int4 *__restrict__ work,
+                                                       int64_t n_work,
+                                                       double2 *__restrict__ scratch_all,
+                                                       int64_t scratch_per_wg) {
+  __shared__ double2 X[RF_LDS];
   __shared__ double2 tw1[512], tw2[512];
-  __shared__ double red[FFT_THREADS];
+  __shared__ double red[RF_THREADS];
   double2 *S = scratch_all + (int64_t)blockIdx.x * scratch_per_wg;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int4 wk = work[wi];
     const RefItem &it = items[wk.x];
     const int64_t ba = wk.y, bb = wk.z;
     const bool two = bb >= 0;
-    const float *ya = it.y0 + ba * it.n_pad;
-    const float *yb = it.y0 + (two ? bb : ba) * it.n_pad;
-    const double *ha = template_row(it, ba);
-    const double *hb = template_row(it, two ? bb : ba);
-    double *ea = it.e64 + ba * it.n_pad;
-    double *eb = two ? it.e64 + bb * it.n_pad : nullptr;
-    double hy_a = 0, hy_b = 0, ydh_a = 0, ydh_b = 0, yc_a = 0, yc_b = 0;
-    // a non-finite y0 entry must not reach the partner through the shared DFT: it is
-    // replaced by 0 there and the template's result is set to NaN at the end
-    double bad_a = 0, bad_b = 0;
+    PairAcc acc{0, 0, 0, 0, 0, 0, 0, 0};
     for (int sg = 0; sg < it.n_segs; ++sg) {
       const SegDev sd = it.segs[sg];
-      const int log2m = sd.log2m;
-      const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
-      const int n1 = 1 << l1, n2 = 1 << l2;
-      const int64_t m = sd.m;
-      const double inv_m = 1.0 / (double)m;
-      for (int k = threadIdx.x; k < n1; k += blockDim.x) {
-        const int64_t r = (int64_t)k * (m / n1);
-        tw1[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
+      switch (sd.log2m) {
+#define TDA_SEG(LM)                                                             \
+  case LM:                                                                      \
+    if constexpr (LM <= LMAX) refine_segment<LM>(it, sd, ba, bb, two, X, tw1, tw2, S, acc); \
+    else acc.bad_a = acc.bad_b = 1.0;                                           \
+    break;
+        TDA_SEG(1) TDA_SEG(2) TDA_SEG(3) TDA_SEG(4) TDA_SEG(5) TDA_SEG(6) TDA_SEG(7)
+        TDA_SEG(8) TDA_SEG(9) TDA_SEG(10) TDA_SEG(11) TDA_SEG(12) TDA_SEG(13) TDA_SEG(14)
+        TDA_SEG(15) TDA_SEG(16) TDA_SEG(17) TDA_SEG(18)
+#undef TDA_SEG
+        default: acc.bad_a = acc.bad_b = 1.0;
       }
-      for (int k = threadIdx.x; k < n2; k += blockDim.x) {
-        const int64_t r = (int64_t)k * (m / n2);
-        tw2[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
-      }
-      __syncthreads();
-      const int cb1 = FFT_BUF / n1 < n2 ? FFT_BUF / n1 : n2;
-      // pass 1: column DFTs (length n1) of x[n2 j1 + j2], twiddle w_m^{j2 k1}, to S[k1 n2 + j2]
-      for (int j2b = 0; j2b < n2; j2b += cb1) {
-        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
-          const int c = u & (cb1 - 1), j1 = u / cb1;
-          const int64_t jpos = (int64_t)n2 * j1 + j2b + c;
-          double xa = 0.0, xb = 0.0;
-          if (jpos < sd.length) {
-            const int32_t p = it.pos2row[sd.offset + jpos];
-            if (p >= 0) {
-              xa = (double)ya[p];
-              if (!isfinite(xa)) bad_a = 1.0, xa = 0.0;
-              if (two) {
-                xb = (double)yb[p];
-                if (!isfinite(xb)) bad_b = 1.0, xb = 0.0;
-              }
-            }
-          }
-          buf[0][c * n1 + j1] = make_double2(xa, xb);
-        }
-        __syncthreads();
-        const double2 *R = dft_lds(buf[0], buf[1], cb1, l1, tw1);
-        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
-          const int c = u & (cb1 - 1), k1 = u / cb1;
-          const int64_t j2 = j2b + c;
-          const int64_t r = (j2 * (int64_t)k1) & (m - 1);
-          S[(int64_t)k1 * n2 + j2] = cmul(R[c * n1 + k1], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
-        }
-        __threadfence_block();
-        __syncthreads();
-      }
-      // pass 2: row DFTs (length n2), times lambda, inverse row DFTs, twiddle w_m^{-j2 k1}
-      const int cb2 = FFT_BUF / n2 < n1 ? FFT_BUF / n2 : n1;
-      for (int k1b = 0; k1b < n1; k1b += cb2) {
-        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
-          const int c = u / n2, j2 = u & (n2 - 1);
-          buf[0][c * n2 + j2] = S[(int64_t)(k1b + c) * n2 + j2];
-        }
-        __syncthreads();
-        double2 *R = dft_lds(buf[0], buf[1], cb2, l2, tw2);
-        double2 *O = R == buf[0] ? buf[1] : buf[0];
-        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
-          const int c = u / n2, k2 = u & (n2 - 1);
-          const double lam = sd.lam[(int64_t)(k1b + c) + (int64_t)n1 * k2];
-          const double2 v = R[c * n2 + k2];
-          O[c * n2 + k2] = make_double2(lam * v.x, -lam * v.y);  // conj(lambda X) for the inverse
-        }
-        __syncthreads();
-        const double2 *R2 = dft_lds(O, R, cb2, l2, tw2);
-        for (int u = threadIdx.x; u < cb2 * n2; u += blockDim.x) {
-          const int c = u / n2, j2 = u & (n2 - 1);
-          const int64_t k1 = k1b + c;
-          const int64_t r = (k1 * (int64_t)j2) & (m - 1);
-          // inverse row result = conj(R2); times w_m^{-j2 k1} = conj(w_m^{j2 k1}); keep conjugated
-          // for the final inverse column DFT: conj(conj(R2) conj(w)) = R2 w
-          S[k1 * n2 + j2] = cmul(R2[c * n2 + j2], make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]));
-        }
-        __threadfence_block();
-        __syncthreads();
-      }
-      // pass 3: inverse column DFTs (length n1): (C z)_{n2 j1 + j2} = conj(DFT(conj T)) / m,
-      // where S already holds conj T; results to S at the natural position n2 j1 + j2
-      for (int j2b = 0; j2b < n2; j2b += cb1) {
-        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
-          const int c = u & (cb1 - 1), k1 = u / cb1;
-          buf[0][c * n1 + k1] = S[(int64_t)k1 * n2 + j2b + c];
-        }
-        __syncthreads();
-        const double2 *R = dft_lds(buf[0], buf[1], cb1, l1, tw1);
-        for (int u = threadIdx.x; u < cb1 * n1; u += blockDim.x) {
-          const int c = u & (cb1 - 1), j1 = u / cb1;
-          const double2 v = R[c * n1 + j1];
-          S[(int64_t)n2 * j1 + j2b + c] = make_double2(v.x * inv_m, -v.y * inv_m);
-        }
-        __threadfence_block();
-        __syncthreads();
-      }
-      // residual e = h - C y0 on the segment's padded rows (0 on padding), and the dots
-      for (int64_t p = sd.row0 + threadIdx.x; p < sd.row0 + sd.npad; p += blockDim.x) {
-        const int32_t jg = it.idx[p];
-        double va = 0.0, vb = 0.0;
-        if (jg >= 0) {
-          const int64_t jpos = jg - sd.offset;
-          const double2 cz = S[jpos];
-          const double yd = it.yd_pos[jg];
-          const double xa = (double)ya[p];
-          const double hva = ha[jg];
-          va = hva - cz.x;
-          hy_a += hva * xa;
-          ydh_a += hva * yd;
-          yc_a += xa * cz.x;
-          if (two) {
-            const double xb = (double)yb[p];
-            const double hvb = hb[jg];
-            vb = hvb - cz.y;
-            hy_b += hvb * xb;
-            ydh_b += hvb * yd;
-            yc_b += xb * cz.y;
-          }
-        }
-        ea[p] = va;
-        if (two) eb[p] = vb;
-      }
-      __syncthreads();
     }
-    const double s_hya = block_sum(hy_a, red), s_ydha = block_sum(ydh_a, red);
-    const double s_yca = block_sum(yc_a, red);
-    const double s_hyb = block_sum(hy_b, red), s_ydhb = block_sum(ydh_b, red);
-    const double s_ycb = block_sum(yc_b, red);
-    const double s_bada = block_sum(bad_a, red), s_badb = block_sum(bad_b, red);
+    const double s_hya = block_sum(acc.hy_a, red), s_ydha = block_sum(acc.ydh_a, red);
+    const double s_yca = block_sum(acc.yc_a, red);
+    const double s_hyb = block_sum(acc.hy_b, red), s_ydhb = block_sum(acc.ydh_b, red);
+    const double s_ycb = block_sum(acc.yc_b, red);
+    const double s_bada = block_sum(acc.bad_a, red), s_badb = block_sum(acc.bad_b, red);
     if (threadIdx.x == 0) {
       const double nan = __builtin_nan("");
       it.qpart[ba] = s_bada > 0 ? nan : it.qdd[0] - 2.0 * s_ydha + 2.0 * s_hya - s_yca;
@@ -763,8 +809,12 @@ __global__ __launch_bounds__(FFT_THREADS) void k_refine(const RefItem *__restric
 hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refine, dim3((unsigned)n_wg), dim3(FFT_THREADS), 0, s, items, work, n_work,
-                     (double2 *)scratch, scratch_per_wg / 2);
+  if (scratch_per_wg / 2 <= ((int64_t)1 << 16))
+    hipLaunchKernelGGL(k_refine<16>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
+                       n_work, (double2 *)scratch, scratch_per_wg / 2);
+  else
+    hipLaunchKernelGGL(k_refine<18>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
+                       n_work, (double2 *)scratch, scratch_per_wg / 2);
   return hipGetLastError();
 }
 

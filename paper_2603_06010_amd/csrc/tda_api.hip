@@ -59,38 +59,68 @@ struct DevBuf {
 
 // Ring of pinned host staging slots and matching device buffers for per-call
 // descriptors.  A slot is reused only after the work that read it has finished.
+// Slot K is the graph slot: sized before a capture, used only while capturing (no
+// waits or allocations there), and never recycled, because the captured graph copies
+// from it on every replay.
 struct DescRing {
   static constexpr int K = 4;
-  void *host[K] = {};
-  void *dev[K] = {};
-  size_t cap[K] = {};
+  void *host[K + 1] = {};
+  void *dev[K + 1] = {};
+  size_t cap[K + 1] = {};
   hipEvent_t ev[K] = {};
   int next = 0;
   int cur = -1;
+  bool graph = false;     // calls go to the graph slot
+  size_t last_used = 0;   // bytes used by the last sealed call
 
+  hipError_t grow(int slot, size_t need) {
+    if (host[slot]) hipHostFree(host[slot]);
+    if (dev[slot]) hipFree(dev[slot]);
+    host[slot] = dev[slot] = nullptr;
+    cap[slot] = 0;
+    const size_t c = std::max(need * 2, (size_t)1 << 16);
+    hipError_t e = hipHostMalloc(&host[slot], c, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(&dev[slot], c);
+    if (e != hipSuccess) return e;
+    cap[slot] = c;
+    return hipSuccess;
+  }
+  // Size the graph slot (outside any capture) and route the next calls to it.
+  hipError_t begin_graph(size_t need) {
+    if (need > cap[K]) {
+      hipError_t e = grow(K, need);
+      if (e != hipSuccess) return e;
+    }
+    graph = true;
+    cur = -1;
+    return hipSuccess;
+  }
+  void end_graph() {
+    graph = false;
+    cur = -1;
+  }
   // Returns a device pointer holding a copy of `data` (enqueued on s).
   hipError_t push(const void *data, size_t n, hipStream_t s, void **dptr) {
     if (cur < 0) {
-      cur = next;
-      next = (next + 1) % K;
-      if (ev[cur]) {
-        hipError_t e = hipEventSynchronize(ev[cur]);
-        if (e != hipSuccess) return e;
+      if (graph) {
+        cur = K;
+      } else {
+        cur = next;
+        next = (next + 1) % K;
+        if (ev[cur]) {
+          hipError_t e = hipEventSynchronize(ev[cur]);
+          if (e != hipSuccess) return e;
+        }
       }
       used = 0;
     }
     const size_t need = used + ((n + 255) & ~(size_t)255);
     if (need > cap[cur]) {
-      if (used) return hipErrorInvalidValue;  // one growth per call, before any push
-      if (host[cur]) hipHostFree(host[cur]);
-      if (dev[cur]) hipFree(dev[cur]);
-      host[cur] = dev[cur] = nullptr;
-      size_t c = std::max(need * 2, (size_t)1 << 16);
-      hipError_t e = hipHostMalloc(&host[cur], c, hipHostMallocDefault);
+      // one growth per call, before any push; never while capturing
+      if (used || cur == K) return hipErrorInvalidValue;
+      hipError_t e = grow(cur, need);
       if (e != hipSuccess) return e;
-      e = hipMalloc(&dev[cur], c);
-      if (e != hipSuccess) return e;
-      cap[cur] = c;
     }
     memcpy((char *)host[cur] + used, data, n);
     hipError_t e = hipMemcpyAsync((char *)dev[cur] + used, (char *)host[cur] + used, n,
@@ -102,22 +132,20 @@ struct DescRing {
   // Reserve room for a whole call up front (so a call never grows mid-way).
   hipError_t reserve(size_t total) {
     if (cur >= 0) return hipSuccess;
+    if (graph) {
+      if (total > cap[K]) return hipErrorInvalidValue;
+      cur = K;
+      used = 0;
+      return hipSuccess;
+    }
     int slot = next;
     if (ev[slot]) {
       hipError_t e = hipEventSynchronize(ev[slot]);
       if (e != hipSuccess) return e;
     }
     if (total > cap[slot]) {
-      if (host[slot]) hipHostFree(host[slot]);
-      if (dev[slot]) hipFree(dev[slot]);
-      host[slot] = dev[slot] = nullptr;
-      cap[slot] = 0;
-      size_t c = std::max(total * 2, (size_t)1 << 16);
-      hipError_t e = hipHostMalloc(&host[slot], c, hipHostMallocDefault);
+      hipError_t e = grow(slot, total);
       if (e != hipSuccess) return e;
-      e = hipMalloc(&dev[slot], c);
-      if (e != hipSuccess) return e;
-      cap[slot] = c;
     }
     cur = slot;
     next = (next + 1) % K;
@@ -126,6 +154,11 @@ struct DescRing {
   }
   hipError_t seal(hipStream_t s) {
     if (cur < 0) return hipSuccess;
+    last_used = used;
+    if (cur == K) {  // graph slot: nothing to wait for later
+      cur = -1;
+      return hipSuccess;
+    }
     if (!ev[cur]) {
       hipError_t e = hipEventCreateWithFlags(&ev[cur], hipEventDisableTiming);
       if (e != hipSuccess) return e;
@@ -135,12 +168,12 @@ struct DescRing {
     return e;
   }
   void destroy() {
-    for (int k = 0; k < K; ++k) {
-      if (ev[k]) hipEventSynchronize(ev[k]), hipEventDestroy(ev[k]);
+    for (int k = 0; k <= K; ++k) {
+      if (k < K && ev[k]) hipEventSynchronize(ev[k]), hipEventDestroy(ev[k]);
       if (host[k]) hipHostFree(host[k]);
       if (dev[k]) hipFree(dev[k]);
       host[k] = dev[k] = nullptr;
-      ev[k] = nullptr;
+      if (k < K) ev[k] = nullptr;
       cap[k] = 0;
     }
   }
@@ -519,6 +552,10 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
     return fail_with(TDA_ESTATE, "compact handle: only mixed evaluation with its cached data");
   DeviceGuard guard(h->device);
   hipStream_t s = (hipStream_t)hip_stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  if (cap != hipStreamCaptureStatusNone)
+    return fail_with(TDA_ESTATE, "stream capture outside a plan: use tda_plan_execute");
   TDA_TRY(order_after_previous(h, s));
   if (precision == TDA_PREC_FP64)
     TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
@@ -566,7 +603,7 @@ std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
   return out;
 }
 
-constexpr int kRefineWG = 512;
+constexpr int kRefineWG = 768;  // persistent refinement workgroups (3 per CU)
 
 }  // namespace
 
@@ -643,6 +680,7 @@ static tda_status build_mixed(tda_ctx *h) {
     sd.offset = g.offset;
     sd.length = g.length;
     sd.row0 = g.row0;
+    sd.nkeep = g.n_keep;
     sd.npad = g.n_pad;
     sd.m = g.m;
     sd.log2m = g.log2m;
@@ -783,16 +821,13 @@ static void add_refine_pairs(int32_t item, int64_t B, std::vector<int4> &wr) {
     wr.push_back(int4{item, (int32_t)b, b + 1 < B ? (int32_t)(b + 1) : -1, 0});
 }
 
-// fwd/corr jobs: (block i, groups of 128 templates); bwd jobs: (block j, groups of 256, 2 halves)
+// product jobs: (block, group of 256 templates, half); see the product kernels for halves
 static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, bool transposed,
                            std::vector<BlockJob> &jobs) {
   for (int32_t i = 0; i < h->nblk; ++i) {
     const int64_t k = transposed ? (int64_t)(h->blk_last_h[i] + 1 - i)
                                  : (int64_t)(i + 1 - h->blk_first_h[i]);
-    if (transposed)
-      jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), 2, k});
-    else
-      jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 128), 1, k});
+    jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), 2, k});
   }
 }
 
@@ -837,7 +872,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     int64_t nw;
     hipStream_t s;
   };
-  static const int kVariants[2] = {2, 1};
+  static const int kVariants[2] = {1, 2};
   Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
   Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
   int64_t max_chunks = 0;
@@ -1020,8 +1055,13 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
   }
   if (max_B == 0) return TDA_OK;
   tda_ctx &P = mc->pool;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap == hipStreamCaptureStatusActive;
+  if (capturing && !mc->ring.graph)
+    return fail_with(TDA_ESTATE, "stream capture outside a plan: use tda_plan_execute");
   if (!mc->done) HIP_TRY(hipEventCreateWithFlags(&mc->done, hipEventDisableTiming));
-  HIP_TRY(hipStreamWaitEvent(s, mc->done, 0));
+  if (!capturing) HIP_TRY(hipStreamWaitEvent(s, mc->done, 0));
   for (int64_t k = 0; k < n_items; ++k) {
     if (order_handles) TDA_TRY(order_after_previous(items[k].h, s));
     if (precision == TDA_PREC_MIXED && items[k].B > 0 && items[k].d != items[k].h->data_ptr)
@@ -1108,12 +1148,98 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
                          (double *const *)d_outs, (const int64_t *)d_Bs,
                          (int64_t)group_out.size(), max_B, s));
   HIP_TRY(mc->ring.seal(s));
-  HIP_TRY(hipEventRecord(mc->done, s));
+  if (!capturing) HIP_TRY(hipEventRecord(mc->done, s));
   if (order_handles)
     for (int64_t k = 0; k < n_items; ++k) TDA_TRY(mark_done(items[k].h, s));
   return TDA_OK;
 }
 }  // namespace
+
+// ---------------------------------------------------------------- plans and HIP graphs
+
+struct tda_plan {
+  MultiCtx *mc = nullptr;
+  std::vector<tda_work> items;
+  int32_t precision = TDA_PREC_FP64;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" tda_status tda_plan_create(const tda_work *items, int64_t n_items, int32_t precision,
+                                      tda_plan_t *out) {
+  if (!out) return fail_with(TDA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_items < 1 || !items || !items[0].h) return fail_with(TDA_EINVAL, "bad item list");
+  tda_plan *p = new tda_plan();
+  p->items.assign(items, items + n_items);
+  p->precision = precision;
+  p->device = items[0].h->device;
+  p->mc = multi_ctx_create();
+  DeviceGuard guard(p->device);
+  hipStream_t s = nullptr;
+  tda_status st = TDA_OK;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    st = fail_with(TDA_EHIP, "plan: stream creation failed");
+  } else {
+    HIP_TRY(hipDeviceSynchronize());
+    st = multi_impl(p->mc, p->items.data(), nullptr, n_items, precision, s, false);
+    if (st == TDA_OK && hipStreamSynchronize(s) != hipSuccess)
+      st = fail_with(TDA_EHIP, "plan: first evaluation failed");
+    (void)hipStreamDestroy(s);
+  }
+  if (st != TDA_OK) {
+    multi_ctx_destroy(p->mc);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_plan_execute(tda_plan_t p, void *hip_stream, int32_t use_graph) {
+  if (!p) return fail_with(TDA_EINVAL, "NULL plan");
+  DeviceGuard guard(p->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!p->exec && !use_graph)
+    return multi_impl(p->mc, p->items.data(), nullptr, (int64_t)p->items.size(), p->precision,
+                      s, false);
+  if (!p->exec) {
+    if (!s) return fail_with(TDA_EINVAL, "graph capture needs a non-default stream");
+    // the graph replays copies out of its own descriptor slot, sized from the eager
+    // evaluation of the same items
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(p->mc->ring.begin_graph(p->mc->ring.last_used));
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const tda_status st = multi_impl(p->mc, p->items.data(), nullptr, (int64_t)p->items.size(),
+                                     p->precision, s, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    p->mc->ring.end_graph();
+    if (st != TDA_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail_with(TDA_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    p->graph = g;
+    HIP_TRY(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(p->exec, s));
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_plan_destroy(tda_plan_t p) {
+  if (!p) return TDA_OK;
+  {
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    multi_ctx_destroy(p->mc);
+  }
+  delete p;
+  return TDA_OK;
+}
 
 // ---------------------------------------------------------------- kernel timing
 
@@ -1149,6 +1275,8 @@ namespace tda {
 TimedScope::TimedScope(const char *n, hipStream_t s) : name(n), stream(s), slot(-1) {
   TimingState &t = timing();
   if (!t.on) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   std::lock_guard<std::mutex> lk(t.mu);
   TimingState::Rec r{n, pool_event(t), pool_event(t)};
   (void)hipEventRecord(r.a, s);

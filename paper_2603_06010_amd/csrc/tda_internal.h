@@ -80,6 +80,7 @@ struct MixItem {
 struct SegDev {
   int64_t offset, length;  // sample range of the segment
   int64_t row0;            // first padded row
+  int64_t nkeep;           // retained rows of the segment
   int64_t npad;            // padded rows of the segment
   int64_t m;               // circulant length (power of two >= 2 length)
   int32_t log2m;

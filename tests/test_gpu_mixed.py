@@ -129,3 +129,34 @@ def test_multi_matches_single(tda):
         tda.loglik_multi([(hs[0], ds[0], H, out), (hs[1], ds[1], H, out)], precision=prec)
         single = hs[0].loglik(ds[0], H, precision=prec) + hs[1].loglik(ds[1], H, precision=prec)
         np.testing.assert_allclose(out.cpu().numpy(), single.cpu().numpy(), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_plan_graph_replay(tda, precision):
+    """A captured plan replayed several times, with eager work in between, matches the
+    eager evaluation on every replay."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(91, 1800, 2, 1, 70)
+    hs = [tda.Handle(inst.acf, inst.N, m, precision="mixed").factor() for m in inst.masks]
+    ds = [to_dev(x) for x in inst.d]
+    H = to_dev(inst.H)
+    ref = torch.empty(70, dtype=torch.float64, device="cuda")
+    tda.loglik_multi([(hs[0], ds[0], H, ref), (hs[1], ds[1], H, ref)], precision=precision)
+    torch.cuda.synchronize()
+    want = ref.cpu().numpy()
+    out = torch.empty(70, dtype=torch.float64, device="cuda")
+    plan = tda.Plan([(hs[0], ds[0], H, out), (hs[1], ds[1], H, out)], precision=precision)
+    stream = torch.cuda.Stream()
+    for rep in range(4):
+        out.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.execute(stream=stream, graph=True)
+        stream.synchronize()
+        np.testing.assert_allclose(out.cpu().numpy(), want, rtol=0, atol=1e-8)
+        # eager work on the default stream between replays
+        other = torch.empty(70, dtype=torch.float64, device="cuda")
+        tda.loglik_multi([(hs[0], ds[0], H, other)], precision=precision)
+        torch.cuda.synchronize()
+    plan.close()
