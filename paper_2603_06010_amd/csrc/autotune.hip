@@ -74,12 +74,19 @@ int autotune_pick(const char *kernel, int64_t rows, int64_t templates, const int
   }
   int best = variants[0];
   float best_ms = 1e30f;
+  const char *verbose = getenv("TDA_AUTOTUNE_VERBOSE");
   for (int k = 0; k < n_variants; ++k) {
+    // the second of two launches: the first also pays for loading the code object
     float ms = 0.f;
-    if (hipEventRecord(a, s) != hipSuccess || launch(ctx, variants[k]) != hipSuccess ||
-        hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-        hipEventElapsedTime(&ms, a, b) != hipSuccess)
-      continue;
+    bool ok = true;
+    for (int rep = 0; rep < 2 && ok; ++rep)
+      ok = hipEventRecord(a, s) == hipSuccess && launch(ctx, variants[k]) == hipSuccess &&
+           hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+           hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    if (!ok) continue;
+    if (verbose && verbose[0] == '1')
+      fprintf(stderr, "[autotune] %s rows=%lld templates=%lld variant %d: %.3f ms\n", kernel,
+              (long long)rows, (long long)templates, variants[k], ms);
     if (ms < best_ms) {
       best_ms = ms;
       best = variants[k];

@@ -208,11 +208,33 @@ __global__ void k_lambda(const double *__restrict__ acf, int64_t length, int64_t
   lam[k] = acf[0] + 2.0 * s;
 }
 
+// Pass twiddles of the in-LDS h-point DFT (h = 2^LH): for pass p >= 1 with sub-transform
+// length Ns and radix R, entry [q-1][k] = w_{Ns R}^{q k} (q = 1 .. R-1, k < Ns).
+__global__ void k_pass_twiddles(int LH, double *__restrict__ ptw) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= rl_tw_size(LH)) return;
+  int p = 1;
+  while (p + 1 < rl_npass(LH) && i >= rl_off(LH, p + 1)) ++p;
+  const int ns = 1 << rl_lns(LH, p), r = 1 << rl_L(LH, p);
+  const int u = i - rl_off(LH, p), q = u / ns + 1, k = u % ns;
+  const int len = ns * r, e = (q * k) % len;
+  double sn, cs;
+  sincospi(2.0 * (double)e / (double)len, &sn, &cs);
+  ptw[2 * i] = cs;
+  ptw[2 * i + 1] = -sn;
+}
+
 hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
-                         hipStream_t s) {
+                         double *ptw, hipStream_t s) {
   const unsigned g = (unsigned)((m + 255) / 256);
   hipLaunchKernelGGL(k_twiddles, dim3(g), dim3(256), 0, s, m, tw);
   hipLaunchKernelGGL(k_lambda, dim3(g), dim3(256), 0, s, acf, length, m, tw, lam);
+  if (ptw && m >= 16 && m <= RL_MAX_M) {
+    int lm = 0;
+    while (((int64_t)1 << lm) < m) ++lm;
+    const int n = rl_tw_size(lm - 2);
+    if (n > 0) hipLaunchKernelGGL(k_pass_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, lm - 2, ptw);
+  }
   return hipGetLastError();
 }
 
@@ -340,12 +362,83 @@ __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int64_
   if (ks < nks) mma_step<NPROD, WB>(s0, acc);
 }
 
+// Pipelined variant (WB = 4): operands pass through LDS.  Each k-step's 32 fragments
+// (A hi/lo and B hi/lo, 8 tiles each) are copied global -> LDS by direct loads, one wave
+// per operand array, GP_STAGES - 1 k-steps ahead of the matrix cores; every fragment is
+// fetched once per workgroup and the waves read their tiles with ds_read_b128.
+constexpr int GP_STAGES = 4;
+constexpr int GP_STAGE_BYTES = 32 * FRAG * 2;
+constexpr size_t GP_LDS_BYTES = (size_t)GP_STAGES * GP_STAGE_BYTES;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// wait until at most N vector-memory operations of this wave are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Workgroup barrier that keeps the direct loads of later stages in flight (a release
+// fence would wait for all of them).  Each wave has already waited for its own copies
+// of the stage it is about to read; the memory clobber keeps LDS accesses on their side.
+__device__ __forceinline__ void gp_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// this wave's operand array (8 tiles) at k-step ks -> fragments 8 w .. 8 w + 7 of a stage
+__device__ __forceinline__ void gp_issue(const uint16_t *src, int64_t s_tile, int64_t s_ks,
+                                         int64_t ks, char *stage, int w, int lane) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const uint16_t *p = src + u * s_tile + ks * s_ks + lane * 8;
+    __builtin_amdgcn_global_load_lds((const void *)p, (lds_void_t *)(stage + (8 * w + u) * 1024),
+                                     16, 0, 0);
+  }
+}
+
+template <int NPROD>
+__device__ __forceinline__ void gemm3_pipe(const FragSrc &A, const FragSrc &B, int64_t nks,
+                                           f16v (&acc)[4][4], char *smem) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ta = 4 * (w >> 1), tb = 4 * (w & 1);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f16v{};
+  const uint16_t *src = w == 0 ? A.hi : w == 1 ? A.lo : w == 2 ? B.hi : B.lo;
+  const int64_t s_tile = w < 2 ? A.s_tile : B.s_tile, s_ks = w < 2 ? A.s_ks : B.s_ks;
+#pragma unroll
+  for (int p = 0; p < GP_STAGES - 1; ++p)
+    if (p < nks) gp_issue(src, s_tile, s_ks, p, smem + p * GP_STAGE_BYTES, w, lane);
+  for (int64_t t = 0; t < nks; ++t) {
+    const int64_t ahead = nks - 1 - t;  // k-steps issued after t (at most GP_STAGES - 2 here)
+    if (ahead >= 2) wait_vmcnt<16>();
+    else if (ahead == 1) wait_vmcnt<8>();
+    else wait_vmcnt<0>();
+    gp_barrier();  // stage t complete for every wave; stage t - 1 no longer read
+    if (t + GP_STAGES - 1 < nks)
+      gp_issue(src, s_tile, s_ks, t + GP_STAGES - 1,
+               smem + ((t + GP_STAGES - 1) % GP_STAGES) * GP_STAGE_BYTES, w, lane);
+    const bf8 *S = (const bf8 *)(smem + (t % GP_STAGES) * GP_STAGE_BYTES);
+    Step<4> st;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      st.ah[a] = S[(ta + a) * 64 + lane];
+      st.al[a] = S[(8 + ta + a) * 64 + lane];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      st.bh[b] = S[(16 + tb + b) * 64 + lane];
+      st.bl[b] = S[(24 + tb + b) * 64 + lane];
+    }
+    mma_step<NPROD, 4>(st, acc);
+  }
+}
+
 // Work entries (item, block, group of 256 templates, sub): WB = 2 workgroups take the
 // B half `sub`; WB = 4 workgroups cover both halves at sub = 0 and skip sub = 1.
 
 // w0 = W h: rows of row block i (A = F(W)), templates of the group (B = F(Hs)); w0 is
 // written in F(w0^T).
-template <int WB>
+template <int WB, bool PIPE = false>
 __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem *__restrict__ items,
                                                                   const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
@@ -362,7 +455,12 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem
   const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
                   nks_all * FRAG, FRAG};
   f16v acc[4][WB];
-  gemm3<3, WB>(A, B, nks, acc);
+  if constexpr (PIPE) {
+    extern __shared__ char gp_smem[];
+    gemm3_pipe<3>(A, B, nks, acc, gp_smem);
+  } else {
+    gemm3<3, WB>(A, B, nks, acc);
+  }
   // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8), pos p%8
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -391,7 +489,7 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem
 
 // y0^T = w0^T W over column block j (K = rows [j TB, (last_j + 1) TB)): A = F(w0^T)
 // (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for WB = 2).
-template <int WB>
+template <int WB, bool PIPE = false>
 __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem *__restrict__ items,
                                                                   const int4 *__restrict__ work) {
   const int4 wk = work[blockIdx.x];
@@ -410,7 +508,12 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem
   const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG,
                   it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG, FRAG, 8 * FRAG};
   f16v acc[4][WB];
-  gemm3<3, WB>(A, B, nks, acc);
+  if constexpr (PIPE) {
+    extern __shared__ char gp_smem[];
+    gemm3_pipe<3>(A, B, nks, acc, gp_smem);
+  } else {
+    gemm3<3, WB>(A, B, nks, acc);
+  }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int64_t trow0 = 32 * (T0 + 4 * (w >> 1) + a);
@@ -431,7 +534,7 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem
 // 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  CORR_PROD selects
 // 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
 constexpr int CORR_PROD = 3;
-template <int WB>
+template <int WB, bool PIPE = false>
 __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_corr(const MixItem *__restrict__ items,
                                                               const int4 *__restrict__ work) {
   __shared__ double red[2][256];
@@ -449,7 +552,12 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_corr(const MixItem *__
   const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
                   nks_all * FRAG, FRAG};
   f16v acc[4][WB];
-  gemm3<CORR_PROD, WB>(A, B, nks, acc);
+  if constexpr (PIPE) {
+    extern __shared__ char gp_smem[];
+    gemm3_pipe<CORR_PROD>(A, B, nks, acc, gp_smem);
+  } else {
+    gemm3<CORR_PROD, WB>(A, B, nks, acc);
+  }
 #pragma unroll
   for (int b = 0; b < WB; ++b) {
     double ss = 0.0;
@@ -482,11 +590,15 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
   it.out[b] = -0.5 * (it.qpart[b] + c) + it.cterm;
 }
 
-// variant 1: 128 x 128 wave tiles (WB = 4); variant 2: 128 x 64 wave tiles (WB = 2)
+// variant 1: 128 x 128 wave tiles (WB = 4); variant 2: 128 x 64 wave tiles (WB = 2);
+// variant 3: WB = 4 with operands staged through LDS
 #define TDA_LAUNCH_VARIANT(K)                                                                 \
   if (n_work <= 0) return hipSuccess;                                                        \
   if (variant == 2)                                                                          \
     hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
+  else if (variant == 3)                                                                     \
+    hipLaunchKernelGGL((K<4, true>), dim3((unsigned)n_work), dim3(256), GP_LDS_BYTES, s,     \
+                       items, work);                                                         \
   else                                                                                       \
     hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
   return hipGetLastError();
@@ -513,7 +625,6 @@ hipError_t launch_finish(const MixItem *items, const int2 *work, int64_t n_work,
   return hipGetLastError();
 }
 
-void register_mixed_attributes() {}
 
 // ---------------------------------------------------------------- FP64 refinement
 // Per template pair (a, b) and segment: x = y0 scattered to the segment's sample
@@ -815,6 +926,282 @@ hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work,
   else
     hipLaunchKernelGGL(k_refine<18>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
                        n_work, (double2 *)scratch, scratch_per_wg / 2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- FP64 refinement in LDS
+// Same quantities as k_refine (C y0 by circulant embedding, eq:toeplitz_fft), organised so
+// that one template's transforms fit in one workgroup's LDS.  With m = 4h the circulant
+// length, n' = m/2 >= length, w_m = exp(-2 pi i / m) and x = y0 at the segment's sample
+// positions (0 at excluded samples and beyond the segment):
+//   (C x)_j = (1/m) [ tE_j + tO_j ],   j < length,
+//   tE = unnormalised inverse n'-point DFT of (lambda_{2k} X_{2k})     (circulant part)
+//   tO_j = sum_{k < n'} lambda_{2k+1} X_{2k+1} w_m^{-j(2k+1)}          (skew-circulant part)
+// where X_r = sum_j x_j w_m^{j r}.  Each part is one forward and one inverse h-point
+// complex DFT of the real data packed as x_{2p} + i x_{2p+1} (pre-multiplied by w_m^{2p}
+// for the odd part); the pointwise stage between them pairs index k with h-k (even part)
+// or h-1-k (odd part), whose values are conjugate-symmetric.  Inverse DFTs are forward
+// DFTs of the conjugate.  The h-point DFT is a sequence of in-place Stockham passes over
+// an LDS array padded by one element per 16 (bank spread for the strided writes).
+constexpr int RL_THREADS = 512;
+constexpr int RL_XN = (1 << RL_LHMAX) + ((1 << RL_LHMAX) >> 4);
+constexpr size_t RL_LDS_BYTES = (size_t)RL_XN * sizeof(double2) + RL_THREADS * sizeof(double);
+
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 scal(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ __forceinline__ double2 mul_i(double2 a) { return make_double2(-a.y, a.x); }
+
+// cos(pi t / 16) for 0 <= t <= 16 (correctly rounded doubles).
+__device__ __forceinline__ constexpr double cos_pi16(int t) {
+  const int u = t <= 8 ? t : 16 - t;
+  const double c = u == 0 ? 1.0 : u == 1 ? 0x1.f6297cff75cb0p-1 : u == 2 ? 0x1.d906bcf328d46p-1
+                 : u == 3 ? 0x1.a9b66290ea1a3p-1 : u == 4 ? 0x1.6a09e667f3bcdp-1
+                 : u == 5 ? 0x1.1c73b39ae68c8p-1 : u == 6 ? 0x1.87de2a6aea963p-2
+                 : u == 7 ? 0x1.8f8b83c69a60bp-3 : 0.0;
+  return t <= 8 ? c : -c;
+}
+
+// Forward DFT of 2^L <= 32 points in registers, decimation in frequency, natural order in,
+// bit-reversed order out; the twiddles w_32^t are constants, so they cost no registers and
+// the trivial ones (1, -i) no multiplications.
+template <int L>
+__device__ __forceinline__ void dft_small(double2 (&v)[1 << L]) {
+  static_assert(L <= 5, "at most 32 points");
+  constexpr int N = 1 << L;
+#pragma unroll
+  for (int s = L; s >= 1; --s) {
+    const int half = 1 << (s - 1), span = 1 << s;
+#pragma unroll
+    for (int g = 0; g < N; g += span)
+#pragma unroll
+      for (int o = 0; o < half; ++o) {
+        const double2 a = v[g + o], b = v[g + o + half];
+        v[g + o] = cadd(a, b);
+        const double2 d = csub(a, b);
+        const int t = (32 / span) * o;  // w_span^o = w_32^t = cos(pi t/16) - i sin(pi t/16)
+        if (t == 0) {
+          v[g + o + half] = d;
+        } else if (t == 8) {
+          v[g + o + half] = make_double2(d.y, -d.x);
+        } else {
+          const double c = cos_pi16(t), sn = cos_pi16(t < 8 ? 8 - t : t - 8);
+          v[g + o + half] = make_double2(d.x * c + d.y * sn, d.y * c - d.x * sn);
+        }
+      }
+  }
+}
+
+// Pass P of the h = 2^LH point forward DFT: radix R = 2^L over sub-transforms of length
+// Ns = 2^LNS; thread j < h/R loads X[j + q h/R], twiddles by w_{Ns R}^{q (j mod Ns)},
+// transforms, and stores to X[(j div Ns) Ns R + j mod Ns + q Ns] (natural order at the end).
+template <int LH, int P>
+__device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ ptw) {
+  constexpr int L = rl_L(LH, P), LNS = rl_lns(LH, P), OFF = rl_off(LH, P);
+  constexpr int R = 1 << L, NS = 1 << LNS, NT = 1 << (LH - L);
+  static_assert(NT <= RL_THREADS, "pass needs more threads than the workgroup has");
+  const int j = threadIdx.x;
+  const bool act = j < NT;
+  const int k = j & (NS - 1);
+  double2 a[R];
+  if (act) {
+    // strides that are multiples of 16 keep the padded addresses at constant offsets
+    if constexpr (NT % 16 == 0) {
+      const double2 *x0 = X + lpad(j);
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[q] = x0[q * (NT + NT / 16)];
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) a[q] = X[lpad(j + q * NT)];
+    }
+    if constexpr (LNS > 0) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) a[q] = cmul(a[q], ptw[OFF + (q - 1) * NS + k]);
+    }
+    dft_small<L>(a);
+  }
+  __syncthreads();
+  if (act) {
+    const int base = ((j >> LNS) << (LNS + L)) + k;
+    if constexpr (NS % 16 == 0) {
+      double2 *x0 = X + lpad(base);
+#pragma unroll
+      for (int q = 0; q < R; ++q) x0[q * (NS + NS / 16)] = a[brev_c(q, L)];
+    } else if constexpr (NS == 1 && R % 16 == 0) {
+      double2 *x0 = X + lpad(base);  // base = j R, a multiple of 16
+#pragma unroll
+      for (int q = 0; q < R; ++q) x0[q + (q >> 4)] = a[brev_c(q, L)];
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) X[lpad(base + q * NS)] = a[brev_c(q, L)];
+    }
+  }
+  __syncthreads();
+}
+
+template <int LH>
+__device__ __forceinline__ void rl_fft(double2 *X, const double2 *ptw) {
+  rl_pass<LH, 0>(X, ptw);
+  if constexpr (rl_npass(LH) > 1) rl_pass<LH, 1>(X, ptw);
+  if constexpr (rl_npass(LH) > 2) rl_pass<LH, 2>(X, ptw);
+}
+
+struct RlAcc {
+  double hy, ydh, yc, bad;
+};
+
+template <int LH>
+__device__ void rl_segment(const RefItem &it, const SegDev &sd, int64_t b, double2 *X,
+                           RlAcc &acc) {
+  constexpr int h = 1 << LH;
+  const int t = threadIdx.x;
+  const float *y = it.y0 + b * it.n_pad;
+  const double *hrow = template_row(it, b) + sd.offset;
+  const double *ydp = it.yd_pos + sd.offset;
+  const int32_t *p2r = it.pos2row + sd.offset;
+  double *e = it.e64 + b * it.n_pad;
+  const double2 *tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
+  const double2 *ptw = (const double2 *)sd.ptw;
+  const double *lam = sd.lam;
+  const int len = (int)sd.length;
+  const double inv_m = 1.0 / (double)(4 * h);
+  auto wm = [&](int r) {  // w_m^r, 0 <= r < m
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  auto xat = [&](int jj) -> double {
+    if (jj >= len) return 0.0;
+    const int32_t r = p2r[jj];
+    if (r < 0) return 0.0;
+    const double v = (double)y[r];
+    if (!isfinite(v)) {
+      acc.bad = 1.0;
+      return 0.0;
+    }
+    return v;
+  };
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
+
+  // ---- even frequencies: circulant part
+  for (int p = t; p < h; p += RL_THREADS) X[lpad(p)] = make_double2(xat(2 * p), xat(2 * p + 1));
+  __syncthreads();
+  rl_fft<LH>(X, ptw);
+  for (int k = t; k <= h / 2; k += RL_THREADS) {
+    const int kr = (h - k) & (h - 1);
+    const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+    // spectra of the even- and odd-indexed samples: E = (vk + conj vr)/2, O = -i (vk - conj vr)/2
+    const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+    const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+    const double2 c = wm(2 * k);  // w_{n'}^k
+    const double2 cO = cmul(c, O);
+    const double2 yk = scal(lam[2 * k], cadd(E, cO));
+    const double2 yr = scal(lam[2 * h - 2 * k], conj2(csub(E, cO)));
+    const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
+    X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(c), op))));
+    if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(c, conj2(op)))));
+  }
+  __syncthreads();
+  rl_fft<LH>(X, ptw);
+  // tE_{2p} + i tE_{2p+1} = conj(X[p]); kept (scaled) in e until the odd part adds to it
+  for (int p = t; p < h; p += RL_THREADS) {
+    const double2 v = X[lpad(p)];
+    const int j0 = 2 * p;
+    if (j0 < len && p2r[j0] >= 0) e[p2r[j0]] = v.x * inv_m;
+    if (j0 + 1 < len && p2r[j0 + 1] >= 0) e[p2r[j0 + 1]] = -v.y * inv_m;
+  }
+  __syncthreads();
+
+  // ---- odd frequencies: skew-circulant part
+  for (int p = t; p < h; p += RL_THREADS)
+    X[lpad(p)] = cmul(make_double2(xat(2 * p), xat(2 * p + 1)), wm(2 * p));
+  __syncthreads();
+  rl_fft<LH>(X, ptw);
+  const double2 om = wm(1);
+  for (int k = t; k < h / 2; k += RL_THREADS) {
+    const int kr = h - 1 - k;
+    const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+    const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+    const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+    const double2 dB = cmul(wm(2 * k + 1), B);
+    const double2 yk = scal(lam[2 * k + 1], cadd(A, dB));          // X_{2k+1}
+    const double2 ykh = scal(lam[2 * k + 2 * h + 1], csub(A, dB));  // X_{2k+2h+1}
+    const double2 P = cadd(yk, ykh);
+    const double2 Q = cmul(conj2(wm(2 * k)), csub(yk, ykh));
+    X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
+    X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+  }
+  __syncthreads();
+  rl_fft<LH>(X, ptw);
+  // tO_{2p} + i tO_{2p+1} = conj(w_m^{2p} X[p]); the same thread owns positions 2p, 2p+1 in
+  // both parts, so e holds its own tE here
+  for (int p = t; p < h; p += RL_THREADS) {
+    const double2 gz = conj2(cmul(wm(2 * p), X[lpad(p)]));
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int jj = 2 * p + u;
+      if (jj >= len) break;
+      const int32_t r = p2r[jj];
+      if (r < 0) continue;
+      const double cz = e[r] + (u ? gz.y : gz.x) * inv_m;
+      double xv = (double)y[r];
+      if (!isfinite(xv)) xv = 0.0;
+      const double hv = hrow[jj];
+      e[r] = hv - cz;
+      acc.hy += hv * xv;
+      acc.ydh += hv * ydp[jj];
+      acc.yc += xv * cz;
+    }
+  }
+  __syncthreads();
+}
+
+// Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
+__global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__restrict__ items,
+                                                           const int2 *__restrict__ work,
+                                                           int64_t n_work) {
+  extern __shared__ double2 rl_smem[];
+  double2 *X = rl_smem;
+  double *red = (double *)(rl_smem + RL_XN);
+  for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+    const int2 wk = work[wi];
+    const RefItem &it = items[wk.x];
+    const int64_t b = wk.y;
+    RlAcc acc{0, 0, 0, 0};
+    for (int sg = 0; sg < it.n_segs; ++sg) {
+      const SegDev sd = it.segs[sg];
+      switch (sd.log2m - 2) {
+#define TDA_RL(LH) \
+  case LH: rl_segment<LH>(it, sd, b, X, acc); break;
+        TDA_RL(2) TDA_RL(3) TDA_RL(4) TDA_RL(5) TDA_RL(6) TDA_RL(7) TDA_RL(8) TDA_RL(9)
+        TDA_RL(10) TDA_RL(11) TDA_RL(12) TDA_RL(13)
+#undef TDA_RL
+        default: acc.bad = 1.0;
+      }
+    }
+    const double s_hy = block_sum(acc.hy, red), s_ydh = block_sum(acc.ydh, red);
+    const double s_yc = block_sum(acc.yc, red), s_bad = block_sum(acc.bad, red);
+    if (threadIdx.x == 0)
+      it.qpart[b] = s_bad > 0 ? __builtin_nan("") : it.qdd[0] - 2.0 * s_ydh + 2.0 * s_hy - s_yc;
+  }
+}
+
+void register_mixed_attributes() {
+  hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)RL_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_trmm_fwd<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)GP_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_trmm_bwd<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)GP_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_corr<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)GP_LDS_BYTES);
+}
+
+hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
+                             hipStream_t s) {
+  if (n_work <= 0) return hipSuccess;
+  const int64_t g = std::min<int64_t>(n_work, 2048);
+  hipLaunchKernelGGL(k_refine_lds, dim3((unsigned)g), dim3(RL_THREADS), RL_LDS_BYTES, s, items,
+                     work, n_work);
   return hipGetLastError();
 }
 

@@ -387,7 +387,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     g.n_pad = (keep + TB - 1) / TB * TB;
     for (int64_t j = keep; j < g.n_pad; ++j) idx.push_back(-1);
     g.nblk = (int32_t)(g.n_pad / TB);
-    int32_t l2 = 0;
+    int32_t l2 = 4;  // m >= 16: the in-LDS refinement needs m/4 >= 4
     while (((int64_t)1 << l2) < 2 * g.length) ++l2;
     g.log2m = l2;
     g.m = (int64_t)1 << l2;
@@ -666,16 +666,18 @@ static tda_status build_mixed(tda_ctx *h) {
                          (uint16_t *)h->wb_hi.p, (uint16_t *)h->wb_lo.p,
                          (const int64_t *)h->wb_off_d.p, max_k, 0, 0));
   // circulant eigenvalues and twiddles per segment
+  // (per segment: m eigenvalues; m twiddles w_m^r then m/4 pass twiddles, complex)
   int64_t msum = 0;
   for (const Seg &g : h->segs) msum += g.m;
   TDA_TRY(h->alloc(h->lam_d, (size_t)msum * sizeof(double)));
-  TDA_TRY(h->alloc(h->tw_d, (size_t)2 * msum * sizeof(double)));
+  TDA_TRY(h->alloc(h->tw_d, (size_t)2 * (msum + msum / 4) * sizeof(double)));
   h->segdev_h.clear();
   int64_t mo = 0;
   for (const Seg &g : h->segs) {
     double *lam = (double *)h->lam_d.p + mo;
-    double *tw = (double *)h->tw_d.p + 2 * mo;
-    HIP_TRY(launch_lambda((const double *)h->acf_d.p, g.length, g.m, tw, lam, 0));
+    double *tw = (double *)h->tw_d.p + 2 * (mo + mo / 4);
+    double *ptw = tw + 2 * g.m;
+    HIP_TRY(launch_lambda((const double *)h->acf_d.p, g.length, g.m, tw, lam, ptw, 0));
     SegDev sd{};
     sd.offset = g.offset;
     sd.length = g.length;
@@ -686,6 +688,7 @@ static tda_status build_mixed(tda_ctx *h) {
     sd.log2m = g.log2m;
     sd.lam = lam;
     sd.tw = tw;
+    sd.ptw = ptw;
     h->segdev_h.push_back(sd);
     h->max_m = std::max(h->max_m, g.m);
     mo += g.m;
@@ -838,6 +841,8 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
                                 const std::vector<const tda_ctx *> &hs, double *fft_scratch,
                                 int64_t max_m, hipStream_t s) {
   const int64_t n = (int64_t)mis.size();
+  // refinement in LDS when every segment's circulant fits, else paired with global scratch
+  const bool rl = max_m <= RL_MAX_M;
   std::vector<BlockJob> jf, jb;
   std::vector<int4> wr;
   std::vector<int2> wfin;
@@ -845,7 +850,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     if (mis[k].B == 0) continue;
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, false, jf);
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, true, jb);
-    add_refine_pairs((int32_t)k, mis[k].B, wr);
+    if (!rl) add_refine_pairs((int32_t)k, mis[k].B, wr);
     for (int32_t b = 0; b < mis[k].B; ++b) wfin.push_back(int2{(int32_t)k, b});
   }
   const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
@@ -857,7 +862,8 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   HIP_TRY(ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
   HIP_TRY(ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
   HIP_TRY(ring.push(wbk.data(), wbk.size() * sizeof(int4), s, &d_wb));
-  HIP_TRY(ring.push(wr.data(), wr.size() * sizeof(int4), s, &d_wr));
+  d_wr = nullptr;
+  if (!wr.empty()) HIP_TRY(ring.push(wr.data(), wr.size() * sizeof(int4), s, &d_wr));
   HIP_TRY(ring.push(wfin.data(), wfin.size() * sizeof(int2), s, &d_fin));
   const MixItem *dm = (const MixItem *)d_mi;
   // autotuned variant per product kernel, keyed by the largest item's shape
@@ -872,7 +878,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     int64_t nw;
     hipStream_t s;
   };
-  static const int kVariants[2] = {1, 2};
+  static const int kVariants[3] = {1, 2, 3};
   Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
   Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
   int64_t max_chunks = 0;
@@ -882,7 +888,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_h", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
   }
-  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 2, s,
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
@@ -891,7 +897,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("trmm_fwd", s);
     HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
   }
-  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 2, s,
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
@@ -902,14 +908,17 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   }
   {
     TimedScope ts("refine_fft", s);
-    HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
-                          fft_scratch, 2 * max_m, kRefineWG, s));
+    if (rl)
+      HIP_TRY(launch_refine_lds((const RefItem *)d_ri, (const int2 *)d_fin, (int64_t)wfin.size(), s));
+    else
+      HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
+                            fft_scratch, 2 * max_m, kRefineWG, s));
   }
   {
     TimedScope ts("split_e", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
-  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 2, s,
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_corr(x->dm, x->w, x->nw, v, x->s);
@@ -930,7 +939,7 @@ static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int
   if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
   const int64_t Bp = (B + MT - 1) / MT * MT;
   TDA_TRY(h->alloc(h->ws_mix, mix_ws_bytes(h, Bp)));
-  TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
+  if (h->max_m > RL_MAX_M) TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
   const MixWs ws = carve_mix_ws(h, Bp, (char *)h->ws_mix.p);
   std::vector<MixItem> mis{make_mix_item(h, H, ldh, B, Bp, ws, out)};
   std::vector<RefItem> ris{make_ref_item(h, mis[0])};
@@ -1125,7 +1134,7 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
       max_m = std::max(max_m, items[k].h->max_m);
     }
     TDA_TRY(P.alloc(P.ws_mix, total));
-    TDA_TRY(P.alloc(P.ws_fft, (size_t)kRefineWG * max_m * 16));
+    if (max_m > RL_MAX_M) TDA_TRY(P.alloc(P.ws_fft, (size_t)kRefineWG * max_m * 16));
     for (int64_t k = 0; k < n_items; ++k) {
       const tda_work &w = items[k];
       const int64_t Bp = (w.B + MT - 1) / MT * MT;

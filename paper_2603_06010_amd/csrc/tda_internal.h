@@ -87,7 +87,25 @@ struct SegDev {
   int32_t pad0;
   const double *lam;       // [m] circulant eigenvalues
   const double *tw;        // [2m] cos/sin of 2 pi r / m
+  const double *ptw;       // [2 rl_tw_size(log2m - 2)] pass twiddles of the m/4-point DFT
 };
+
+// In-LDS refinement: the m/4-point complex DFTs (h = m/4 <= 2^RL_LHMAX) run in one
+// workgroup's LDS as in-place Stockham passes of radix 2^L (L <= 5).  The pass plan for
+// h = 2^LH: ceil(LH / 5) passes of near-equal radix, larger radices first.
+constexpr int RL_LHMAX = 13;
+constexpr int64_t RL_MAX_M = (int64_t)4 << RL_LHMAX;
+__host__ __device__ constexpr int rl_npass(int LH) { return LH <= 5 ? 1 : (LH + 4) / 5; }
+__host__ __device__ constexpr int rl_L(int LH, int p) {
+  return LH / rl_npass(LH) + (p < LH - (LH / rl_npass(LH)) * rl_npass(LH) ? 1 : 0);
+}
+// log2 of the sub-transform length entering pass p
+__host__ __device__ constexpr int rl_lns(int LH, int p) { return p == 0 ? 0 : rl_lns(LH, p - 1) + rl_L(LH, p - 1); }
+// offset of pass p's twiddles w_{Ns R}^{q k} (q = 1 .. R-1, k < Ns, stored [q-1][k])
+__host__ __device__ constexpr int rl_off(int LH, int p) {
+  return p <= 1 ? 0 : rl_off(LH, p - 1) + (((1 << rl_L(LH, p - 1)) - 1) << rl_lns(LH, p - 1));
+}
+__host__ __device__ constexpr int rl_tw_size(int LH) { return rl_off(LH, rl_npass(LH)); }
 
 struct RefItem {
   const SegDev *segs;
@@ -158,7 +176,7 @@ hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const i
                               int32_t n_pad, int64_t N, const double *d, double *dbar, double *yd,
                               double *yd_pos, double *qdd, hipStream_t s);
 hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
-                         hipStream_t s);
+                         double *ptw, hipStream_t s);
 // from_e = 0: split the gathered templates h; 1: split the FP64 residual e64 (same layout)
 // one launch over all items; max_chunks = max over items of (Bp/32)(n_pad/16) 64
 hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
@@ -188,6 +206,10 @@ void register_mixed_attributes();
 // work entries (item, template a, template b or -1, 0): two templates share one DFT
 hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s);
+// In-LDS refinement for launches whose segments all have m <= RL_MAX_M; work entries
+// (item, template).
+hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
+                             hipStream_t s);
 
 // ---------------------------------------------------------------- internal entry points (tda_api.hip)
 struct MultiCtx;

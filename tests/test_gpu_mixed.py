@@ -160,3 +160,30 @@ def test_plan_graph_replay(tda, precision):
         tda.loglik_multi([(hs[0], ds[0], H, other)], precision=precision)
         torch.cuda.synchronize()
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_scale_invariance(tda, precision):
+    """acf -> s acf with d, H -> sqrt(s) (d, H) leaves the quadratic form unchanged and
+    shifts log det C by N_eff log s; s = 1e-40 puts the inputs at raw strain magnitudes
+    (ACF values near 1e-42), where no input is normalised."""
+    from gpu_util import to_dev
+    inst = synth.random_rhs_case(57, 2500, 1, 1, 48)
+    s = 1e-40
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    h1 = tda.Handle(inst.acf, inst.N, inst.masks[0], precision=precision).factor()
+    h2 = tda.Handle(inst.acf * s, inst.N, inst.masks[0], precision=precision).factor()
+    base = h1.loglik(d, H).cpu().numpy()
+    scaled = h2.loglik(d * np.sqrt(s), H * np.sqrt(s)).cpu().numpy()
+    n_eff = h1.info()["n_eff"]
+    assert abs(h2.info()["logdet"] - h1.info()["logdet"] - n_eff * np.log(s)) < 1e-9 * n_eff * abs(np.log(s))
+    want = base - 0.5 * n_eff * np.log(s)
+    tol = TOL_MIXED if precision == "mixed" else 1e-6 + 2e-9 * np.abs(want)
+    assert np.max(np.abs(scaled - want) - tol) <= 0, np.max(np.abs(scaled - want))
+    # and against the oracle on the scaled inputs
+    f = oracle.factor(inst.acf * s, inst.N, inst.masks[0])
+    ref = oracle.loglik(f, inst.d[0] * np.sqrt(s), inst.H * np.sqrt(s))
+    tol_o = TOL_MIXED if precision == "mixed" else TOLF(ref)
+    assert np.all(np.abs(scaled - ref) <= tol_o), np.max(np.abs(scaled - ref))
+    h1.close()
+    h2.close()
