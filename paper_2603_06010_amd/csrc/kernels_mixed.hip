@@ -45,8 +45,11 @@ __device__ __forceinline__ void split2f(float x, uint16_t &hi, uint16_t &lo) {
   lo = bf16_bits(x - bf16_float(hi));
 }
 
+// Fragment load through a global-address-space pointer (a global_load, not a flat load
+// that would also count against the LDS counter); every operand lives in device memory.
+typedef __attribute__((address_space(1))) const bf8 gbf8;
 __device__ __forceinline__ bf8 load_frag(const uint16_t *p) {
-  return *reinterpret_cast<const bf8 *>(p);
+  return *(gbf8 *)(p);
 }
 
 // ---------------------------------------------------------------- W64 access
@@ -250,6 +253,7 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   const int lane = (int)(chunk & 63);
   const int64_t ks = (chunk >> 6) % nks;
   const int64_t tt = (chunk >> 6) / nks;
+  const int64_t dst = ((tt * it.tks + ks) * 64 + lane) * 8;
   const int64_t b = 32 * tt + (lane & 31);
   const int64_t p0 = 16 * ks + 8 * (lane >> 5);
   uint16_t hi[8], lo[8];
@@ -269,8 +273,8 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
   vl.x = lo[0] | ((uint32_t)lo[1] << 16); vl.y = lo[2] | ((uint32_t)lo[3] << 16);
   vl.z = lo[4] | ((uint32_t)lo[5] << 16); vl.w = lo[6] | ((uint32_t)lo[7] << 16);
-  *reinterpret_cast<uint4 *>(it.hs_hi + chunk * 8) = vh;
-  *reinterpret_cast<uint4 *>(it.hs_lo + chunk * 8) = vl;
+  *reinterpret_cast<uint4 *>(it.hs_hi + dst) = vh;
+  *reinterpret_cast<uint4 *>(it.hs_lo + dst) = vl;
 }
 
 hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
@@ -282,11 +286,19 @@ hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chu
 }
 
 // ---------------------------------------------------------------- BF16x3 products
-// A workgroup (4 waves) computes a 256 x 128 tile of D = A B over K = 16 nks; A and B are
-// given as fragment arrays: A tile t (32 rows) at k-step ks is at A + t s_tile + ks s_ks.
-// Wave w owns A tiles 4 (w/2) .. +4 and B tiles 2 (w%2) .. +2 (a 128 x 64 sub-tile).
-// Fragments go straight from HBM/L2 into registers, one k-step ahead of the matrix
-// cores.  Every product is hi*hi + hi*lo + lo*hi with FP32 accumulation.
+// A workgroup computes a tile of D = A B over K = 16 nks; A and B are given as fragment
+// arrays: A tile t (32 rows) at k-step ks is at A + t s_tile + ks s_ks.  Every product is
+// hi*hi + hi*lo + lo*hi with FP32 accumulation.  Variants (picked per shape by the
+// autotuner):
+//   1: 4 waves, wave tile 4 A x 4 B tiles (128 x 128), workgroup 256 x 256; operands
+//      straight from memory into registers one k-step ahead; one wave per SIMD.
+//   2: 4 waves, wave tile 4 x 2, workgroup 256 x 128 (half a template group); two
+//      workgroups per CU.
+//   3: as 1, with the operands staged through LDS (4 stages of 32 fragments, direct
+//      global -> LDS loads three k-steps ahead).
+//   5: 8 waves, wave tile 4 x 2, workgroup 256 x 256 from a 3-stage LDS ring; two waves
+//      per SIMD hide each other's latency while every fragment is fetched once per
+//      workgroup.
 struct FragSrc {
   const uint16_t *hi, *lo;
   int64_t s_tile, s_ks;  // element strides between tiles and between k-steps
@@ -294,10 +306,22 @@ struct FragSrc {
 
 constexpr int FRAG = 512;  // bf16 elements per fragment (64 lanes x 8)
 
-// Wave tile: 4 A tiles x WB B tiles; workgroup of 4 waves covers 8 A tiles x 2 WB B tiles.
-// WB = 4 (128 x 128 per wave, 256 x 256 per workgroup) maximises operand reuse; WB = 2
-// (128 x 64 per wave) halves the registers so two workgroups fit per CU.  The
-// autotuner picks per shape.
+// Layout of variant V: waves per workgroup, B tiles per wave, whether a workgroup covers
+// a whole group of 256 templates (else half, chosen by the work entry's `sub`), the wave's
+// first A and B tile, and the LDS stages (0: operands go straight to registers).
+template <int V>
+struct PL {
+  static constexpr int NW = V == 5 ? 8 : 4;
+  static constexpr int WB = V == 2 || V == 5 ? 2 : 4;
+  static constexpr bool FULL = V != 2;
+  static constexpr int STAGES = V == 3 ? 4 : V == 5 ? 3 : 0;
+  static constexpr int OCC = V == 2 ? 2 : 1;  // workgroups per CU the registers allow
+  __device__ static int ta(int w) { return NW == 8 ? 4 * (w >> 2) : 4 * (w >> 1); }
+  __device__ static int tb(int w) { return NW == 8 ? 2 * (w & 3) : WB * (w & 1); }
+  // LDS bytes of the operand ring
+  static constexpr size_t lds_bytes() { return (size_t)STAGES * 32 * FRAG * 2; }
+};
+
 template <int WB>
 struct Step {
   bf8 ah[4], al[4], bh[WB], bl[WB];
@@ -340,16 +364,20 @@ __device__ __forceinline__ void mma_step(const Step<WB> &st, f16v (&acc)[4][WB])
   }
 }
 
-// acc[a][b]: A tile 4 (w/2) + a, B tile WB (w%2) + b of the workgroup's operand window
-template <int NPROD, int WB>
-__device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int64_t nks,
-                                      f16v (&acc)[4][WB]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ta = 4 * (w >> 1), tb = WB * (w & 1);
+template <int WB>
+__device__ __forceinline__ void zero_acc(f16v (&acc)[4][WB]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < WB; ++b) acc[a][b] = f16v{};
+}
+
+// Register path (variants 1, 2): one k-step of operands in flight.
+template <int NPROD, int WB>
+__device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int ta, int tb,
+                                      int64_t nks, f16v (&acc)[4][WB]) {
+  const int lane = threadIdx.x & 63;
+  zero_acc<WB>(acc);
   Step<WB> s0, s1;
   if (nks > 0) load_step<NPROD, WB>(A, B, ta, tb, 0, lane, s0);
   int64_t ks = 0;
@@ -362,118 +390,141 @@ __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int64_
   if (ks < nks) mma_step<NPROD, WB>(s0, acc);
 }
 
-// Pipelined variant (WB = 4): operands pass through LDS.  Each k-step's 32 fragments
-// (A hi/lo and B hi/lo, 8 tiles each) are copied global -> LDS by direct loads, one wave
-// per operand array, GP_STAGES - 1 k-steps ahead of the matrix cores; every fragment is
-// fetched once per workgroup and the waves read their tiles with ds_read_b128.
-constexpr int GP_STAGES = 4;
-constexpr int GP_STAGE_BYTES = 32 * FRAG * 2;
-constexpr size_t GP_LDS_BYTES = (size_t)GP_STAGES * GP_STAGE_BYTES;
+// LDS path (variants 3, 5).  A stage holds one k-step's 32 fragments: A hi tiles 0-7,
+// A lo 0-7, B hi 0-7, B lo 0-7 of the workgroup's window.  Wave w copies fragments
+// FPW w .. FPW w + FPW - 1 (FPW = 32 / NW) with direct global -> LDS loads, STAGES - 1
+// k-steps ahead.  Each wave waits for its own copies of a stage, then a barrier makes
+// the whole stage visible; a bare s_barrier is used because a release fence would also
+// wait for the copies of the later stages.
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// wait until at most N vector-memory operations of this wave are outstanding
 template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Workgroup barrier that keeps the direct loads of later stages in flight (a release
-// fence would wait for all of them).  Each wave has already waited for its own copies
-// of the stage it is about to read; the memory clobber keeps LDS accesses on their side.
 __device__ __forceinline__ void gp_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-// this wave's operand array (8 tiles) at k-step ks -> fragments 8 w .. 8 w + 7 of a stage
-__device__ __forceinline__ void gp_issue(const uint16_t *src, int64_t s_tile, int64_t s_ks,
-                                         int64_t ks, char *stage, int w, int lane) {
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const uint16_t *p = src + u * s_tile + ks * s_ks + lane * 8;
-    __builtin_amdgcn_global_load_lds((const void *)p, (lds_void_t *)(stage + (8 * w + u) * 1024),
-                                     16, 0, 0);
-  }
+// The operand array a wave copies (fragments FPW w .. FPW w + FPW - 1 of a stage lie in
+// one array: A hi, A lo, B hi or B lo), resolved once per workgroup.
+struct GpSrc {
+  const uint16_t *p;  // first fragment of this wave's tiles at k-step 0, plus the lane offset
+  int64_t s_tile, s_ks;
+  int f0;             // first stage fragment index of this wave
+};
+
+template <int NW>
+__device__ __forceinline__ GpSrc gp_src(const FragSrc &A, const FragSrc &B, int w, int lane) {
+  constexpr int FPW = 32 / NW;
+  const int f0 = FPW * w, arr = f0 >> 3, tile0 = f0 & 7;
+  const bool isA = arr < 2;
+  const uint16_t *base = arr == 0 ? A.hi : arr == 1 ? A.lo : arr == 2 ? B.hi : B.lo;
+  const int64_t st = isA ? A.s_tile : B.s_tile, sk = isA ? A.s_ks : B.s_ks;
+  return GpSrc{base + tile0 * st + lane * 8, st, sk, f0};
 }
 
-template <int NPROD>
-__device__ __forceinline__ void gemm3_pipe(const FragSrc &A, const FragSrc &B, int64_t nks,
-                                           f16v (&acc)[4][4], char *smem) {
+template <int NW>
+__device__ __forceinline__ void gp_issue(const GpSrc &g, int64_t ks, char *stage) {
+  constexpr int FPW = 32 / NW;
+  const uint16_t *q = g.p + ks * g.s_ks;
+#pragma unroll
+  for (int u = 0; u < FPW; ++u)
+    __builtin_amdgcn_global_load_lds((const void *)(q + u * g.s_tile),
+                                     (lds_void_t *)(stage + (g.f0 + u) * 1024), 16, 0, 0);
+}
+
+template <int NPROD, int V>
+__device__ __forceinline__ void gemm3_lds(const FragSrc &A, const FragSrc &B, int64_t nks,
+                                          f16v (&acc)[4][PL<V>::WB], char *smem) {
+  using L = PL<V>;
+  constexpr int NST = L::STAGES, FPW = 32 / L::NW, SB = 32 * FRAG * 2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ta = 4 * (w >> 1), tb = 4 * (w & 1);
+  const int ta = L::ta(w), tb = L::tb(w);
+  const GpSrc g = gp_src<L::NW>(A, B, w, lane);
+  zero_acc<L::WB>(acc);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f16v{};
-  const uint16_t *src = w == 0 ? A.hi : w == 1 ? A.lo : w == 2 ? B.hi : B.lo;
-  const int64_t s_tile = w < 2 ? A.s_tile : B.s_tile, s_ks = w < 2 ? A.s_ks : B.s_ks;
-#pragma unroll
-  for (int p = 0; p < GP_STAGES - 1; ++p)
-    if (p < nks) gp_issue(src, s_tile, s_ks, p, smem + p * GP_STAGE_BYTES, w, lane);
+  for (int p = 0; p < NST - 1; ++p)
+    if (p < nks) gp_issue<L::NW>(g, p, smem + p * SB);
   for (int64_t t = 0; t < nks; ++t) {
-    const int64_t ahead = nks - 1 - t;  // k-steps issued after t (at most GP_STAGES - 2 here)
-    if (ahead >= 2) wait_vmcnt<16>();
-    else if (ahead == 1) wait_vmcnt<8>();
-    else wait_vmcnt<0>();
+    // this wave's copies issued after stage t: min(nks - 1 - t, NST - 2) stages
+    const int64_t ahead = nks - 1 - t;
+    if constexpr (NST >= 4) {
+      if (ahead >= 2) wait_vmcnt<2 * FPW>();
+      else if (ahead == 1) wait_vmcnt<FPW>();
+      else wait_vmcnt<0>();
+    } else {
+      if (ahead >= 1) wait_vmcnt<FPW>();
+      else wait_vmcnt<0>();
+    }
     gp_barrier();  // stage t complete for every wave; stage t - 1 no longer read
-    if (t + GP_STAGES - 1 < nks)
-      gp_issue(src, s_tile, s_ks, t + GP_STAGES - 1,
-               smem + ((t + GP_STAGES - 1) % GP_STAGES) * GP_STAGE_BYTES, w, lane);
-    const bf8 *S = (const bf8 *)(smem + (t % GP_STAGES) * GP_STAGE_BYTES);
-    Step<4> st;
+    if (t + NST - 1 < nks)
+      gp_issue<L::NW>(g, t + NST - 1, smem + ((t + NST - 1) % NST) * SB);
+    const bf8 *S = (const bf8 *)(smem + (t % NST) * SB);
+    Step<L::WB> st;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       st.ah[a] = S[(ta + a) * 64 + lane];
       st.al[a] = S[(8 + ta + a) * 64 + lane];
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < L::WB; ++b) {
       st.bh[b] = S[(16 + tb + b) * 64 + lane];
       st.bl[b] = S[(24 + tb + b) * 64 + lane];
     }
-    mma_step<NPROD, 4>(st, acc);
+    mma_step<NPROD, L::WB>(st, acc);
   }
 }
 
-// Work entries (item, block, group of 256 templates, sub): WB = 2 workgroups take the
-// B half `sub`; WB = 4 workgroups cover both halves at sub = 0 and skip sub = 1.
+template <int NPROD, int V>
+__device__ __forceinline__ void gemm3_v(const FragSrc &A, const FragSrc &B, int64_t nks,
+                                        f16v (&acc)[4][PL<V>::WB]) {
+  using L = PL<V>;
+  if constexpr (L::STAGES > 0) {
+    extern __shared__ char gp_smem[];
+    gemm3_lds<NPROD, V>(A, B, nks, acc, gp_smem);
+  } else {
+    const int w = threadIdx.x >> 6;
+    gemm3<NPROD, L::WB>(A, B, L::ta(w), L::tb(w), nks, acc);
+  }
+}
+
+// Work entries (item, block, group of 256 templates, sub): half-group variants take the
+// half `sub`; full-group variants cover both halves at sub = 0 and skip sub = 1.
 
 // w0 = W h: rows of row block i (A = F(W)), templates of the group (B = F(Hs)); w0 is
 // written in F(w0^T).
-template <int WB, bool PIPE = false>
-__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem *__restrict__ items,
-                                                                  const int4 *__restrict__ work) {
+template <int V>
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_fwd(
+    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  using L = PL<V>;
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (WB == 4 && wk.w)) return;
+  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
   const int i = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int bf = it.blk_first[i];
   const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
-  const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
-  const int64_t T0 = (int64_t)wk.z * 8 + (WB == 2 ? 4 * wk.w : 0);
+  const int64_t T0 = (int64_t)wk.z * 8 + (L::FULL ? 0 : 4 * wk.w);
   const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
-  const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
-                  nks_all * FRAG, FRAG};
-  f16v acc[4][WB];
-  if constexpr (PIPE) {
-    extern __shared__ char gp_smem[];
-    gemm3_pipe<3>(A, B, nks, acc, gp_smem);
-  } else {
-    gemm3<3, WB>(A, B, nks, acc);
-  }
+  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0) * FRAG, it.hs_lo + (T0 * it.tks + ks0) * FRAG,
+                  it.tks * FRAG, FRAG};
+  f16v acc[4][L::WB];
+  gemm3_v<3, V>(A, B, nks, acc);
   // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8), pos p%8
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int64_t rt_row = (int64_t)i * TB + 32 * (4 * (w >> 1) + a);
+    const int64_t rt_row = (int64_t)i * TB + 32 * (L::ta(w) + a);
 #pragma unroll
-    for (int b = 0; b < WB; ++b) {
-      const int64_t T = T0 + WB * (w & 1) + b;
+    for (int b = 0; b < L::WB; ++b) {
+      const int64_t T = T0 + L::tb(w) + b;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int64_t base = rt_row + 8 * g;
         const int64_t ks = base >> 4;
         const int lp = (lane & 31) + 32 * (g & 1);
-        const int64_t dst = ((T * nks_all + ks) * 64 + lp) * 8 + 4 * (lane >> 5);
+        const int64_t dst = ((T * it.tks + ks) * 64 + lp) * 8 + 4 * (lane >> 5);
         uint16_t h4[4], l4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) split2f(acc[a][b][4 * g + v], h4[v], l4[v]);
@@ -488,38 +539,34 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_fwd(const MixItem
 }
 
 // y0^T = w0^T W over column block j (K = rows [j TB, (last_j + 1) TB)): A = F(w0^T)
-// (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for WB = 2).
-template <int WB, bool PIPE = false>
-__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem *__restrict__ items,
-                                                                  const int4 *__restrict__ work) {
+// (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for the
+// half-group variant).
+template <int V>
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_bwd(
+    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  using L = PL<V>;
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (WB == 4 && wk.w)) return;
+  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
   const int j = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int last = it.blk_last[j];
   const int64_t nks = (int64_t)(last + 1 - j) * (TB / 16);
-  const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)j * (TB / 16);
   const int64_t T0 = (int64_t)wk.z * 8;
-  const int st0 = WB == 2 ? 4 * wk.w : 0;
-  const FragSrc A{it.w0_hi + (T0 * nks_all + ks0) * FRAG, it.w0_lo + (T0 * nks_all + ks0) * FRAG,
-                  nks_all * FRAG, FRAG};
+  const int st0 = L::FULL ? 0 : 4 * wk.w;
+  const FragSrc A{it.w0_hi + (T0 * it.tks + ks0) * FRAG, it.w0_lo + (T0 * it.tks + ks0) * FRAG,
+                  it.tks * FRAG, FRAG};
   const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG,
                   it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG, FRAG, 8 * FRAG};
-  f16v acc[4][WB];
-  if constexpr (PIPE) {
-    extern __shared__ char gp_smem[];
-    gemm3_pipe<3>(A, B, nks, acc, gp_smem);
-  } else {
-    gemm3<3, WB>(A, B, nks, acc);
-  }
+  f16v acc[4][L::WB];
+  gemm3_v<3, V>(A, B, nks, acc);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int64_t trow0 = 32 * (T0 + 4 * (w >> 1) + a);
+    const int64_t trow0 = 32 * (T0 + L::ta(w) + a);
 #pragma unroll
-    for (int b = 0; b < WB; ++b) {
-      const int64_t col = (int64_t)j * TB + 32 * (st0 + WB * (w & 1) + b) + (lane & 31);
+    for (int b = 0; b < L::WB; ++b) {
+      const int64_t col = (int64_t)j * TB + 32 * (st0 + L::tb(w) + b) + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int64_t trow = trow0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -534,47 +581,42 @@ __global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_trmm_bwd(const MixItem
 // 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  CORR_PROD selects
 // 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
 constexpr int CORR_PROD = 3;
-template <int WB, bool PIPE = false>
-__global__ __launch_bounds__(256, WB == 4 ? 1 : 2) void k_corr(const MixItem *__restrict__ items,
-                                                              const int4 *__restrict__ work) {
+template <int V>
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
+    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  using L = PL<V>;
   __shared__ double red[2][256];
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (WB == 4 && wk.w)) return;
+  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
   const int i = wk.y;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int bf = it.blk_first[i];
   const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
-  const int64_t nks_all = it.n_pad / 16;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
-  const int64_t T0 = (int64_t)wk.z * 8 + (WB == 2 ? 4 * wk.w : 0);
+  const int64_t T0 = (int64_t)wk.z * 8 + (L::FULL ? 0 : 4 * wk.w);
   const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
-  const FragSrc B{it.hs_hi + (T0 * nks_all + ks0) * FRAG, it.hs_lo + (T0 * nks_all + ks0) * FRAG,
-                  nks_all * FRAG, FRAG};
-  f16v acc[4][WB];
-  if constexpr (PIPE) {
-    extern __shared__ char gp_smem[];
-    gemm3_pipe<CORR_PROD>(A, B, nks, acc, gp_smem);
-  } else {
-    gemm3<CORR_PROD, WB>(A, B, nks, acc);
-  }
+  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0) * FRAG, it.hs_lo + (T0 * it.tks + ks0) * FRAG,
+                  it.tks * FRAG, FRAG};
+  f16v acc[4][L::WB];
+  gemm3_v<CORR_PROD, V>(A, B, nks, acc);
+  // per column: sum of squares over the wave's 128 rows; the two row halves of the
+  // workgroup meet in LDS
 #pragma unroll
-  for (int b = 0; b < WB; ++b) {
+  for (int b = 0; b < L::WB; ++b) {
     double ss = 0.0;
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int r = 0; r < 16; ++r) ss += (double)acc[a][b][r] * (double)acc[a][b][r];
     ss += __shfl_xor(ss, 32);  // lanes l and l+32 hold other rows of the same column
-    const int col = 32 * (WB * (w & 1) + b) + (lane & 31);
-    if (lane < 32) red[w >> 1][col] = ss;
+    const int col = 32 * (L::tb(w) + b) + (lane & 31);
+    if (lane < 32) red[L::ta(w) >> 2][col] = ss;
   }
   __syncthreads();
-  const int ncol = 64 * WB;
-  if ((int)threadIdx.x < ncol) {
-    const int col = threadIdx.x;
+  const int ncol = L::FULL ? 256 : 128;
+  for (int col = threadIdx.x; col < ncol; col += 64 * L::NW)
     it.corr_part[(int64_t)i * it.Bp + T0 * 32 + col] = red[0][col] + red[1][col];
-  }
 }
 
 // out[b] = -1/2 (qpart[b] + sum_i corr_part[i][b]) + cterm; entries (item, b)
@@ -590,17 +632,25 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
   it.out[b] = -0.5 * (it.qpart[b] + c) + it.cterm;
 }
 
-// variant 1: 128 x 128 wave tiles (WB = 4); variant 2: 128 x 64 wave tiles (WB = 2);
-// variant 3: WB = 4 with operands staged through LDS
 #define TDA_LAUNCH_VARIANT(K)                                                                 \
   if (n_work <= 0) return hipSuccess;                                                        \
-  if (variant == 2)                                                                          \
-    hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
-  else if (variant == 3)                                                                     \
-    hipLaunchKernelGGL((K<4, true>), dim3((unsigned)n_work), dim3(256), GP_LDS_BYTES, s,     \
-                       items, work);                                                         \
-  else                                                                                       \
-    hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);           \
+  switch (variant) {                                                                         \
+    case 2:                                                                                  \
+      hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(64 * PL<2>::NW), 0, s, items,     \
+                         work);                                                              \
+      break;                                                                                 \
+    case 3:                                                                                  \
+      hipLaunchKernelGGL(K<3>, dim3((unsigned)n_work), dim3(64 * PL<3>::NW),                  \
+                         PL<3>::lds_bytes(), s, items, work);                                \
+      break;                                                                                 \
+    case 5:                                                                                  \
+      hipLaunchKernelGGL(K<5>, dim3((unsigned)n_work), dim3(64 * PL<5>::NW),                  \
+                         PL<5>::lds_bytes(), s, items, work);                                \
+      break;                                                                                 \
+    default:                                                                                 \
+      hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(64 * PL<1>::NW), 0, s, items,     \
+                         work);                                                              \
+  }                                                                                          \
   return hipGetLastError();
 
 hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
@@ -993,47 +1043,57 @@ __device__ __forceinline__ void dft_small(double2 (&v)[1 << L]) {
 }
 
 // Pass P of the h = 2^LH point forward DFT: radix R = 2^L over sub-transforms of length
-// Ns = 2^LNS; thread j < h/R loads X[j + q h/R], twiddles by w_{Ns R}^{q (j mod Ns)},
+// Ns = 2^LNS.  Sub-transform j < h/R loads X[j + q h/R], twiddles by w_{Ns R}^{q (j mod Ns)},
 // transforms, and stores to X[(j div Ns) Ns R + j mod Ns + q Ns] (natural order at the end).
+// Thread t takes j = t + RL_THREADS g, g < G; every element is read into registers before
+// any is written back, so the pass works in place.
 template <int LH, int P>
 __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ ptw) {
   constexpr int L = rl_L(LH, P), LNS = rl_lns(LH, P), OFF = rl_off(LH, P);
   constexpr int R = 1 << L, NS = 1 << LNS, NT = 1 << (LH - L);
-  static_assert(NT <= RL_THREADS, "pass needs more threads than the workgroup has");
-  const int j = threadIdx.x;
-  const bool act = j < NT;
-  const int k = j & (NS - 1);
-  double2 a[R];
+  constexpr int G = NT > RL_THREADS ? NT / RL_THREADS : 1;
+  constexpr int NTA = NT > RL_THREADS ? RL_THREADS : NT;
+  const int t = threadIdx.x;
+  const bool act = t < NTA;
+  double2 a[G][R];
   if (act) {
-    // strides that are multiples of 16 keep the padded addresses at constant offsets
-    if constexpr (NT % 16 == 0) {
-      const double2 *x0 = X + lpad(j);
 #pragma unroll
-      for (int q = 0; q < R; ++q) a[q] = x0[q * (NT + NT / 16)];
-    } else {
+    for (int g = 0; g < G; ++g) {
+      const int j = t + RL_THREADS * g, k = j & (NS - 1);
+      // strides that are multiples of 16 keep the padded addresses at constant offsets
+      if constexpr (NT % 16 == 0) {
+        const double2 *x0 = X + lpad(j);
 #pragma unroll
-      for (int q = 0; q < R; ++q) a[q] = X[lpad(j + q * NT)];
+        for (int q = 0; q < R; ++q) a[g][q] = x0[q * (NT + NT / 16)];
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[g][q] = X[lpad(j + q * NT)];
+      }
+      if constexpr (LNS > 0) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) a[g][q] = cmul(a[g][q], ptw[OFF + (q - 1) * NS + k]);
+      }
+      dft_small<L>(a[g]);
     }
-    if constexpr (LNS > 0) {
-#pragma unroll
-      for (int q = 1; q < R; ++q) a[q] = cmul(a[q], ptw[OFF + (q - 1) * NS + k]);
-    }
-    dft_small<L>(a);
   }
   __syncthreads();
   if (act) {
-    const int base = ((j >> LNS) << (LNS + L)) + k;
-    if constexpr (NS % 16 == 0) {
-      double2 *x0 = X + lpad(base);
 #pragma unroll
-      for (int q = 0; q < R; ++q) x0[q * (NS + NS / 16)] = a[brev_c(q, L)];
-    } else if constexpr (NS == 1 && R % 16 == 0) {
-      double2 *x0 = X + lpad(base);  // base = j R, a multiple of 16
+    for (int g = 0; g < G; ++g) {
+      const int j = t + RL_THREADS * g, k = j & (NS - 1);
+      const int base = ((j >> LNS) << (LNS + L)) + k;
+      if constexpr (NS % 16 == 0) {
+        double2 *x0 = X + lpad(base);
 #pragma unroll
-      for (int q = 0; q < R; ++q) x0[q + (q >> 4)] = a[brev_c(q, L)];
-    } else {
+        for (int q = 0; q < R; ++q) x0[q * (NS + NS / 16)] = a[g][brev_c(q, L)];
+      } else if constexpr (NS == 1 && R % 16 == 0) {
+        double2 *x0 = X + lpad(base);  // base = j R, a multiple of 16
 #pragma unroll
-      for (int q = 0; q < R; ++q) X[lpad(base + q * NS)] = a[brev_c(q, L)];
+        for (int q = 0; q < R; ++q) x0[q + (q >> 4)] = a[g][brev_c(q, L)];
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) X[lpad(base + q * NS)] = a[g][brev_c(q, L)];
+      }
     }
   }
   __syncthreads();
@@ -1041,115 +1101,232 @@ __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ 
 
 template <int LH>
 __device__ __forceinline__ void rl_fft(double2 *X, const double2 *ptw) {
+  static_assert(rl_npass(LH) <= 4, "at most four passes");
   rl_pass<LH, 0>(X, ptw);
   if constexpr (rl_npass(LH) > 1) rl_pass<LH, 1>(X, ptw);
   if constexpr (rl_npass(LH) > 2) rl_pass<LH, 2>(X, ptw);
+  if constexpr (rl_npass(LH) > 3) rl_pass<LH, 3>(X, ptw);
 }
 
 struct RlAcc {
   double hy, ydh, yc, bad;
 };
 
+// Element-wise phases: a thread handles positions p = t + RL_THREADS i (samples 2p and
+// 2p + 1) or frequency pairs k = t + RL_THREADS i.  Every global access of a chunk of
+// RL_CH iterations is issued before any of its values is used, so the loads of a chunk
+// are in flight together (stores to e would otherwise keep later loads from being
+// hoisted).  Segments without excluded samples compute rows instead of loading them.
+constexpr int RL_CH = 4;
+
 template <int LH>
-__device__ void rl_segment(const RefItem &it, const SegDev &sd, int64_t b, double2 *X,
+__device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int64_t b, double2 *X,
                            RlAcc &acc) {
   constexpr int h = 1 << LH;
+  constexpr int NI = h >= RL_THREADS ? h / RL_THREADS : 1;         // position iterations
+  constexpr int NKE = (h / 2 + RL_THREADS) / RL_THREADS;           // k = 0 .. h/2
+  constexpr int NKO = h / 2 >= RL_THREADS ? h / 2 / RL_THREADS : 1; // k = 0 .. h/2 - 1
   const int t = threadIdx.x;
-  const float *y = it.y0 + b * it.n_pad;
-  const double *hrow = template_row(it, b) + sd.offset;
-  const double *ydp = it.yd_pos + sd.offset;
-  const int32_t *p2r = it.pos2row + sd.offset;
-  double *e = it.e64 + b * it.n_pad;
-  const double2 *tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
-  const double2 *ptw = (const double2 *)sd.ptw;
-  const double *lam = sd.lam;
+  const float *__restrict__ y = it.y0 + b * it.n_pad;
+  const double *__restrict__ hrow = template_row(it, b) + sd.offset;
+  const double *__restrict__ ydp = it.yd_pos + sd.offset;
+  const int32_t *__restrict__ p2r = it.pos2row + sd.offset;
+  double *__restrict__ e = it.e64 + b * it.n_pad;
+  const double2 *__restrict__ tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
+  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
+  const double *__restrict__ lam = sd.lam;
   const int len = (int)sd.length;
+  const bool dense = sd.nkeep == sd.length;
+  const int32_t row0 = (int32_t)sd.row0;
   const double inv_m = 1.0 / (double)(4 * h);
   auto wm = [&](int r) {  // w_m^r, 0 <= r < m
     const double2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
-  auto xat = [&](int jj) -> double {
-    if (jj >= len) return 0.0;
-    const int32_t r = p2r[jj];
-    if (r < 0) return 0.0;
-    const double v = (double)y[r];
+  // padded row of sample jj of the segment; -1 if excluded or beyond the segment
+  auto row_of = [&](int jj) -> int32_t {
+    if (jj >= len) return -1;
+    return dense ? row0 + jj : p2r[jj];
+  };
+  auto finite_or_flag = [&](float v) -> double {
     if (!isfinite(v)) {
       acc.bad = 1.0;
       return 0.0;
     }
-    return v;
+    return (double)v;
   };
+  // rows and y0 values of the samples 2p, 2p + 1 of chunk i0
+  auto load_x = [&](int i0, int32_t (&rr)[RL_CH][2], float (&xv)[RL_CH][2]) {
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      const bool in = i0 + c < NI && p < h;
+      rr[c][0] = in ? row_of(2 * p) : -1;
+      rr[c][1] = in ? row_of(2 * p + 1) : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) xv[c][u] = rr[c][u] >= 0 ? y[rr[c][u]] : 0.f;
+  };
+
   for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
 
   // ---- even frequencies: circulant part
-  for (int p = t; p < h; p += RL_THREADS) X[lpad(p)] = make_double2(xat(2 * p), xat(2 * p + 1));
+  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+    int32_t rr[RL_CH][2];
+    float xv[RL_CH][2];
+    load_x(i0, rr, xv);
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NI && p < h)
+        X[lpad(p)] = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
+    }
+  }
   __syncthreads();
   rl_fft<LH>(X, ptw);
-  for (int k = t; k <= h / 2; k += RL_THREADS) {
-    const int kr = (h - k) & (h - 1);
-    const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-    // spectra of the even- and odd-indexed samples: E = (vk + conj vr)/2, O = -i (vk - conj vr)/2
-    const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-    const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-    const double2 c = wm(2 * k);  // w_{n'}^k
-    const double2 cO = cmul(c, O);
-    const double2 yk = scal(lam[2 * k], cadd(E, cO));
-    const double2 yr = scal(lam[2 * h - 2 * k], conj2(csub(E, cO)));
-    const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
-    X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(c), op))));
-    if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(c, conj2(op)))));
+  for (int i0 = 0; i0 < NKE; i0 += RL_CH) {
+    double la[RL_CH], lb[RL_CH];
+    double2 cc[RL_CH];
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NKE && k <= h / 2) {
+        la[c] = lam[2 * k];
+        lb[c] = lam[2 * h - 2 * k];
+        cc[c] = wm(2 * k);  // w_{n'}^k
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NKE && k <= h / 2)) continue;
+      const int kr = (h - k) & (h - 1);
+      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+      // spectra of the even- and odd-indexed samples: E = (vk + conj vr)/2, O = -i (vk - conj vr)/2
+      const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+      const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+      const double2 cO = cmul(cc[c], O);
+      const double2 yk = scal(la[c], cadd(E, cO));
+      const double2 yr = scal(lb[c], conj2(csub(E, cO)));
+      const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
+      X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(cc[c]), op))));
+      if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(cc[c], conj2(op)))));
+    }
   }
   __syncthreads();
   rl_fft<LH>(X, ptw);
   // tE_{2p} + i tE_{2p+1} = conj(X[p]); kept (scaled) in e until the odd part adds to it
-  for (int p = t; p < h; p += RL_THREADS) {
-    const double2 v = X[lpad(p)];
-    const int j0 = 2 * p;
-    if (j0 < len && p2r[j0] >= 0) e[p2r[j0]] = v.x * inv_m;
-    if (j0 + 1 < len && p2r[j0 + 1] >= 0) e[p2r[j0 + 1]] = -v.y * inv_m;
+  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+    int32_t rr[RL_CH][2];
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      const bool in = i0 + c < NI && p < h;
+      rr[c][0] = in ? row_of(2 * p) : -1;
+      rr[c][1] = in ? row_of(2 * p + 1) : -1;
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NI && p < h)) continue;
+      const double2 v = X[lpad(p)];
+      if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
+      if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
+    }
   }
   __syncthreads();
 
   // ---- odd frequencies: skew-circulant part
-  for (int p = t; p < h; p += RL_THREADS)
-    X[lpad(p)] = cmul(make_double2(xat(2 * p), xat(2 * p + 1)), wm(2 * p));
+  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+    int32_t rr[RL_CH][2];
+    float xv[RL_CH][2];
+    double2 wp[RL_CH];
+    load_x(i0, rr, xv);
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NI && p < h) wp[c] = wm(2 * p);
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NI && p < h)
+        X[lpad(p)] = cmul(make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1])), wp[c]);
+    }
+  }
   __syncthreads();
   rl_fft<LH>(X, ptw);
   const double2 om = wm(1);
-  for (int k = t; k < h / 2; k += RL_THREADS) {
-    const int kr = h - 1 - k;
-    const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-    const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-    const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-    const double2 dB = cmul(wm(2 * k + 1), B);
-    const double2 yk = scal(lam[2 * k + 1], cadd(A, dB));          // X_{2k+1}
-    const double2 ykh = scal(lam[2 * k + 2 * h + 1], csub(A, dB));  // X_{2k+2h+1}
-    const double2 P = cadd(yk, ykh);
-    const double2 Q = cmul(conj2(wm(2 * k)), csub(yk, ykh));
-    X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
-    X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+  for (int i0 = 0; i0 < NKO; i0 += RL_CH) {
+    double la[RL_CH], lb[RL_CH];
+    double2 dd[RL_CH], cc[RL_CH];
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NKO && k < h / 2) {
+        la[c] = lam[2 * k + 1];
+        lb[c] = lam[2 * k + 2 * h + 1];
+        dd[c] = wm(2 * k + 1);
+        cc[c] = wm(2 * k);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NKO && k < h / 2)) continue;
+      const int kr = h - 1 - k;
+      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+      const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+      const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+      const double2 dB = cmul(dd[c], B);
+      const double2 yk = scal(la[c], cadd(A, dB));   // X_{2k+1}
+      const double2 ykh = scal(lb[c], csub(A, dB));  // X_{2k+2h+1}
+      const double2 P = cadd(yk, ykh);
+      const double2 Q = cmul(conj2(cc[c]), csub(yk, ykh));
+      X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
+      X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+    }
   }
   __syncthreads();
   rl_fft<LH>(X, ptw);
   // tO_{2p} + i tO_{2p+1} = conj(w_m^{2p} X[p]); the same thread owns positions 2p, 2p+1 in
   // both parts, so e holds its own tE here
-  for (int p = t; p < h; p += RL_THREADS) {
-    const double2 gz = conj2(cmul(wm(2 * p), X[lpad(p)]));
+  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+    int32_t rr[RL_CH][2];
+    float xv[RL_CH][2];
+    double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
+    double2 wp[RL_CH];
+    load_x(i0, rr, xv);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int jj = 2 * p + u;
-      if (jj >= len) break;
-      const int32_t r = p2r[jj];
-      if (r < 0) continue;
-      const double cz = e[r] + (u ? gz.y : gz.x) * inv_m;
-      double xv = (double)y[r];
-      if (!isfinite(xv)) xv = 0.0;
-      const double hv = hrow[jj];
-      e[r] = hv - cz;
-      acc.hy += hv * xv;
-      acc.ydh += hv * ydp[jj];
-      acc.yc += xv * cz;
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NI && p < h)) continue;
+      wp[c] = wm(2 * p);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int jj = 2 * p + u;
+        ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
+        hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
+        yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int p = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NI && p < h)) continue;
+      const double2 gz = conj2(cmul(wp[c], X[lpad(p)]));
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (rr[c][u] < 0) continue;
+        const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
+        const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
+        e[rr[c][u]] = hv[c][u] - cz;
+        acc.hy += hv[c][u] * xd;
+        acc.ydh += hv[c][u] * yv[c][u];
+        acc.yc += xd * cz;
+      }
     }
   }
   __syncthreads();
@@ -1188,12 +1365,18 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
 void register_mixed_attributes() {
   hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)RL_LDS_BYTES);
-  hipFuncSetAttribute((const void *)k_trmm_fwd<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)GP_LDS_BYTES);
-  hipFuncSetAttribute((const void *)k_trmm_bwd<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)GP_LDS_BYTES);
-  hipFuncSetAttribute((const void *)k_corr<4, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)GP_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_trmm_fwd<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<3>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_trmm_bwd<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<3>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_corr<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<3>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_trmm_fwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_trmm_bwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_corr<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
 }
 
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,

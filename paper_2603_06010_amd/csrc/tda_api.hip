@@ -583,20 +583,53 @@ struct BlockJob {
   int64_t k;  // work weight (K of the block)
 };
 
+// Product work order.  Workgroup g runs on XCD g mod 8, and each XCD has its own L2, so
+// the list is built per XCD and interleaved.  Work is cut into super-tiles of kRB
+// consecutive blocks of one item x kTG template groups: the ~32 workgroups an XCD runs
+// at once then share each template k-step among kRB blocks and each operator block
+// among kTG groups in L2, instead of re-reading the templates for every block.
+// Super-tiles go to the XCD with the least work so far, longest first.
+constexpr int kRB = 4, kTG = 8;
 std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
   constexpr int NX = 8;
-  std::vector<std::vector<BlockJob>> q(NX);
-  for (size_t n = 0; n < jobs.size(); ++n) q[n % NX].push_back(jobs[n]);
-  std::vector<std::vector<int4>> lists(NX);
-  size_t longest = 0;
-  for (int x = 0; x < NX; ++x) {
-    std::stable_sort(q[x].begin(), q[x].end(),
-                     [](const BlockJob &a, const BlockJob &b) { return a.k > b.k; });
-    for (const BlockJob &j : q[x])
-      for (int t = 0; t < j.ntg; ++t)
-        for (int u = 0; u < j.nsub; ++u) lists[x].push_back(int4{j.item, j.block, t, u});
-    longest = std::max(longest, lists[x].size());
+  struct Tile {
+    int64_t work;
+    std::vector<int4> wg;
+  };
+  std::vector<Tile> tiles;
+  size_t n = 0;
+  while (n < jobs.size()) {
+    // a run of consecutive blocks of one item
+    size_t e = n;
+    while (e < jobs.size() && e - n < (size_t)kRB && jobs[e].item == jobs[n].item) ++e;
+    const int32_t ntg = jobs[n].ntg, nsub = jobs[n].nsub;
+    // fewer blocks in the run (end of an item): more groups, about 32 workgroups per tile
+    const int32_t tg = std::min<int32_t>(ntg, std::max<int32_t>(kTG, 32 / (int32_t)(e - n)));
+    for (int32_t t0 = 0; t0 < ntg; t0 += tg) {
+      Tile T{0, {}};
+      for (int32_t t = t0; t < std::min(ntg, t0 + tg); ++t)
+        for (size_t q = n; q < e; ++q)
+          for (int32_t u = 0; u < nsub; ++u) {
+            T.wg.push_back(int4{jobs[q].item, jobs[q].block, t, u});
+            T.work += jobs[q].k;
+          }
+      tiles.push_back(std::move(T));
+    }
+    n = e;
   }
+  std::stable_sort(tiles.begin(), tiles.end(),
+                   [](const Tile &x, const Tile &y) { return x.work > y.work; });
+  std::vector<std::vector<int4>> lists(NX);
+  int64_t load[NX] = {};
+  for (Tile &T : tiles) {
+    int x = 0;
+    for (int c = 1; c < NX; ++c)
+      if (load[c] < load[x]) x = c;
+    load[x] += T.work;
+    lists[x].insert(lists[x].end(), T.wg.begin(), T.wg.end());
+  }
+  size_t longest = 0;
+  for (int x = 0; x < NX; ++x) longest = std::max(longest, lists[x].size());
   std::vector<int4> out(longest * NX, int4{0, -1, 0, 0});
   for (int x = 0; x < NX; ++x)
     for (size_t k = 0; k < lists[x].size(); ++k) out[k * NX + x] = lists[x][k];
@@ -742,23 +775,29 @@ struct MixWs {
 };
 
 // Bytes of workspace one mixed item needs for Bp templates.
+// fragments per template tile of the split layouts
+static int64_t tile_ksteps(const tda_ctx *h) { return h->n_pad / 16 + TKS_PAD; }
+
 static size_t mix_ws_bytes(const tda_ctx *h, int64_t Bp) {
   const size_t el = (size_t)Bp * h->n_pad;
-  return el * (2 + 2 + 2 + 2 + 4 + 8) + (size_t)Bp * 8 + (size_t)h->nblk * Bp * 8 + 6 * 256;
+  const size_t el_t = (size_t)(Bp / 32) * tile_ksteps(h) * 512;  // split layouts
+  return el_t * (2 + 2 + 2 + 2) + el * (4 + 8) + (size_t)Bp * 8 + (size_t)h->nblk * Bp * 8 +
+         6 * 256;
 }
 
 static MixWs carve_mix_ws(const tda_ctx *h, int64_t Bp, char *base) {
   const size_t el = (size_t)Bp * h->n_pad;
+  const size_t el_t = (size_t)(Bp / 32) * tile_ksteps(h) * 512;
   auto take = [&](size_t bytes) {
     char *p = base;
     base += (bytes + 255) & ~(size_t)255;
     return p;
   };
   MixWs w;
-  w.hs_hi = (uint16_t *)take(el * 2);
-  w.hs_lo = (uint16_t *)take(el * 2);
-  w.w0_hi = (uint16_t *)take(el * 2);
-  w.w0_lo = (uint16_t *)take(el * 2);
+  w.hs_hi = (uint16_t *)take(el_t * 2);
+  w.hs_lo = (uint16_t *)take(el_t * 2);
+  w.w0_hi = (uint16_t *)take(el_t * 2);
+  w.w0_lo = (uint16_t *)take(el_t * 2);
   w.y0 = (float *)take(el * 4);
   w.e64 = (double *)take(el * 8);
   w.qpart = (double *)take((size_t)Bp * 8);
@@ -794,6 +833,7 @@ static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int
   mi.Bp = (int32_t)Bp;
   mi.nblk = h->nblk;
   mi.n_pad = (int32_t)h->n_pad;
+  mi.tks = tile_ksteps(h);
   return mi;
 }
 
@@ -832,6 +872,17 @@ static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, bool tran
                                  : (int64_t)(i + 1 - h->blk_first_h[i]);
     jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), 2, k});
   }
+}
+
+// timing names carry the product variant the autotuner picked ("trmm_fwd/v2")
+static const char *const kTrmmFwdNames[] = {"trmm_fwd",    "trmm_fwd/v1", "trmm_fwd/v2",
+                                            "trmm_fwd/v3", "trmm_fwd/v4", "trmm_fwd/v5"};
+static const char *const kTrmmBwdNames[] = {"trmm_bwd",    "trmm_bwd/v1", "trmm_bwd/v2",
+                                            "trmm_bwd/v3", "trmm_bwd/v4", "trmm_bwd/v5"};
+static const char *const kTrmmCorrNames[] = {"trmm_corr",    "trmm_corr/v1", "trmm_corr/v2",
+                                             "trmm_corr/v3", "trmm_corr/v4", "trmm_corr/v5"};
+static const char *variant_name(const char *const *names, int v) {
+  return v >= 1 && v <= 5 ? names[v] : names[0];
 }
 
 // The mixed launch sequence over a set of items whose MixItem/RefItem descriptors are
@@ -878,7 +929,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     int64_t nw;
     hipStream_t s;
   };
-  static const int kVariants[3] = {1, 2, 3};
+  static const int kVariants[4] = {1, 2, 3, 5};
   Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
   Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
   int64_t max_chunks = 0;
@@ -888,22 +939,22 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_h", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
   }
-  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 3, s,
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
                                }, &cf);
   {
-    TimedScope ts("trmm_fwd", s);
+    TimedScope ts(variant_name(kTrmmFwdNames, vf), s);
     HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
   }
-  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 3, s,
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
                                }, &cb);
   {
-    TimedScope ts("trmm_bwd", s);
+    TimedScope ts(variant_name(kTrmmBwdNames, vb), s);
     HIP_TRY(launch_trmm_bwd(dm, (const int4 *)d_wb, (int64_t)wbk.size(), vb, s));
   }
   {
@@ -918,13 +969,13 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_e", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
-  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 3, s,
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_corr(x->dm, x->w, x->nw, v, x->s);
                                }, &cf);
   {
-    TimedScope ts("trmm_corr", s);
+    TimedScope ts(variant_name(kTrmmCorrNames, vc), s);
     HIP_TRY(launch_corr(dm, (const int4 *)d_wf, (int64_t)wf.size(), vc, s));
   }
   {

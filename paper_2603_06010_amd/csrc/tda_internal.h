@@ -63,8 +63,9 @@ struct MixItem {
   const double *H;
   int64_t ldh;
   const double *const *Hrows;      // optional per-template row pointers
-  uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][n_pad/16][64][8]
+  uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][tks][64][8]
   uint16_t *w0_hi, *w0_lo;         // split W h, same layout as hs
+  int64_t tks;                     // k-steps per template tile in those layouts (n_pad/16 + TKS_PAD)
   float *y0;                       // [Bp][n_pad]
   double *e64;                     // [Bp][n_pad] FP64 residual h - C y0 (padded rows 0)
   double *corr_part;               // [nblk][Bp] per-block sums of (W e)^2
@@ -75,6 +76,11 @@ struct MixItem {
   int32_t nblk;
   int32_t n_pad;
 };
+
+// Template tiles of the split layouts are n_pad/16 + TKS_PAD fragments apart: without the
+// pad the tiles sit a power of two apart (1 MB at N = 16384) and the tiles read together
+// by the products would fall on the same memory channels.
+constexpr int64_t TKS_PAD = 5;
 
 // Refinement (FP64 FFT Toeplitz quadratic form), per item.
 struct SegDev {
@@ -91,13 +97,13 @@ struct SegDev {
 };
 
 // In-LDS refinement: the m/4-point complex DFTs (h = m/4 <= 2^RL_LHMAX) run in one
-// workgroup's LDS as in-place Stockham passes of radix 2^L (L <= 5).  The pass plan for
-// h = 2^LH: ceil(LH / 5) passes of near-equal radix, larger radices first.
+// workgroup's LDS as in-place Stockham passes of radix 2^L (L <= 4).  The pass plan for
+// h = 2^LH: ceil(LH / 4) passes of near-equal radix, larger radices first.
 constexpr int RL_LHMAX = 13;
 constexpr int64_t RL_MAX_M = (int64_t)4 << RL_LHMAX;
-__host__ __device__ constexpr int rl_npass(int LH) { return LH <= 5 ? 1 : (LH + 4) / 5; }
+__host__ __device__ constexpr int rl_npass(int LH) { return LH <= 4 ? 1 : (LH + 3) / 4; }
 __host__ __device__ constexpr int rl_L(int LH, int p) {
-  return LH / rl_npass(LH) + (p < LH - (LH / rl_npass(LH)) * rl_npass(LH) ? 1 : 0);
+  return LH / rl_npass(LH) + (p < LH % rl_npass(LH) ? 1 : 0);
 }
 // log2 of the sub-transform length entering pass p
 __host__ __device__ constexpr int rl_lns(int LH, int p) { return p == 0 ? 0 : rl_lns(LH, p - 1) + rl_L(LH, p - 1); }
