@@ -296,6 +296,7 @@ hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chu
 //      workgroups per CU.
 //   3: as 1, with the operands staged through LDS (4 stages of 32 fragments, direct
 //      global -> LDS loads three k-steps ahead).
+//   4: as 1 with three register stages (loads two k-steps ahead).
 //   5: 8 waves, wave tile 4 x 2, workgroup 256 x 256 from a 3-stage LDS ring; two waves
 //      per SIMD hide each other's latency while every fragment is fetched once per
 //      workgroup.
@@ -315,6 +316,7 @@ struct PL {
   static constexpr int WB = V == 2 || V == 5 ? 2 : 4;
   static constexpr bool FULL = V != 2;
   static constexpr int STAGES = V == 3 ? 4 : V == 5 ? 3 : 0;
+  static constexpr int RST = V == 4 ? 3 : 2;  // register stages of the register path
   static constexpr int OCC = V == 2 ? 2 : 1;  // workgroups per CU the registers allow
   __device__ static int ta(int w) { return NW == 8 ? 4 * (w >> 2) : 4 * (w >> 1); }
   __device__ static int tb(int w) { return NW == 8 ? 2 * (w & 3) : WB * (w & 1); }
@@ -328,20 +330,23 @@ struct Step {
 };
 
 // NPROD = 3: hi*hi + hi*lo + lo*hi; NPROD = 1: hi*hi only (lo parts not loaded)
+// Issued in the order mma_step consumes them: A hi and B hi (first pass), B lo, A lo.
 template <int NPROD, int WB>
 __device__ __forceinline__ void load_step(const FragSrc &A, const FragSrc &B, int ta, int tb,
                                           int64_t ks, int lane, Step<WB> &st) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t off = (int64_t)(ta + a) * A.s_tile + ks * A.s_ks + lane * 8;
-    st.ah[a] = load_frag(A.hi + off);
-    if (NPROD == 3) st.al[a] = load_frag(A.lo + off);
-  }
+  for (int a = 0; a < 4; ++a)
+    st.ah[a] = load_frag(A.hi + (int64_t)(ta + a) * A.s_tile + ks * A.s_ks + lane * 8);
 #pragma unroll
-  for (int b = 0; b < WB; ++b) {
-    const int64_t off = (int64_t)(tb + b) * B.s_tile + ks * B.s_ks + lane * 8;
-    st.bh[b] = load_frag(B.hi + off);
-    if (NPROD == 3) st.bl[b] = load_frag(B.lo + off);
+  for (int b = 0; b < WB; ++b)
+    st.bh[b] = load_frag(B.hi + (int64_t)(tb + b) * B.s_tile + ks * B.s_ks + lane * 8);
+  if (NPROD == 3) {
+#pragma unroll
+    for (int b = 0; b < WB; ++b)
+      st.bl[b] = load_frag(B.lo + (int64_t)(tb + b) * B.s_tile + ks * B.s_ks + lane * 8);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      st.al[a] = load_frag(A.lo + (int64_t)(ta + a) * A.s_tile + ks * A.s_ks + lane * 8);
   }
 }
 
@@ -372,22 +377,42 @@ __device__ __forceinline__ void zero_acc(f16v (&acc)[4][WB]) {
     for (int b = 0; b < WB; ++b) acc[a][b] = f16v{};
 }
 
-// Register path (variants 1, 2): one k-step of operands in flight.
-template <int NPROD, int WB>
+// Register path (variants 1, 2, 4): NST register stages, loads issued NST - 1 k-steps
+// ahead.  The scheduling barriers keep each k-step's loads ahead of the matrix-core ops
+// before them, and the loop body has no branch (loads past the end are clamped to the
+// last k-step), so the compiler's wait counts leave the later stages in flight.
+template <int NPROD, int WB, int NST>
 __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int ta, int tb,
                                       int64_t nks, f16v (&acc)[4][WB]) {
   const int lane = threadIdx.x & 63;
   zero_acc<WB>(acc);
-  Step<WB> s0, s1;
-  if (nks > 0) load_step<NPROD, WB>(A, B, ta, tb, 0, lane, s0);
+  if (nks <= 0) return;
+  Step<WB> st[NST];
+#pragma unroll
+  for (int p = 0; p < NST - 1; ++p)
+    load_step<NPROD, WB>(A, B, ta, tb, p < nks ? p : nks - 1, lane, st[p]);
+  // loads of a later k-step are spread through this k-step's matrix-core ops
+  constexpr int NL = (NPROD == 3 ? 2 : 1) * (4 + WB), NM = NPROD * 4 * WB;
   int64_t ks = 0;
-  for (; ks + 1 < nks; ks += 2) {
-    load_step<NPROD, WB>(A, B, ta, tb, ks + 1, lane, s1);
-    mma_step<NPROD, WB>(s0, acc);
-    if (ks + 2 < nks) load_step<NPROD, WB>(A, B, ta, tb, ks + 2, lane, s0);
-    mma_step<NPROD, WB>(s1, acc);
+  for (; ks + NST <= nks; ks += NST) {
+#pragma unroll
+    for (int u = 0; u < NST; ++u) {
+      const int64_t kn = ks + u + NST - 1;
+      load_step<NPROD, WB>(A, B, ta, tb, kn < nks ? kn : nks - 1, lane, st[(u + NST - 1) % NST]);
+      mma_step<NPROD, WB>(st[u], acc);
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);        // one global load
+        __builtin_amdgcn_sched_group_barrier(0x008, NM / NL, 0);  // then matrix-core ops
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
-  if (ks < nks) mma_step<NPROD, WB>(s0, acc);
+  // remaining nks mod NST steps sit in the first stages
+  const int64_t rem = nks - ks;
+#pragma unroll
+  for (int u = 0; u < NST - 1; ++u)
+    if (u < rem) mma_step<NPROD, WB>(st[u], acc);
 }
 
 // LDS path (variants 3, 5).  A stage holds one k-step's 32 fragments: A hi tiles 0-7,
@@ -485,7 +510,7 @@ __device__ __forceinline__ void gemm3_v(const FragSrc &A, const FragSrc &B, int6
     gemm3_lds<NPROD, V>(A, B, nks, acc, gp_smem);
   } else {
     const int w = threadIdx.x >> 6;
-    gemm3<NPROD, L::WB>(A, B, L::ta(w), L::tb(w), nks, acc);
+    gemm3<NPROD, L::WB, L::RST>(A, B, L::ta(w), L::tb(w), nks, acc);
   }
 }
 
@@ -642,6 +667,10 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
     case 3:                                                                                  \
       hipLaunchKernelGGL(K<3>, dim3((unsigned)n_work), dim3(64 * PL<3>::NW),                  \
                          PL<3>::lds_bytes(), s, items, work);                                \
+      break;                                                                                 \
+    case 4:                                                                                  \
+      hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(64 * PL<4>::NW), 0, s, items,     \
+                         work);                                                              \
       break;                                                                                 \
     case 5:                                                                                  \
       hipLaunchKernelGGL(K<5>, dim3((unsigned)n_work), dim3(64 * PL<5>::NW),                  \
@@ -1070,8 +1099,12 @@ __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ 
         for (int q = 0; q < R; ++q) a[g][q] = X[lpad(j + q * NT)];
       }
       if constexpr (LNS > 0) {
+        // a few twiddles at a time, so they do not all hold registers at once
 #pragma unroll
-        for (int q = 1; q < R; ++q) a[g][q] = cmul(a[g][q], ptw[OFF + (q - 1) * NS + k]);
+        for (int q = 1; q < R; ++q) {
+          a[g][q] = cmul(a[g][q], ptw[OFF + (q - 1) * NS + k]);
+          if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+        }
       }
       dft_small<L>(a[g]);
     }

@@ -929,7 +929,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     int64_t nw;
     hipStream_t s;
   };
-  static const int kVariants[4] = {1, 2, 3, 5};
+  static const int kVariants[5] = {1, 2, 3, 4, 5};
   Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
   Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
   int64_t max_chunks = 0;
@@ -939,7 +939,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_h", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
   }
-  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 4, s,
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 5, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
@@ -948,7 +948,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts(variant_name(kTrmmFwdNames, vf), s);
     HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
   }
-  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 4, s,
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 5, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
@@ -969,7 +969,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_e", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
-  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 4, s,
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 5, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_corr(x->dm, x->w, x->nw, v, x->s);
