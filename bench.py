@@ -124,6 +124,8 @@ def main():
                          "c5: request server over 32 resident datasets")
     ap.add_argument("--duration", type=float, default=4.0, help="c5: seconds of request trace")
     ap.add_argument("--rate", type=float, default=20000.0, help="c5: mean requests per second")
+    ap.add_argument("--rates", default="0.01,0.025,0.05,0.1,1.0",
+                    help="c5: offered loads of the sweep, as fractions of --rate")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (reference "
                          "kernel for hardware byte counters)")
@@ -346,16 +348,47 @@ def bench_c4(args, tda, torch, synth, dev, log):
     print(json.dumps(line), flush=True)
 
 
+def _serve_trace(srv, req, Hs, out_dev, torch):
+    """Replay a request trace against a server in real time; returns (wall, stats, templates)."""
+    n = len(req["t"])
+    counts = req["count"]
+    out = torch.empty(int(counts.sum()), dtype=torch.float64, device=out_dev)
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    bank = Hs[0].shape[0]
+    tickets = []
+    srv.stats(reset=True)
+    t_start = time.perf_counter()
+    for k in range(n):
+        delay = req["t"][k] - (time.perf_counter() - t_start)
+        if delay > 0:
+            time.sleep(delay)
+        ds = int(req["dataset"][k])
+        c = int(counts[k])
+        r0 = min(int(req["start"][k]), bank - c)
+        tk = None
+        while tk is None:
+            tk = srv.submit(ds, Hs[ds][r0:r0 + c], out[offs[k]:offs[k] + c])
+        tickets.append(tk)
+    for tk in tickets:
+        srv.wait(tk, 600.0)
+    wall = time.perf_counter() - t_start
+    return wall, srv.stats(), int(counts.sum())
+
+
 def bench_c5(args, tda, torch, synth, dev, log):
     """Request server: 32 resident single-detector datasets (N in 4096..65536), Poisson
-    arrivals of 1-64-template requests from 512 simulated walkers."""
+    arrivals of 1-64-template requests from 512 simulated walkers, swept over offered
+    loads (fractions of --rate); the FP64 server replays every 20th request of the full
+    trace."""
     t0 = time.perf_counter()
     w = synth.c5_workload(duration_s=args.duration, rate_hz=args.rate)
     log(f"c5 inputs in {time.perf_counter() - t0:.1f} s")
-    res = {}
+    fracs = [float(x) for x in args.rates.split(",") if x.strip()]
+    # the server runs the default product variant: tuning trials for every coalesced
+    # batch shape would otherwise land inside the latency measurements
+    os.environ["TDA_AUTOTUNE"] = "0"
+    sweep, res = [], {}
     for prec in ("mixed", "fp64"):
-        # the FP64 pass replays every 20th request (its capacity is far below the offered load)
-        stride = 1 if prec == "mixed" else 20
         t0 = time.perf_counter()
         srv = tda.Server(precision=prec, n_slots=3, max_batch=2048, staging_bytes=256 << 20)
         keep, Hs = [], []
@@ -370,46 +403,42 @@ def bench_c5(args, tda, torch, synth, dev, log):
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         log(f"c5 {prec}: setup {setup:.1f} s")
-        req = {k: v[::stride] for k, v in w.requests.items()}
-        n = len(req["t"])
-        counts = req["count"]
-        out = torch.empty(int(counts.sum()), dtype=torch.float64, device=dev)
-        offs = np.concatenate([[0], np.cumsum(counts)[:-1]])
-        bank = Hs[0].shape[0]
-        tickets = []
-        srv.stats(reset=True)
-        t_start = time.perf_counter()
-        for k in range(n):
-            delay = req["t"][k] - (time.perf_counter() - t_start)
-            if delay > 0:
-                time.sleep(delay)
-            ds = int(req["dataset"][k])
-            c = int(counts[k])
-            r0 = min(int(req["start"][k]), bank - c)
-            tk = None
-            while tk is None:
-                tk = srv.submit(ds, Hs[ds][r0:r0 + c], out[offs[k]:offs[k] + c])
-            tickets.append(tk)
-        for tk in tickets:
-            srv.wait(tk, 600.0)
-        wall = time.perf_counter() - t_start
-        st = srv.stats()
+        # untimed warm-up (code loading, first allocations)
+        _serve_trace(srv, synth.c5_requests(args.rate * min(fracs), 0.5, trace=99), Hs, dev, torch)
+        if prec == "mixed":
+            for i, f in enumerate(fracs):
+                req = w.requests if f == 1.0 else synth.c5_requests(args.rate * f, args.duration,
+                                                                     trace=i + 1)
+                wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
+                point = {"offered_evals_per_s": tmpl / args.duration,
+                         "achieved_evals_per_s": tmpl / wall, "requests": len(req["t"]),
+                         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                         "mean_templates_per_launch": st["mean_templates_per_launch"]}
+                sweep.append(point)
+                log(f"c5 mixed at {f:g} x {args.rate:g} req/s: {point}")
+                if f == max(fracs):
+                    res[prec] = (wall, st, setup, len(req["t"]), tmpl)
+        else:
+            req = {k: v[::20] for k, v in w.requests.items()}
+            wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
+            res[prec] = (wall, st, setup, len(req["t"]), tmpl)
+            log(f"c5 fp64: {st}")
         srv.close()
-        res[prec] = (wall, st, setup, n, int(counts.sum()))
         del keep, Hs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        log(f"c5 {prec}: {st}")
     wall, st, setup, n, tmpl = res["mixed"]
+    top = max(fracs)
     line = _base_line(args, tmpl / wall, "evals/s", wall, 1,
                       {"workload": f"request server: 32 resident datasets N in 4096..65536, Poisson "
-                                   f"{args.rate:g} req/s x {args.duration:g} s, 1-64 templates per "
-                                   f"request, 512 walkers", "requests": n, "templates": tmpl},
+                                   f"{args.rate * top:g} req/s x {args.duration:g} s, 1-64 templates "
+                                   f"per request, 512 walkers", "requests": n, "templates": tmpl},
                       "bf16x3+f64")
     line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"],
                           "unit": "submit to results written"}
     line["offered_evals_per_s"] = tmpl / args.duration
     line["server"] = st
+    line["load_sweep"] = sweep
     line["setup_s"] = setup
     fw, fst, fsetup, fn, ftmpl = res["fp64"]
     line["fp64"] = {"value": ftmpl / fw, "unit": "evals/s", "offered_fraction": 1 / 20,

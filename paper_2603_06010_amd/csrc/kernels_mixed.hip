@@ -289,17 +289,15 @@ hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chu
 // A workgroup computes a tile of D = A B over K = 16 nks; A and B are given as fragment
 // arrays: A tile t (32 rows) at k-step ks is at A + t s_tile + ks s_ks.  Every product is
 // hi*hi + hi*lo + lo*hi with FP32 accumulation.  Variants (picked per shape by the
-// autotuner):
-//   1: 4 waves, wave tile 4 A x 4 B tiles (128 x 128), workgroup 256 x 256; operands
-//      straight from memory into registers one k-step ahead; one wave per SIMD.
+// autotuner); operands go straight from memory into registers:
+//   1: 4 waves, wave tile 4 A x 4 B tiles (128 x 128), workgroup 256 x 256, loads one
+//      k-step ahead; one wave per SIMD (accumulators in AGPRs).
 //   2: 4 waves, wave tile 4 x 2, workgroup 256 x 128 (half a template group); two
-//      workgroups per CU.
-//   3: as 1, with the operands staged through LDS (4 stages of 32 fragments, direct
-//      global -> LDS loads three k-steps ahead).
+//      workgroups per CU, so two waves per SIMD hide each other's latency.
 //   4: as 1 with three register stages (loads two k-steps ahead).
-//   5: 8 waves, wave tile 4 x 2, workgroup 256 x 256 from a 3-stage LDS ring; two waves
-//      per SIMD hide each other's latency while every fragment is fetched once per
-//      workgroup.
+// Staging the operands through LDS with direct global -> LDS loads (one fetch per
+// workgroup instead of per wave pair) measured slower than all three on gfx950, even with
+// every operand cache-resident, and is not kept.
 struct FragSrc {
   const uint16_t *hi, *lo;
   int64_t s_tile, s_ks;  // element strides between tiles and between k-steps
@@ -308,20 +306,17 @@ struct FragSrc {
 constexpr int FRAG = 512;  // bf16 elements per fragment (64 lanes x 8)
 
 // Layout of variant V: waves per workgroup, B tiles per wave, whether a workgroup covers
-// a whole group of 256 templates (else half, chosen by the work entry's `sub`), the wave's
-// first A and B tile, and the LDS stages (0: operands go straight to registers).
+// a whole group of 256 templates (else half, chosen by the work entry's `sub`), register
+// stages, workgroups per CU, and the wave's first A and B tile.
 template <int V>
 struct PL {
-  static constexpr int NW = V == 5 ? 8 : 4;
-  static constexpr int WB = V == 2 || V == 5 ? 2 : 4;
+  static constexpr int NW = 4;
+  static constexpr int WB = V == 2 ? 2 : 4;
   static constexpr bool FULL = V != 2;
-  static constexpr int STAGES = V == 3 ? 4 : V == 5 ? 3 : 0;
-  static constexpr int RST = V == 4 ? 3 : 2;  // register stages of the register path
-  static constexpr int OCC = V == 2 ? 2 : 1;  // workgroups per CU the registers allow
-  __device__ static int ta(int w) { return NW == 8 ? 4 * (w >> 2) : 4 * (w >> 1); }
-  __device__ static int tb(int w) { return NW == 8 ? 2 * (w & 3) : WB * (w & 1); }
-  // LDS bytes of the operand ring
-  static constexpr size_t lds_bytes() { return (size_t)STAGES * 32 * FRAG * 2; }
+  static constexpr int RST = V == 4 ? 3 : 2;
+  static constexpr int OCC = V == 2 ? 2 : 1;
+  __device__ static int ta(int w) { return 4 * (w >> 1); }
+  __device__ static int tb(int w) { return WB * (w & 1); }
 };
 
 template <int WB>
@@ -377,7 +372,7 @@ __device__ __forceinline__ void zero_acc(f16v (&acc)[4][WB]) {
     for (int b = 0; b < WB; ++b) acc[a][b] = f16v{};
 }
 
-// Register path (variants 1, 2, 4): NST register stages, loads issued NST - 1 k-steps
+// NST register stages, loads issued NST - 1 k-steps
 // ahead.  The scheduling barriers keep each k-step's loads ahead of the matrix-core ops
 // before them, and the loop body has no branch (loads past the end are clamped to the
 // last k-step), so the compiler's wait counts leave the later stages in flight.
@@ -415,103 +410,12 @@ __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int ta
     if (u < rem) mma_step<NPROD, WB>(st[u], acc);
 }
 
-// LDS path (variants 3, 5).  A stage holds one k-step's 32 fragments: A hi tiles 0-7,
-// A lo 0-7, B hi 0-7, B lo 0-7 of the workgroup's window.  Wave w copies fragments
-// FPW w .. FPW w + FPW - 1 (FPW = 32 / NW) with direct global -> LDS loads, STAGES - 1
-// k-steps ahead.  Each wave waits for its own copies of a stage, then a barrier makes
-// the whole stage visible; a bare s_barrier is used because a release fence would also
-// wait for the copies of the later stages.
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
-__device__ __forceinline__ void gp_barrier() { asm volatile("s_barrier" ::: "memory"); }
-
-// The operand array a wave copies (fragments FPW w .. FPW w + FPW - 1 of a stage lie in
-// one array: A hi, A lo, B hi or B lo), resolved once per workgroup.
-struct GpSrc {
-  const uint16_t *p;  // first fragment of this wave's tiles at k-step 0, plus the lane offset
-  int64_t s_tile, s_ks;
-  int f0;             // first stage fragment index of this wave
-};
-
-template <int NW>
-__device__ __forceinline__ GpSrc gp_src(const FragSrc &A, const FragSrc &B, int w, int lane) {
-  constexpr int FPW = 32 / NW;
-  const int f0 = FPW * w, arr = f0 >> 3, tile0 = f0 & 7;
-  const bool isA = arr < 2;
-  const uint16_t *base = arr == 0 ? A.hi : arr == 1 ? A.lo : arr == 2 ? B.hi : B.lo;
-  const int64_t st = isA ? A.s_tile : B.s_tile, sk = isA ? A.s_ks : B.s_ks;
-  return GpSrc{base + tile0 * st + lane * 8, st, sk, f0};
-}
-
-template <int NW>
-__device__ __forceinline__ void gp_issue(const GpSrc &g, int64_t ks, char *stage) {
-  constexpr int FPW = 32 / NW;
-  const uint16_t *q = g.p + ks * g.s_ks;
-#pragma unroll
-  for (int u = 0; u < FPW; ++u)
-    __builtin_amdgcn_global_load_lds((const void *)(q + u * g.s_tile),
-                                     (lds_void_t *)(stage + (g.f0 + u) * 1024), 16, 0, 0);
-}
-
-template <int NPROD, int V>
-__device__ __forceinline__ void gemm3_lds(const FragSrc &A, const FragSrc &B, int64_t nks,
-                                          f16v (&acc)[4][PL<V>::WB], char *smem) {
-  using L = PL<V>;
-  constexpr int NST = L::STAGES, FPW = 32 / L::NW, SB = 32 * FRAG * 2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ta = L::ta(w), tb = L::tb(w);
-  const GpSrc g = gp_src<L::NW>(A, B, w, lane);
-  zero_acc<L::WB>(acc);
-#pragma unroll
-  for (int p = 0; p < NST - 1; ++p)
-    if (p < nks) gp_issue<L::NW>(g, p, smem + p * SB);
-  for (int64_t t = 0; t < nks; ++t) {
-    // this wave's copies issued after stage t: min(nks - 1 - t, NST - 2) stages
-    const int64_t ahead = nks - 1 - t;
-    if constexpr (NST >= 4) {
-      if (ahead >= 2) wait_vmcnt<2 * FPW>();
-      else if (ahead == 1) wait_vmcnt<FPW>();
-      else wait_vmcnt<0>();
-    } else {
-      if (ahead >= 1) wait_vmcnt<FPW>();
-      else wait_vmcnt<0>();
-    }
-    gp_barrier();  // stage t complete for every wave; stage t - 1 no longer read
-    if (t + NST - 1 < nks)
-      gp_issue<L::NW>(g, t + NST - 1, smem + ((t + NST - 1) % NST) * SB);
-    const bf8 *S = (const bf8 *)(smem + (t % NST) * SB);
-    Step<L::WB> st;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      st.ah[a] = S[(ta + a) * 64 + lane];
-      st.al[a] = S[(8 + ta + a) * 64 + lane];
-    }
-#pragma unroll
-    for (int b = 0; b < L::WB; ++b) {
-      st.bh[b] = S[(16 + tb + b) * 64 + lane];
-      st.bl[b] = S[(24 + tb + b) * 64 + lane];
-    }
-    mma_step<NPROD, L::WB>(st, acc);
-  }
-}
-
 template <int NPROD, int V>
 __device__ __forceinline__ void gemm3_v(const FragSrc &A, const FragSrc &B, int64_t nks,
                                         f16v (&acc)[4][PL<V>::WB]) {
   using L = PL<V>;
-  if constexpr (L::STAGES > 0) {
-    extern __shared__ char gp_smem[];
-    gemm3_lds<NPROD, V>(A, B, nks, acc, gp_smem);
-  } else {
-    const int w = threadIdx.x >> 6;
-    gemm3<NPROD, L::WB, L::RST>(A, B, L::ta(w), L::tb(w), nks, acc);
-  }
+  const int w = threadIdx.x >> 6;
+  gemm3<NPROD, L::WB, L::RST>(A, B, L::ta(w), L::tb(w), nks, acc);
 }
 
 // Work entries (item, block, group of 256 templates, sub): half-group variants take the
@@ -580,10 +484,14 @@ __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_bwd(
   const int64_t ks0 = (int64_t)j * (TB / 16);
   const int64_t T0 = (int64_t)wk.z * 8;
   const int st0 = L::FULL ? 0 : 4 * wk.w;
-  const FragSrc A{it.w0_hi + (T0 * it.tks + ks0) * FRAG, it.w0_lo + (T0 * it.tks + ks0) * FRAG,
-                  it.tks * FRAG, FRAG};
-  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG,
-                  it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG, FRAG, 8 * FRAG};
+  // K runs from the end of the segment down: the column blocks of one super-tile end at
+  // the same row, so walking K backwards keeps them on the same template k-steps (shared
+  // in L2) until the shorter ones finish.
+  const int64_t kl = nks - 1;
+  const FragSrc A{it.w0_hi + (T0 * it.tks + ks0 + kl) * FRAG, it.w0_lo + (T0 * it.tks + ks0 + kl) * FRAG,
+                  it.tks * FRAG, -FRAG};
+  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG + kl * 8 * FRAG,
+                  it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG + kl * 8 * FRAG, FRAG, -8 * FRAG};
   f16v acc[4][L::WB];
   gemm3_v<3, V>(A, B, nks, acc);
 #pragma unroll
@@ -661,24 +569,13 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
   if (n_work <= 0) return hipSuccess;                                                        \
   switch (variant) {                                                                         \
     case 2:                                                                                  \
-      hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(64 * PL<2>::NW), 0, s, items,     \
-                         work);                                                              \
-      break;                                                                                 \
-    case 3:                                                                                  \
-      hipLaunchKernelGGL(K<3>, dim3((unsigned)n_work), dim3(64 * PL<3>::NW),                  \
-                         PL<3>::lds_bytes(), s, items, work);                                \
+      hipLaunchKernelGGL(K<2>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);         \
       break;                                                                                 \
     case 4:                                                                                  \
-      hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(64 * PL<4>::NW), 0, s, items,     \
-                         work);                                                              \
-      break;                                                                                 \
-    case 5:                                                                                  \
-      hipLaunchKernelGGL(K<5>, dim3((unsigned)n_work), dim3(64 * PL<5>::NW),                  \
-                         PL<5>::lds_bytes(), s, items, work);                                \
+      hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);         \
       break;                                                                                 \
     default:                                                                                 \
-      hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(64 * PL<1>::NW), 0, s, items,     \
-                         work);                                                              \
+      hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);         \
   }                                                                                          \
   return hipGetLastError();
 
@@ -1398,18 +1295,6 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
 void register_mixed_attributes() {
   hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)RL_LDS_BYTES);
-  hipFuncSetAttribute((const void *)k_trmm_fwd<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<3>::lds_bytes());
-  hipFuncSetAttribute((const void *)k_trmm_bwd<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<3>::lds_bytes());
-  hipFuncSetAttribute((const void *)k_corr<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<3>::lds_bytes());
-  hipFuncSetAttribute((const void *)k_trmm_fwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<5>::lds_bytes());
-  hipFuncSetAttribute((const void *)k_trmm_bwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<5>::lds_bytes());
-  hipFuncSetAttribute((const void *)k_corr<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)PL<5>::lds_bytes());
 }
 
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,

@@ -892,23 +892,31 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
                                 const std::vector<const tda_ctx *> &hs, double *fft_scratch,
                                 int64_t max_m, hipStream_t s) {
   const int64_t n = (int64_t)mis.size();
-  // refinement in LDS when every segment's circulant fits, else paired with global scratch
-  const bool rl = max_m <= RL_MAX_M;
+  // refinement in LDS for items whose segments' circulants fit, paired with global
+  // scratch for the others
+  (void)max_m;
   std::vector<BlockJob> jf, jb;
   std::vector<int4> wr;
-  std::vector<int2> wfin;
+  std::vector<int2> wfin, wrl;
   for (int64_t k = 0; k < n; ++k) {
     if (mis[k].B == 0) continue;
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, false, jf);
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, true, jb);
-    if (!rl) add_refine_pairs((int32_t)k, mis[k].B, wr);
-    for (int32_t b = 0; b < mis[k].B; ++b) wfin.push_back(int2{(int32_t)k, b});
+    const bool in_lds = hs[k]->max_m <= RL_MAX_M;
+    if (!in_lds) add_refine_pairs((int32_t)k, mis[k].B, wr);
+    for (int32_t b = 0; b < mis[k].B; ++b) {
+      wfin.push_back(int2{(int32_t)k, b});
+      if (in_lds) wrl.push_back(int2{(int32_t)k, b});
+    }
   }
+  int64_t max_m_scratch = 0;
+  for (int64_t k = 0; k < n; ++k)
+    if (mis[k].B > 0 && hs[k]->max_m > RL_MAX_M) max_m_scratch = std::max(max_m_scratch, hs[k]->max_m);
   const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
   HIP_TRY(ring.reserve(8192 + n * (64 + sizeof(MixItem) + sizeof(RefItem)) +
                        (wf.size() + wbk.size() + wr.size()) * sizeof(int4) +
-                       wfin.size() * sizeof(int2)));
-  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr, *d_fin;
+                       (wfin.size() + wrl.size()) * sizeof(int2)));
+  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr, *d_fin, *d_rl = nullptr;
   HIP_TRY(ring.push(mis.data(), mis.size() * sizeof(MixItem), s, &d_mi));
   HIP_TRY(ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
   HIP_TRY(ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
@@ -916,6 +924,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   d_wr = nullptr;
   if (!wr.empty()) HIP_TRY(ring.push(wr.data(), wr.size() * sizeof(int4), s, &d_wr));
   HIP_TRY(ring.push(wfin.data(), wfin.size() * sizeof(int2), s, &d_fin));
+  if (!wrl.empty()) HIP_TRY(ring.push(wrl.data(), wrl.size() * sizeof(int2), s, &d_rl));
   const MixItem *dm = (const MixItem *)d_mi;
   // autotuned variant per product kernel, keyed by the largest item's shape
   int64_t rows = 0, tmpl = 0;
@@ -929,7 +938,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     int64_t nw;
     hipStream_t s;
   };
-  static const int kVariants[5] = {1, 2, 3, 4, 5};
+  static const int kVariants[3] = {1, 2, 4};
   Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
   Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
   int64_t max_chunks = 0;
@@ -939,7 +948,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_h", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
   }
-  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 5, s,
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
@@ -948,7 +957,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts(variant_name(kTrmmFwdNames, vf), s);
     HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
   }
-  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 5, s,
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
@@ -959,17 +968,17 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   }
   {
     TimedScope ts("refine_fft", s);
-    if (rl)
-      HIP_TRY(launch_refine_lds((const RefItem *)d_ri, (const int2 *)d_fin, (int64_t)wfin.size(), s));
-    else
+    if (!wrl.empty())
+      HIP_TRY(launch_refine_lds((const RefItem *)d_ri, (const int2 *)d_rl, (int64_t)wrl.size(), s));
+    if (!wr.empty())
       HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
-                            fft_scratch, 2 * max_m, kRefineWG, s));
+                            fft_scratch, 2 * max_m_scratch, kRefineWG, s));
   }
   {
     TimedScope ts("split_e", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
-  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 5, s,
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 3, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
                                  return launch_corr(x->dm, x->w, x->nw, v, x->s);

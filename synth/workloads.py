@@ -299,13 +299,24 @@ def c5_workload(eps: float = EPS_PRIMARY, n_datasets: int = 32, duration_s: floa
     """
     st = _streams(4)
     insts = [_instance(st, sizes[k % len(sizes)], 1, 0, bank, eps) for k in range(n_datasets)]
-    r = st["requests"]
+    req = _requests(st["requests"], rate_hz, duration_s, n_datasets, n_walkers, bank)
+    return Workload("C5", insts, req)
+
+
+def _requests(r, rate_hz, duration_s, n_datasets, n_walkers, bank):
     n_req = int(rate_hz * duration_s)
     arrivals = np.cumsum(r.exponential(1.0 / rate_hz, n_req))
-    req = dict(t=arrivals, dataset=r.integers(0, n_datasets, n_req),
-               count=r.integers(1, 65, n_req), walker=r.integers(0, n_walkers, n_req),
-               start=r.integers(0, bank, n_req))
-    return Workload("C5", insts, req)
+    return dict(t=arrivals, dataset=r.integers(0, n_datasets, n_req),
+                count=r.integers(1, 65, n_req), walker=r.integers(0, n_walkers, n_req),
+                start=r.integers(0, bank, n_req))
+
+
+def c5_requests(rate_hz: float, duration_s: float, n_datasets: int = 32, n_walkers: int = 512,
+                bank: int = 256, trace: int = 1) -> dict:
+    """Another Poisson request trace over the C5 datasets (same law as c5_workload's),
+    from its own seeded stream: one trace per offered load of a load sweep."""
+    r = np.random.default_rng([SEED_BASE + 4, 1000 + trace])
+    return _requests(r, rate_hz, duration_s, n_datasets, n_walkers, bank)
 
 
 def make_workload(k: int, **kw) -> Workload:
