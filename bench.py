@@ -209,6 +209,28 @@ def main():
     res_f = out["fp64"].cpu().numpy()
     d_mf = np.abs(res_m - res_f)
 
+    # Gohberg-Semencul FP64 path on the same inputs (segments without excluded samples)
+    gs = None
+    if not any(m is not None and np.any(m) for m in inst.masks):
+        t0 = time.perf_counter()
+        hg = [tda.Handle(inst.acf, inst.N, inst.masks[k], precision="gs").factor()
+              for k in range(inst.n_det)]
+        torch.cuda.synchronize()
+        gs_setup = time.perf_counter() - t0
+        out["gs"] = torch.empty(inst.B, dtype=torch.float64, device=dev)
+        items["gs"] = [(h, dk, H, out["gs"]) for h, dk in zip(hg, d)]
+        wall_g, lat_g, kt_g = run("gs", args.steps, args.warmup)
+        log(f"gs: {wall_g / args.steps * 1e3:.3f} ms/step", kt_g)
+        res_g = out["gs"].cpu().numpy()
+        gs = {"value": inst.B * args.steps / wall_g, "unit": "evals/s",
+              "ms_per_step": wall_g / args.steps * 1e3,
+              "latency_ms": {"p50": _pct(lat_g, 50), "p99": _pct(lat_g, 99)},
+              "max_abs_dlogL_vs_fp64_gpu": float(np.abs(res_g - res_f).max()),
+              "kernels_ms": {k: v[1] / v[0] for k, v in kt_g.items()},
+              "setup_s": gs_setup}
+        for h in hg:
+            h.close()
+
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
 
@@ -251,6 +273,7 @@ def main():
                               "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                               "frac": ach_f / PEAK_FP64, "avg_ms": tf / cf}},
         "speedup_mixed_vs_fp64": evals_m / evals_f,
+        "gs_fp64": gs,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
                      "templates_compared": int(inst.B)},

@@ -33,6 +33,15 @@
  *                     The refined quadratic form is never larger than the
  *                     exact one (variational bound) and its error is
  *                     quadratic in the BF16 product error.
+ *   TDA_PREC_GS    -- FP64 evaluation through the Gohberg-Semencul form of the
+ *                     Toeplitz inverse (Sec. III.A.3): x = C^-1 e_1 and log det C
+ *                     by Levinson-Durbin once per segment, then per template
+ *                     q = (||L(x)^T r||^2 - ||L(z)^T r||^2) / x_0 with
+ *                     z = (0, x_{n-1}, .., x_1) and L(v) the lower-triangular
+ *                     Toeplitz matrix of v, both products by FFT (O(n log n) per
+ *                     template, no factorisation).  Only for segments without
+ *                     excluded samples and of at most 16384 samples; a GS handle
+ *                     evaluates only in TDA_PREC_GS.
  *
  * Conventions for every entry point:
  *   - Returns a tda_status; nothing is thrown across the ABI.  On failure a
@@ -68,7 +77,7 @@ typedef enum {
   TDA_EAGAIN = 8     /* serving: request not admitted now, retry later */
 } tda_status;
 
-typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1 } tda_precision;
+typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1, TDA_PREC_GS = 2 } tda_precision;
 
 /* TDA_FLAG_COMPACT (mixed handles): once tda_set_data has cached the whitened
  * data, release the FP64 solve panels and the FP64 whitening operator, keeping
@@ -121,8 +130,9 @@ typedef struct {
  *   out      receives the handle.  All inputs are copied; the caller may free
  *            them on return.
  * Errors: EINVAL (N < 1, acf_len too short, acf[0] <= 0 or non-finite,
- *   bad segments, no retained sample), ENOMEM, ENODEV, EHIP.
- * Synchronous: returns after assembly finished.
+ *   bad segments, no retained sample; for TDA_PREC_GS also an excluded sample
+ *   inside a segment or a segment longer than 16384), ENOMEM, ENODEV, EHIP.
+ * Synchronous: returns after assembly finished (GS handles assemble nothing).
  */
 tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t N, const uint8_t *gap_mask,
                          const tda_segment *segments, int64_t n_segments, const tda_options *opt,
@@ -132,8 +142,11 @@ tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t N, const ui
  * tda_factor -- FP64 blocked Cholesky of every block, C = L L^T, and
  * log det C = 2 sum log L_ii (Sec. II.A; one-time cost, Sec. III.A.2).
  * Builds the packed triangular-solve panels; for TDA_PREC_MIXED also the
- * FP64 whitening operator W = L^-1 and its BF16 hi/lo copies.
- * Errors: ENOTSPD (tda_info gives fail_row / fail_segment; the handle stays
+ * FP64 whitening operator W = L^-1 and its BF16 hi/lo copies.  For TDA_PREC_GS
+ * instead: Levinson-Durbin per segment (x = C^-1 e_1, log det C = sum of log
+ * prediction-error energies) and the two correlation spectra (Sec. III.A.3).
+ * Errors: ENOTSPD (tda_info gives fail_row / fail_segment; for GS the first
+ *   order whose prediction-error energy is not positive; the handle stays
  *   destroyable), ENOMEM, EHIP.  Idempotent after success.  Synchronous.
  */
 tda_status tda_factor(tda_handle h);

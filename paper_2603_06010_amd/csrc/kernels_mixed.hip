@@ -231,7 +231,7 @@ hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *t
                          double *ptw, hipStream_t s) {
   const unsigned g = (unsigned)((m + 255) / 256);
   hipLaunchKernelGGL(k_twiddles, dim3(g), dim3(256), 0, s, m, tw);
-  hipLaunchKernelGGL(k_lambda, dim3(g), dim3(256), 0, s, acf, length, m, tw, lam);
+  if (lam) hipLaunchKernelGGL(k_lambda, dim3(g), dim3(256), 0, s, acf, length, m, tw, lam);
   if (ptw && m >= 16 && m <= RL_MAX_M) {
     int lm = 0;
     while (((int64_t)1 << lm) < m) ++lm;
@@ -1292,10 +1292,6 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
   }
 }
 
-void register_mixed_attributes() {
-  hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)RL_LDS_BYTES);
-}
 
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
                              hipStream_t s) {
@@ -1304,6 +1300,315 @@ hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_w
   hipLaunchKernelGGL(k_refine_lds, dim3((unsigned)g), dim3(RL_THREADS), RL_LDS_BYTES, s, items,
                      work, n_work);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Gohberg-Semencul path
+// For a segment without excluded samples C is symmetric Toeplitz.  With x = C^-1 e_1
+// (x_0 > 0) the inverse is (1/x_0) (L(x) L(x)^T - L(z) L(z)^T), z = (0, x_{n-1}, ..., x_1),
+// L(v) the lower-triangular Toeplitz matrix with first column v (Sec. III.A.3), so
+//   q = r^T C^-1 r = (||L(x)^T r||^2 - ||L(z)^T r||^2) / x_0,
+// each L(v)^T r a correlation, i.e. the first n outputs of the circulant product with
+// multiplier conj(DFT_m(v)) (m >= 2n, zero padding), computed with the in-LDS parity split
+// of the refinement (complex multipliers of real sequences keep the pairing identities).
+// x and log det C come from Levinson-Durbin.
+
+// Durbin's recursion: a = (1, a_1, .., a_k) the order-k prediction-error filter, E_k its
+// error energy; reflection kappa_k = -(sum_{j<k} a_j acf[k - j]) / E_{k-1}, a_j += kappa_k
+// a_{k-j} (pairwise, in place), E_k = E_{k-1} (1 - kappa_k^2); x = a / E_{n-1}.
+__global__ __launch_bounds__(1024) void k_levinson(const double *__restrict__ acf, int n,
+                                                   double *__restrict__ x,
+                                                   double *__restrict__ logdet_out,
+                                                   int32_t *__restrict__ fail) {
+  extern __shared__ double lev_a[];  // [n]
+  __shared__ double wsum[16];
+  __shared__ double shE, shL;
+  __shared__ int shFail;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int j = t; j < n; j += 1024) lev_a[j] = j == 0 ? 1.0 : 0.0;
+  if (t == 0) {
+    shE = acf[0];
+    shL = log(acf[0]);
+    shFail = (acf[0] > 0.0 && isfinite(acf[0])) ? -1 : 0;
+  }
+  __syncthreads();
+  for (int k = 1; k < n && shFail < 0; ++k) {
+    double part = 0.0;
+    for (int j = t; j < k; j += 1024) part += lev_a[j] * acf[k - j];
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) wsum[wv] = part;
+    __syncthreads();
+    double num = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) num += wsum[w];
+    const double kappa = -num / shE;
+    for (int j = t; 2 * j <= k; j += 1024) {
+      const double aj = lev_a[j], ak = lev_a[k - j];
+      if (2 * j == k) {
+        lev_a[j] = aj + kappa * aj;
+      } else {
+        lev_a[j] = aj + kappa * ak;
+        lev_a[k - j] = ak + kappa * aj;
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      const double E = shE * (1.0 - kappa * kappa);
+      if (!(E > 0.0) || !isfinite(E)) {
+        shFail = k;
+      } else {
+        shE = E;
+        shL += log(E);
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = t; j < n; j += 1024) x[j] = lev_a[j] / shE;
+  if (t == 0) {
+    *logdet_out = shL;
+    *fail = shFail;
+  }
+}
+
+hipError_t launch_levinson(const double *acf, int64_t n, double *x, double *logdet,
+                           int32_t *fail, hipStream_t s) {
+  if (n < 1 || n > RL_MAX_LEV) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_levinson, dim3(1), dim3(1024), (size_t)n * sizeof(double), s, acf, (int)n,
+                     x, logdet, fail);
+  return hipGetLastError();
+}
+
+// M_k = sum_j v_j exp(+2 pi i j k / m) = conj(DFT_m(v))_k, direct sums in FP64
+__global__ void k_gs_spectra(const double *__restrict__ x, int64_t n, int64_t m,
+                             const double *__restrict__ tw, double *__restrict__ M1,
+                             double *__restrict__ M2) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= m) return;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  int64_t r = 0;  // j k mod m
+  for (int64_t j = 0; j < n; ++j) {
+    const double c = tw[2 * r], sn = tw[2 * r + 1];
+    const double xv = x[j], zv = j == 0 ? 0.0 : x[n - j];
+    ar += xv * c;
+    ai += xv * sn;
+    br += zv * c;
+    bi += zv * sn;
+    r += k;
+    if (r >= m) r -= m;
+  }
+  M1[2 * k] = ar;
+  M1[2 * k + 1] = ai;
+  M2[2 * k] = br;
+  M2[2 * k + 1] = bi;
+}
+
+hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double *tw,
+                             double *M1, double *M2, hipStream_t s) {
+  hipLaunchKernelGGL(k_gs_spectra, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, x, n, m,
+                     tw, M1, M2);
+  return hipGetLastError();
+}
+
+// Sum over this thread's outputs j < length of (L(v)^T r)_j^2, with M = conj(DFT_m(v)).
+template <int LH>
+__device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64_t b,
+                                        const double2 *__restrict__ M, double2 *X,
+                                        double *__restrict__ tes) {
+  constexpr int h = 1 << LH;
+  constexpr int NI = h >= RL_THREADS ? h / RL_THREADS : 1;
+  constexpr int NKE = (h / 2 + RL_THREADS) / RL_THREADS;
+  constexpr int NKO = h / 2 >= RL_THREADS ? h / 2 / RL_THREADS : 1;
+  const int t = threadIdx.x;
+  const double *__restrict__ hrow = gs_template_row(it, b) + sd.offset;
+  const double *__restrict__ dd = it.d + sd.offset;
+  const double2 *__restrict__ tw = (const double2 *)sd.tw;
+  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
+  const int len = (int)sd.length;
+  const double inv_m = 1.0 / (double)(4 * h);
+  auto wm = [&](int r) {
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  // residual samples 2p, 2p + 1 of chunk i0 (0 beyond the segment)
+  auto load_r = [&](int i0, double (&rv)[RL_CH][2]) {
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int jj = 2 * (t + RL_THREADS * (i0 + c)) + u;
+        rv[c][u] = (i0 + c < NI && jj < len) ? dd[jj] - hrow[jj] : 0.0;
+      }
+  };
+  double ss = 0.0;
+  {
+    // ---- even frequencies
+    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+      double rv[RL_CH][2];
+      load_r(i0, rv);
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int p = t + RL_THREADS * (i0 + c);
+        if (i0 + c < NI && p < h) X[lpad(p)] = make_double2(rv[c][0], rv[c][1]);
+      }
+    }
+    __syncthreads();
+    rl_fft<LH>(X, ptw);
+    for (int i0 = 0; i0 < NKE; i0 += RL_CH) {
+      double2 ma[RL_CH], mb[RL_CH], cc[RL_CH];
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int k = t + RL_THREADS * (i0 + c);
+        if (i0 + c < NKE && k <= h / 2) {
+          ma[c] = M[2 * k];
+          mb[c] = M[2 * h - 2 * k];
+          cc[c] = wm(2 * k);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int k = t + RL_THREADS * (i0 + c);
+        if (!(i0 + c < NKE && k <= h / 2)) continue;
+        const int kr = (h - k) & (h - 1);
+        const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+        const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+        const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+        const double2 cO = cmul(cc[c], O);
+        const double2 yk = cmul(ma[c], cadd(E, cO));
+        const double2 yr = cmul(mb[c], conj2(csub(E, cO)));
+        const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
+        X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(cc[c]), op))));
+        if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(cc[c], conj2(op)))));
+      }
+    }
+    __syncthreads();
+    rl_fft<LH>(X, ptw);
+    // even part of the outputs 2p, 2p + 1 parked in this workgroup's scratch (same thread later)
+    for (int i = 0; i < NI; ++i) {
+      const int p = t + RL_THREADS * i;
+      if (p >= h || 2 * p >= len) continue;
+      const double2 g = X[lpad(p)];
+      tes[2 * p] = g.x;
+      if (2 * p + 1 < len) tes[2 * p + 1] = -g.y;
+    }
+    __syncthreads();
+    // ---- odd frequencies
+    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+      double rv[RL_CH][2];
+      double2 wp[RL_CH];
+      load_r(i0, rv);
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int p = t + RL_THREADS * (i0 + c);
+        if (i0 + c < NI && p < h) wp[c] = wm(2 * p);
+      }
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int p = t + RL_THREADS * (i0 + c);
+        if (i0 + c < NI && p < h) X[lpad(p)] = cmul(make_double2(rv[c][0], rv[c][1]), wp[c]);
+      }
+    }
+    __syncthreads();
+    rl_fft<LH>(X, ptw);
+    const double2 om = wm(1);
+    for (int i0 = 0; i0 < NKO; i0 += RL_CH) {
+      double2 ma[RL_CH], mb[RL_CH], dv[RL_CH], cc[RL_CH];
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int k = t + RL_THREADS * (i0 + c);
+        if (i0 + c < NKO && k < h / 2) {
+          ma[c] = M[2 * k + 1];
+          mb[c] = M[2 * k + 2 * h + 1];
+          dv[c] = wm(2 * k + 1);
+          cc[c] = wm(2 * k);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int k = t + RL_THREADS * (i0 + c);
+        if (!(i0 + c < NKO && k < h / 2)) continue;
+        const int kr = h - 1 - k;
+        const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+        const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+        const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+        const double2 dB = cmul(dv[c], B);
+        const double2 yk = cmul(ma[c], cadd(A, dB));
+        const double2 ykh = cmul(mb[c], csub(A, dB));
+        const double2 P = cadd(yk, ykh);
+        const double2 Q = cmul(conj2(cc[c]), csub(yk, ykh));
+        X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
+        X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+      }
+    }
+    __syncthreads();
+    rl_fft<LH>(X, ptw);
+    for (int i = 0; i < NI; ++i) {
+      const int p = t + RL_THREADS * i;
+      if (p >= h || 2 * p >= len) continue;
+      const double2 gz = conj2(cmul(wm(2 * p), X[lpad(p)]));
+      const double c0 = (tes[2 * p] + gz.x) * inv_m;
+      ss += c0 * c0;
+      if (2 * p + 1 < len) {
+        const double c1 = (tes[2 * p + 1] + gz.y) * inv_m;
+        ss += c1 * c1;
+      }
+    }
+    __syncthreads();
+  }
+  return ss;
+}
+
+template <int LH>
+__device__ __forceinline__ void gs_segment(const GsItem &it, const GsSeg &sd, int64_t b, double2 *X,
+                                           double *__restrict__ tes, double &qacc) {
+  const double s1 = gs_sumsq<LH>(it, sd, b, (const double2 *)sd.M1, X, tes);
+  const double s2 = gs_sumsq<LH>(it, sd, b, (const double2 *)sd.M2, X, tes);
+  qacc += (s1 - s2) * sd.inv_x0;
+}
+
+__global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ items,
+                                                   const int2 *__restrict__ work, int64_t n_work,
+                                                   double *__restrict__ scratch, int64_t stride) {
+  extern __shared__ double2 rl_smem[];
+  double2 *X = rl_smem;
+  double *red = (double *)(rl_smem + RL_XN);
+  double *tes = scratch + (int64_t)blockIdx.x * stride;
+  for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+    const int2 wk = work[wi];
+    const GsItem &it = items[wk.x];
+    const int64_t b = wk.y;
+    double qp = 0.0;
+    bool bad = false;
+    for (int sg = 0; sg < it.n_segs; ++sg) {
+      const GsSeg sd = it.segs[sg];
+      switch (sd.log2m - 2) {
+#define TDA_GS(LH) \
+  case LH: gs_segment<LH>(it, sd, b, X, tes, qp); break;
+        TDA_GS(2) TDA_GS(3) TDA_GS(4) TDA_GS(5) TDA_GS(6) TDA_GS(7) TDA_GS(8) TDA_GS(9)
+        TDA_GS(10) TDA_GS(11) TDA_GS(12) TDA_GS(13)
+#undef TDA_GS
+        default: bad = true;
+      }
+    }
+    const double q = block_sum(bad ? __builtin_nan("") : qp, red);
+    if (threadIdx.x == 0) it.out[b] = -0.5 * q + it.cterm;
+  }
+}
+
+hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
+                     int64_t scratch_stride, int32_t n_wg, hipStream_t s) {
+  if (n_work <= 0) return hipSuccess;
+  const int64_t g = std::min<int64_t>(n_work, n_wg);
+  hipLaunchKernelGGL(k_gs, dim3((unsigned)g), dim3(RL_THREADS), RL_LDS_BYTES, s, items, work, n_work,
+                     scratch, scratch_stride);
+  return hipGetLastError();
+}
+
+void register_mixed_attributes() {
+  hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)RL_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_gs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)RL_LDS_BYTES);
+  hipFuncSetAttribute((const void *)k_levinson, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)(RL_MAX_LEV * sizeof(double)));
 }
 
 }  // namespace tda

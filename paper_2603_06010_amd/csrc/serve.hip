@@ -285,7 +285,8 @@ extern "C" tda_status tda_server_create(const tda_server_options *opt, tda_serve
   if (opt->struct_size < sizeof(tda_server_options)) return set_error(TDA_EINVAL, "struct_size");
   if (opt->n_slots < 1 || opt->n_slots > 16 || opt->max_batch < 1 || opt->max_queue < 1)
     return set_error(TDA_EINVAL, "n_slots in [1,16], max_batch >= 1, max_queue >= 1");
-  if (opt->precision != TDA_PREC_FP64 && opt->precision != TDA_PREC_MIXED)
+  if (opt->precision != TDA_PREC_FP64 && opt->precision != TDA_PREC_MIXED &&
+      opt->precision != TDA_PREC_GS)
     return set_error(TDA_EINVAL, "unknown precision");
   *out = nullptr;
   tda_server *s = new tda_server();

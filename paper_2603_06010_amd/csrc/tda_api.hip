@@ -214,6 +214,12 @@ struct tda_ctx {
   DevBuf dbar_d, yd_d, ydpos_d, qdd_d;
   const double *data_ptr = nullptr;
 
+  // Gohberg-Semencul state: per segment twiddles, pass twiddles, the two spectra and
+  // x = C^-1 e_1; descriptors; Levinson outputs
+  DevBuf gs_tab_d, gs_seg_d, gs_lev_d;
+  std::vector<GsSeg> gs_seg_h;
+  int64_t gs_max_len = 0;
+
   // workspaces
   DevBuf ws_scratch, ws_tiles, ws_items;
   DevBuf ws_hs_hi, ws_hs_lo, ws_w0_hi, ws_w0_lo, ws_y0, ws_fft, ws_work, ws_mix, ws_ref;
@@ -264,7 +270,8 @@ struct tda_ctx {
                      &wb_hi,   &wb_lo,    &wa_off_d,   &wb_off_d,    &lam_d,      &tw_d,
                      &segdev_d, &dbar_d,  &yd_d,       &ydpos_d,     &qdd_d,      &ws_scratch,
                      &ws_tiles, &ws_items, &ws_hs_hi,  &ws_hs_lo,    &ws_w0_hi,   &ws_w0_lo,
-                     &ws_y0,   &ws_fft,   &ws_work,    &ws_mix,      &ws_ref};
+                     &ws_y0,   &ws_fft,   &ws_work,    &ws_mix,      &ws_ref,     &gs_tab_d,
+                     &gs_seg_d, &gs_lev_d};
     for (DevBuf *b : all) release(*b);
   }
   double cterm() const { return -0.5 * logdet - 0.5 * (double)n_eff * kLog2Pi; }
@@ -326,7 +333,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     if (opt->struct_size < sizeof(tda_options)) return fail_with(TDA_EINVAL, "options struct_size");
     o = *opt;
   }
-  if (o.precision != TDA_PREC_FP64 && o.precision != TDA_PREC_MIXED)
+  if (o.precision != TDA_PREC_FP64 && o.precision != TDA_PREC_MIXED && o.precision != TDA_PREC_GS)
     return fail_with(TDA_EINVAL, "unknown precision %d", o.precision);
   if (o.flags & ~TDA_FLAG_COMPACT) return fail_with(TDA_EINVAL, "unknown flags");
   int ndev = 0;
@@ -433,17 +440,30 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
       (st = upload(h, h->blk_last_d, h->blk_last_h.data(), h->nblk * sizeof(int32_t))) != TDA_OK ||
       (st = upload(h, h->panel_off_d, h->panel_off_h.data(), h->nblk * sizeof(int64_t))) != TDA_OK)
     return cleanup(st);
-  // dense blocks (lower triangle used), assembled now
-  size_t dense = 0;
-  for (const Seg &g : h->segs) dense += (size_t)g.n_pad * g.n_pad;
-  if ((st = h->alloc(h->A_d, dense * sizeof(double))) != TDA_OK) return cleanup(st);
-  size_t a_off = 0;
-  for (const Seg &g : h->segs) {
-    hipError_t e = launch_assemble((const double *)h->acf_d.p, (const int32_t *)h->idx_d.p + g.row0,
-                                   g.n_keep, g.n_pad, (double *)h->A_d.p + a_off, 0);
-    if (e != hipSuccess)
-      return cleanup(fail_with(TDA_EHIP, "assemble launch: %s", hipGetErrorString(e)));
-    a_off += (size_t)g.n_pad * g.n_pad;
+  if (h->precision == TDA_PREC_GS) {
+    // Gohberg-Semencul needs each segment Toeplitz (no excluded sample inside it)
+    for (size_t si = 0; si < h->segs.size(); ++si) {
+      const Seg &g = h->segs[si];
+      if (g.n_keep != g.length)
+        return cleanup(fail_with(TDA_EINVAL, "GS precision: segment %zu has excluded samples", si));
+      if (g.length > RL_MAX_LEV)
+        return cleanup(fail_with(TDA_EINVAL, "GS precision: segment %zu is longer than %d samples",
+                                 si, RL_MAX_LEV));
+    }
+  } else {
+    // dense blocks (lower triangle used), assembled now
+    size_t dense = 0;
+    for (const Seg &g : h->segs) dense += (size_t)g.n_pad * g.n_pad;
+    if ((st = h->alloc(h->A_d, dense * sizeof(double))) != TDA_OK) return cleanup(st);
+    size_t a_off = 0;
+    for (const Seg &g : h->segs) {
+      hipError_t e = launch_assemble((const double *)h->acf_d.p,
+                                     (const int32_t *)h->idx_d.p + g.row0, g.n_keep, g.n_pad,
+                                     (double *)h->A_d.p + a_off, 0);
+      if (e != hipSuccess)
+        return cleanup(fail_with(TDA_EHIP, "assemble launch: %s", hipGetErrorString(e)));
+      a_off += (size_t)g.n_pad * g.n_pad;
+    }
   }
   hipError_t e = hipDeviceSynchronize();
   if (e != hipSuccess) return cleanup(fail_with(TDA_EHIP, "assemble: %s", hipGetErrorString(e)));
@@ -454,10 +474,17 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
 // ---------------------------------------------------------------- factor
 
 static tda_status build_mixed(tda_ctx *h);
+static tda_status build_gs(tda_ctx *h);
 
 extern "C" tda_status tda_factor(tda_handle h) {
   if (!h) return fail_with(TDA_EINVAL, "NULL handle");
   if (h->factored) return TDA_OK;
+  if (h->precision == TDA_PREC_GS) {
+    DeviceGuard guard(h->device);
+    TDA_TRY(build_gs(h));
+    h->factored = true;
+    return TDA_OK;
+  }
   if (!h->A_d.p) return fail_with(TDA_ESTATE, "handle has no assembled covariance");
   DeviceGuard guard(h->device);
   int64_t ncp = 0;
@@ -505,6 +532,110 @@ extern "C" tda_status tda_factor(tda_handle h) {
   return TDA_OK;
 }
 
+// ---------------------------------------------------------------- Gohberg-Semencul set-up
+
+// Per segment (tables in doubles): twiddles w_m^r (2m), pass twiddles (2 m/4), the two
+// correlation spectra (2m each) and x = C^-1 e_1 (length).
+static tda_status build_gs(tda_ctx *h) {
+  const size_t ns = h->segs.size();
+  std::vector<size_t> base(ns);
+  size_t tot = 0;
+  for (size_t si = 0; si < ns; ++si) {
+    const Seg &g = h->segs[si];
+    base[si] = tot;
+    tot += (size_t)(2 * g.m + 2 * (g.m / 4) + 4 * g.m + g.length);
+  }
+  TDA_TRY(h->alloc(h->gs_tab_d, tot * sizeof(double)));
+  TDA_TRY(h->alloc(h->gs_lev_d, ns * (sizeof(double) + sizeof(int32_t))));
+  double *tab = (double *)h->gs_tab_d.p;
+  double *ld_d = (double *)h->gs_lev_d.p;
+  int32_t *fail_d = (int32_t *)(ld_d + ns);
+  for (size_t si = 0; si < ns; ++si) {
+    const Seg &g = h->segs[si];
+    double *tw = tab + base[si], *ptw = tw + 2 * g.m, *M1 = ptw + 2 * (g.m / 4), *M2 = M1 + 2 * g.m;
+    double *x = M2 + 2 * g.m;
+    HIP_TRY(launch_lambda((const double *)h->acf_d.p, g.length, g.m, tw, nullptr, ptw, 0));
+    HIP_TRY(launch_levinson((const double *)h->acf_d.p, g.length, x, ld_d + si, fail_d + si, 0));
+    HIP_TRY(launch_gs_spectra(x, g.length, g.m, tw, M1, M2, 0));
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<double> ld(ns);
+  std::vector<int32_t> fail(ns);
+  HIP_TRY(hipMemcpy(ld.data(), ld_d, ns * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(fail.data(), fail_d, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+  h->gs_seg_h.clear();
+  h->logdet = 0.0;
+  h->gs_max_len = 0;
+  h->max_m = 0;
+  for (size_t si = 0; si < ns; ++si) {
+    const Seg &g = h->segs[si];
+    if (fail[si] >= 0) {
+      h->fail_row = fail[si];
+      h->fail_segment = (int32_t)si;
+      return fail_with(TDA_ENOTSPD,
+                       "covariance not positive definite: Levinson order %d of segment %zu",
+                       fail[si], si);
+    }
+    double *tw = tab + base[si], *ptw = tw + 2 * g.m, *M1 = ptw + 2 * (g.m / 4), *M2 = M1 + 2 * g.m;
+    double x0 = 0.0;
+    HIP_TRY(hipMemcpy(&x0, M2 + 2 * g.m, sizeof(double), hipMemcpyDeviceToHost));
+    if (!(x0 > 0.0) || !isfinite(x0)) return fail_with(TDA_ENOTSPD, "segment %zu: (C^-1)_00 = %g", si, x0);
+    GsSeg sd{};
+    sd.offset = g.offset;
+    sd.length = g.length;
+    sd.m = g.m;
+    sd.log2m = g.log2m;
+    sd.inv_x0 = 1.0 / x0;
+    sd.tw = tw;
+    sd.ptw = ptw;
+    sd.M1 = M1;
+    sd.M2 = M2;
+    h->gs_seg_h.push_back(sd);
+    h->logdet += ld[si];
+    h->gs_max_len = std::max(h->gs_max_len, g.length);
+    h->max_m = std::max(h->max_m, g.m);
+  }
+  if (!isfinite(h->logdet)) return fail_with(TDA_ENOTSPD, "log det is not finite");
+  TDA_TRY(upload(h, h->gs_seg_d, h->gs_seg_h.data(), ns * sizeof(GsSeg)));
+  return TDA_OK;
+}
+
+constexpr int32_t kGsWG = 1024;  // persistent Gohberg-Semencul workgroups (one per CU runs at once)
+
+static GsItem make_gs_item(const tda_ctx *h, const double *d, const double *H, int64_t ldh,
+                           int64_t B, double *out) {
+  GsItem it{};
+  it.segs = (const GsSeg *)h->gs_seg_d.p;
+  it.n_segs = (int32_t)h->gs_seg_h.size();
+  it.B = (int32_t)B;
+  it.d = d;
+  it.H = H;
+  it.ldh = ldh;
+  it.out = out;
+  it.cterm = h->cterm();
+  return it;
+}
+
+static tda_status loglik_gs(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
+                            double *out, hipStream_t s) {
+  const int32_t n_wg = (int32_t)std::min<int64_t>(B, kGsWG);
+  TDA_TRY(h->alloc(h->ws_fft, (size_t)n_wg * h->gs_max_len * sizeof(double)));
+  const GsItem it = make_gs_item(h, d, H, ldh, B, out);
+  std::vector<int2> work((size_t)B);
+  for (int64_t b = 0; b < B; ++b) work[b] = int2{0, (int32_t)b};
+  HIP_TRY(h->ring.reserve(1024 + sizeof(GsItem) + work.size() * sizeof(int2)));
+  void *d_it, *d_w;
+  HIP_TRY(h->ring.push(&it, sizeof(GsItem), s, &d_it));
+  HIP_TRY(h->ring.push(work.data(), work.size() * sizeof(int2), s, &d_w));
+  {
+    TimedScope ts("gs_fft", s);
+    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, B, (double *)h->ws_fft.p,
+                      h->gs_max_len, n_wg, s));
+  }
+  HIP_TRY(h->ring.seal(s));
+  return TDA_OK;
+}
+
 // ---------------------------------------------------------------- FP64 evaluation
 
 static tda_status loglik_f64(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
@@ -544,10 +675,12 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
   if (B > (int64_t)1 << 30) return fail_with(TDA_EINVAL, "B too large");
   if (!d || !H || !out) return fail_with(TDA_EINVAL, "NULL device pointer");
   if (ldh < h->N) return fail_with(TDA_EINVAL, "ldh < N");
-  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED)
+  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED && precision != TDA_PREC_GS)
     return fail_with(TDA_EINVAL, "unknown precision");
   if (precision == TDA_PREC_MIXED && h->precision != TDA_PREC_MIXED)
     return fail_with(TDA_ESTATE, "mixed evaluation needs a handle built with TDA_PREC_MIXED");
+  if ((precision == TDA_PREC_GS) != (h->precision == TDA_PREC_GS))
+    return fail_with(TDA_ESTATE, "a GS handle evaluates only (and only it) in TDA_PREC_GS");
   if (h->compacted && (precision == TDA_PREC_FP64 || d != h->data_ptr))
     return fail_with(TDA_ESTATE, "compact handle: only mixed evaluation with its cached data");
   DeviceGuard guard(h->device);
@@ -559,6 +692,8 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
   TDA_TRY(order_after_previous(h, s));
   if (precision == TDA_PREC_FP64)
     TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
+  else if (precision == TDA_PREC_GS)
+    TDA_TRY(loglik_gs(h, d, H, B, ldh, out, s));
   else
     TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s));
   return mark_done(h, s);
@@ -1056,8 +1191,9 @@ int64_t handle_n(tda_handle h) { return h->N; }
 size_t handle_bytes(tda_handle h) { return h->held; }
 bool handle_ready(tda_handle h, int32_t precision) {
   if (!h->factored) return false;
+  if ((precision == TDA_PREC_GS) != (h->precision == TDA_PREC_GS)) return false;
   if (precision == TDA_PREC_FP64) return !h->compacted;
-  return h->precision == TDA_PREC_MIXED;
+  return h->precision == precision;
 }
 tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s) {
   if (h->precision != TDA_PREC_MIXED || h->data_ptr == d) return TDA_OK;
@@ -1081,7 +1217,7 @@ namespace {
 tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
                       int64_t n_items, int32_t precision, hipStream_t s, bool order_handles) {
   if (n_items == 0) return TDA_OK;
-  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED)
+  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED && precision != TDA_PREC_GS)
     return fail_with(TDA_EINVAL, "unknown precision");
   const int dev = items[0].h ? items[0].h->device : -1;
   std::vector<double *> group_out;
@@ -1100,6 +1236,9 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
     if (w.ldh < w.h->N) return fail_with(TDA_EINVAL, "item %lld: ldh < N", (long long)k);
     if (precision == TDA_PREC_MIXED && w.h->precision != TDA_PREC_MIXED)
       return fail_with(TDA_ESTATE, "item %lld: handle not built for mixed precision", (long long)k);
+    if ((precision == TDA_PREC_GS) != (w.h->precision == TDA_PREC_GS))
+      return fail_with(TDA_ESTATE, "item %lld: GS handles evaluate only (and only they) in GS",
+                       (long long)k);
     if (w.h->compacted && (precision == TDA_PREC_FP64 || w.d != w.h->data_ptr))
       return fail_with(TDA_ESTATE, "item %lld: compact handle used beyond its cached data",
                        (long long)k);
@@ -1139,7 +1278,28 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
   TDA_TRY(P.alloc(P.ws_work, (size_t)parts * sizeof(double)));
   double *partbuf = (double *)P.ws_work.p;
   std::vector<void *> blobs;
-  if (precision == TDA_PREC_FP64) {
+  if (precision == TDA_PREC_GS) {
+    std::vector<GsItem> gis(n_items);
+    std::vector<int2> work;
+    int64_t max_len = 0;
+    for (int64_t k = 0; k < n_items; ++k) {
+      const tda_work &w = items[k];
+      gis[k] = make_gs_item(w.h, w.d, w.H, w.ldh, w.B, partbuf + part_off[k]);
+      gis[k].Hrows = hrows ? hrows[k] : nullptr;
+      max_len = std::max(max_len, w.h->gs_max_len);
+      for (int64_t b = 0; b < w.B; ++b) work.push_back(int2{(int32_t)k, (int32_t)b});
+    }
+    const int32_t n_wg = (int32_t)std::min<int64_t>((int64_t)work.size(), kGsWG);
+    TDA_TRY(P.alloc(P.ws_fft, (size_t)n_wg * max_len * sizeof(double)));
+    HIP_TRY(mc->ring.reserve(4096 + gis.size() * sizeof(GsItem) + work.size() * sizeof(int2) +
+                             n_items * 16 + group_out.size() * 16));
+    void *d_it, *d_w;
+    HIP_TRY(mc->ring.push(gis.data(), gis.size() * sizeof(GsItem), s, &d_it));
+    HIP_TRY(mc->ring.push(work.data(), work.size() * sizeof(int2), s, &d_w));
+    TimedScope ts("gs_fft", s);
+    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, (int64_t)work.size(),
+                      (double *)P.ws_fft.p, max_len, n_wg, s));
+  } else if (precision == TDA_PREC_FP64) {
     std::vector<TrsmItem> its(n_items);
     std::vector<TrsmTile> tiles;
     int64_t scratch = 0;

@@ -212,6 +212,47 @@ void register_mixed_attributes();
 // work entries (item, template a, template b or -1, 0): two templates share one DFT
 hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s);
+// Gohberg-Semencul evaluation (segments without excluded samples, m <= RL_MAX_M).
+struct GsSeg {
+  int64_t offset, length;  // sample range of the segment (all samples retained)
+  int64_t m;               // circulant length (power of two >= 2 length)
+  int32_t log2m;
+  int32_t pad0;
+  double inv_x0;           // 1 / (C^-1)_00
+  const double *tw;        // [2m] cos/sin of 2 pi r / m
+  const double *ptw;       // pass twiddles of the m/4-point DFT
+  const double *M1, *M2;   // [2m] conj(DFT_m) of x = C^-1 e_1 and of (0, x_{n-1}, ..., x_1)
+};
+
+struct GsItem {
+  const GsSeg *segs;
+  int32_t n_segs;
+  int32_t B;
+  const double *d;                 // [N] data
+  const double *H;                 // templates, rows of stride ldh
+  int64_t ldh;
+  const double *const *Hrows;      // optional per-template row pointers
+  double *out;                     // [B] -q/2 + cterm
+  double cterm;
+};
+
+__device__ __forceinline__ const double *gs_template_row(const GsItem &it, int64_t b) {
+  return it.Hrows ? it.Hrows[b] : it.H + b * it.ldh;
+}
+
+// Levinson-Durbin for the first column of the inverse of the symmetric Toeplitz matrix
+// with first column acf[0..n): x = C^-1 e_1, log det C = sum log E_k; *fail = first k with
+// E_k <= 0 or not finite (else -1).  One workgroup; n <= RL_MAX_LEV.
+constexpr int RL_MAX_LEV = 16384;
+hipError_t launch_levinson(const double *acf, int64_t n, double *x, double *logdet,
+                           int32_t *fail, hipStream_t s);
+// conj(DFT_m) of x zero-padded and of (0, x_{n-1}, ..., x_1) zero-padded
+hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double *tw,
+                             double *M1, double *M2, hipStream_t s);
+// q_b over the segments of each item, out[b] = -q_b/2 + cterm; work entries (item, b)
+hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
+                     int64_t scratch_stride, int32_t n_wg, hipStream_t s);
+
 // In-LDS refinement for launches whose segments all have m <= RL_MAX_M; work entries
 // (item, template).
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,

@@ -1,0 +1,109 @@
+"""Gohberg-Semencul FP64 path (segments without excluded samples) against the FP64
+oracle through the C ABI.
+
+q = (||L(x)^T r||^2 - ||L(z)^T r||^2) / x_0 with x = C^-1 e_1 from Levinson-Durbin and
+both products by FFT.  It is an FP64 method; the subtraction of two quadratic forms
+loses about log10(kappa(C)) digits relative to them, so the tolerance is the FP64 one
+scaled by 10: |dlogL| <= 1e-5 + 2e-8 |logL| (kappa(C) ~ 3e6 at nugget 1e-6).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def TOLGS(want):
+    return 1e-5 + 2e-8 * np.abs(want)
+
+
+@pytest.fixture(scope="module")
+def tda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_06010_amd as tda
+    tda.load_library()
+    return tda
+
+
+@pytest.mark.parametrize("N,B,segments,eps", [
+    (1024, 32, None, 1e-6),
+    (3000, 200, None, 1e-6),
+    (4096, 65, None, 1e-6),
+    (2600, 130, [(0, 1000), (1200, 1300), (2550, 50)], 1e-6),
+    (700, 17, [(0, 5), (5, 695)], 1e-6),
+    (2048, 16, None, 1e-4),
+    (16, 3, None, 1e-6),
+])
+def test_gs_parity(tda, N, B, segments, eps):
+    from gpu_util import to_dev
+    print(f"case N={N} B={B} segments={segments}", flush=True)
+    inst = synth.random_rhs_case(500 + N + B, N, 1, 0, B, eps=eps, segments=segments)
+    h = tda.Handle(inst.acf, N, None, segments, precision="gs").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    got = h.loglik(d, H).cpu().numpy()
+    f = oracle.factor(inst.acf, N, None, segments)
+    want = oracle.loglik(f, inst.d[0], inst.H)
+    assert abs(h.info()["logdet"] - f.logdet) < 1e-9 * abs(f.logdet) + 1e-9
+    assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+    h.close()
+
+
+def test_gs_full_size_and_vs_fp64(tda):
+    """Two detectors x N = 16384 (the benchmark shape), 256 templates: GS vs the FP64
+    Cholesky path on the GPU, and vs the oracle on a sample."""
+    from gpu_util import to_dev
+    import torch
+    w = synth.c2_workload(B=256, n=16384)
+    inst = w.instances[0]
+    H = to_dev(inst.H)
+    out = {p: torch.empty(inst.B, dtype=torch.float64, device="cuda") for p in ("gs", "fp64")}
+    hs = {p: [tda.Handle(inst.acf, inst.N, inst.masks[k], precision=p).factor()
+              for k in range(inst.n_det)] for p in out}
+    ds = [to_dev(x) for x in inst.d]
+    for p in out:
+        tda.loglik_multi([(h, dk, H, out[p]) for h, dk in zip(hs[p], ds)], precision=p)
+    torch.cuda.synchronize()
+    g, f = out["gs"].cpu().numpy(), out["fp64"].cpu().numpy()
+    assert np.all(np.abs(g - f) <= TOLGS(f)), np.max(np.abs(g - f))
+    facs = [oracle.factor(inst.acf, inst.N, inst.masks[k]) for k in range(inst.n_det)]
+    want = oracle.loglik_network(facs, inst.d, inst.H[:8])
+    assert np.all(np.abs(g[:8] - want) <= TOLGS(want)), np.max(np.abs(g[:8] - want))
+    for p in hs:
+        for h in hs[p]:
+            h.close()
+
+
+def test_gs_errors_and_isolation(tda):
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(77, 1500, 1, 2, 20)
+    # excluded samples inside a segment: not Toeplitz
+    with pytest.raises(tda.TdaError) as e:
+        tda.Handle(inst.acf, inst.N, inst.masks[0], precision="gs")
+    assert e.value.status == 1
+    # not positive definite: Levinson reports the failing order
+    bad = np.zeros(64); bad[0] = 1.0; bad[1] = 0.9; bad[2] = -0.9
+    hb = tda.Handle(bad, 64, None, precision="gs")
+    with pytest.raises(tda.TdaError) as e:
+        hb.factor()
+    assert e.value.status == 2 and hb.info()["fail_row"] >= 1
+    hb.close()
+    # a GS handle evaluates only in GS
+    h = tda.Handle(inst.acf, inst.N, None, precision="gs").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    with pytest.raises(tda.TdaError):
+        h.loglik(d, H, precision="fp64")
+    # NaN in one template stays in that template
+    base = h.loglik(d, H).cpu().numpy()
+    H2 = H.clone(); H2[3, 17] = float("nan")
+    r2 = h.loglik(d, H2).cpu().numpy()
+    assert np.isnan(r2[3]) and np.array_equal(np.delete(r2, 3), np.delete(base, 3))
+    # batch composition does not change a template's result (one template per workgroup)
+    sub = h.loglik(d, H[5:9].contiguous()).cpu().numpy()
+    np.testing.assert_array_equal(sub, base[5:9])
+    torch.cuda.synchronize()
+    h.close()
