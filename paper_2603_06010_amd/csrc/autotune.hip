@@ -59,6 +59,12 @@ int autotune_pick(const char *kernel, int64_t rows, int64_t templates, const int
                   int n_variants, hipStream_t s, hipError_t (*launch)(void *ctx, int variant),
                   void *ctx) {
   Tuner &t = tuner();
+  // TDA_PRODUCT_VARIANT=<v> forces variant v of every tuned kernel that has one
+  if (const char *force = getenv("TDA_PRODUCT_VARIANT")) {
+    const int v = atoi(force);
+    for (int k = 0; k < n_variants; ++k)
+      if (variants[k] == v) return v;
+  }
   const char *env = getenv("TDA_AUTOTUNE");
   if (n_variants <= 1 || (env && env[0] == '0')) return variants[0];
   std::lock_guard<std::mutex> lk(t.mu);

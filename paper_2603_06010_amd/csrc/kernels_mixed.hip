@@ -26,12 +26,9 @@ __device__ __forceinline__ f16v mfma_bf16(bf8 a, bf8 b, f16v c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// round-to-nearest-even FP32 -> BF16 bits (NaN kept NaN)
+// round-to-nearest-even FP32 -> BF16 bits (NaN kept NaN): the hardware conversion
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
@@ -289,15 +286,18 @@ hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chu
 // A workgroup computes a tile of D = A B over K = 16 nks; A and B are given as fragment
 // arrays: A tile t (32 rows) at k-step ks is at A + t s_tile + ks s_ks.  Every product is
 // hi*hi + hi*lo + lo*hi with FP32 accumulation.  Variants (picked per shape by the
-// autotuner); operands go straight from memory into registers:
+// autotuner):
 //   1: 4 waves, wave tile 4 A x 4 B tiles (128 x 128), workgroup 256 x 256, loads one
-//      k-step ahead; one wave per SIMD (accumulators in AGPRs).
+//      k-step ahead straight into registers; one wave per SIMD (accumulators in AGPRs).
 //   2: 4 waves, wave tile 4 x 2, workgroup 256 x 128 (half a template group); two
 //      workgroups per CU, so two waves per SIMD hide each other's latency.
 //   4: as 1 with three register stages (loads two k-steps ahead).
-// Staging the operands through LDS with direct global -> LDS loads (one fetch per
-// workgroup instead of per wave pair) measured slower than all three on gfx950, even with
-// every operand cache-resident, and is not kept.
+//   5: 8 waves (two per SIMD), wave tile 4 x 2, workgroup 256 x 256.  Each k-step's 32
+//      fragments go once per workgroup from memory into a 4-stage LDS ring (direct
+//      global -> LDS loads, three k-steps ahead), and every wave reads its 12 fragments of
+//      the next k-step from LDS while its matrix-core ops work on the current one.  The
+//      register variants fetch each fragment twice per workgroup (two waves share every A
+//      and every B tile), which keeps the vector-memory path busier than the matrix cores.
 struct FragSrc {
   const uint16_t *hi, *lo;
   int64_t s_tile, s_ks;  // element strides between tiles and between k-steps
@@ -307,16 +307,19 @@ constexpr int FRAG = 512;  // bf16 elements per fragment (64 lanes x 8)
 
 // Layout of variant V: waves per workgroup, B tiles per wave, whether a workgroup covers
 // a whole group of 256 templates (else half, chosen by the work entry's `sub`), register
-// stages, workgroups per CU, and the wave's first A and B tile.
+// stages, workgroups per CU, waves per SIMD, LDS stages, and the wave's first A and B tile.
 template <int V>
 struct PL {
-  static constexpr int NW = 4;
-  static constexpr int WB = V == 2 ? 2 : 4;
+  static constexpr int NW = V == 5 ? 8 : 4;
+  static constexpr int WB = V == 2 || V == 5 ? 2 : 4;
   static constexpr bool FULL = V != 2;
   static constexpr int RST = V == 4 ? 3 : 2;
   static constexpr int OCC = V == 2 ? 2 : 1;
-  __device__ static int ta(int w) { return 4 * (w >> 1); }
-  __device__ static int tb(int w) { return WB * (w & 1); }
+  static constexpr int WPS = NW * OCC / 4;
+  static constexpr int LDS_STAGES = V == 5 ? 4 : 0;
+  __device__ static int ta(int w) { return NW == 8 ? 4 * (w >> 2) : 4 * (w >> 1); }
+  __device__ static int tb(int w) { return NW == 8 ? 2 * (w & 3) : WB * (w & 1); }
+  static constexpr size_t lds_bytes() { return (size_t)LDS_STAGES * 32 * FRAG * 2; }
 };
 
 template <int WB>
@@ -378,8 +381,7 @@ __device__ __forceinline__ void zero_acc(f16v (&acc)[4][WB]) {
 // last k-step), so the compiler's wait counts leave the later stages in flight.
 template <int NPROD, int WB, int NST>
 __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int ta, int tb,
-                                      int64_t nks, f16v (&acc)[4][WB]) {
-  const int lane = threadIdx.x & 63;
+                                      int64_t nks, int lane, f16v (&acc)[4][WB]) {
   zero_acc<WB>(acc);
   if (nks <= 0) return;
   Step<WB> st[NST];
@@ -410,50 +412,173 @@ __device__ __forceinline__ void gemm3(const FragSrc &A, const FragSrc &B, int ta
     if (u < rem) mma_step<NPROD, WB>(st[u], acc);
 }
 
+// LDS path (variant 5).  A stage holds one k-step's 32 fragments: A hi tiles 0-7, A lo
+// 0-7, B hi 0-7, B lo 0-7 of the workgroup's window; wave w copies fragments 4w .. 4w + 3
+// (one quarter of one of the four arrays).  Loads past the last k-step are clamped to it
+// (their stage is never read), so every k-step issues the same four copies and the wait
+// counts are constants.  The barrier at k-step t follows the wave's wait for its copies of
+// stage t + 1: after it stage t + 1 is complete for every wave and stage t - 1, which the
+// new copies overwrite, has been read by all of them.
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int WB>
+__device__ __forceinline__ void lds_read_step(const char *stage, int ta, int tb, int lane,
+                                              Step<WB> &st) {
+  const bf8 *S = (const bf8 *)stage;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) st.ah[a] = S[(ta + a) * 64 + lane];
+#pragma unroll
+  for (int b = 0; b < WB; ++b) st.bh[b] = S[(16 + tb + b) * 64 + lane];
+#pragma unroll
+  for (int b = 0; b < WB; ++b) st.bl[b] = S[(24 + tb + b) * 64 + lane];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) st.al[a] = S[(8 + ta + a) * 64 + lane];
+}
+
 template <int NPROD, int V>
-__device__ __forceinline__ void gemm3_v(const FragSrc &A, const FragSrc &B, int64_t nks,
+__device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int64_t nks, int tid,
+                                         f16v (&acc)[4][PL<V>::WB], char *smem) {
+  using L = PL<V>;
+  constexpr int NS = L::LDS_STAGES, SB = 32 * FRAG * 2;
+  static_assert(L::NW == 8 && NS == 4, "LDS path: 8 waves, 4 stages");
+  const int lane = tid & 63, w = tid >> 6;
+  const int ta = L::ta(w), tb = L::tb(w);
+  // this wave's copies: array w >> 1, tiles 4 (w & 1) .. + 3
+  const int arr = w >> 1;
+  const bool isA = arr < 2;
+  const uint16_t *src = arr == 0 ? A.hi : arr == 1 ? A.lo : arr == 2 ? B.hi : B.lo;
+  const int64_t s_tile = isA ? A.s_tile : B.s_tile, s_ks = isA ? A.s_ks : B.s_ks;
+  const uint16_t *gp = src + 4 * (w & 1) * s_tile + lane * 8;
+  char *const dst0 = smem + 4 * w * 1024;
+  auto issue = [&](int64_t ks, int slot) __attribute__((always_inline)) {
+    const uint16_t *q = gp + (ks < nks ? ks : nks - 1) * s_ks;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      __builtin_amdgcn_global_load_lds((const void *)(q + u * s_tile),
+                                       (lds_void_t *)(dst0 + slot * SB + u * 1024), 16, 0, 0);
+  };
+  zero_acc<L::WB>(acc);
+  if (nks <= 0) return;
+  issue(0, 0);
+  issue(1, 1);
+  issue(2, 2);
+  wait_vmcnt<8>();
+  __builtin_amdgcn_s_barrier();
+  Step<L::WB> r0, r1;
+  lds_read_step<L::WB>(smem, ta, tb, lane, r0);
+  // one k-step: wait for stage t + 1, barrier, copies for stage t + 3, LDS reads of stage
+  // t + 1 spread through the matrix-core ops of stage t
+  auto kstep = [&](int64_t t, const Step<L::WB> &cur, Step<L::WB> &nxt) __attribute__((always_inline)) {
+    wait_vmcnt<4>();
+    __builtin_amdgcn_s_barrier();
+    issue(t + 3, (int)((t + 3) & 3));
+    lds_read_step<L::WB>(smem + ((t + 1) & 3) * SB, ta, tb, lane, nxt);
+    mma_step<NPROD, L::WB>(cur, acc);
+    // matrix-core ops first: their operands were read a k-step ago, so the wait for them
+    // does not also wait for the reads of the next stage
+    constexpr int NR = 4 + 2 * L::WB + 4, NM = NPROD * 4 * L::WB;
+    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);        // the four copies
+    __builtin_amdgcn_sched_group_barrier(0x008, NM / NR, 0);  // matrix-core ops
+#pragma unroll
+    for (int q = 0; q < NR - 1; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);        // one LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, NM / NR, 0);  // then matrix-core ops
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  int64_t t = 0;
+  for (; t + 2 <= nks; t += 2) {
+    kstep(t, r0, r1);
+    kstep(t + 1, r1, r0);
+  }
+  if (t < nks) mma_step<NPROD, L::WB>(r0, acc);
+  // no copy may still be landing in LDS when the workgroup reuses or releases it
+  wait_vmcnt<0>();
+  __builtin_amdgcn_s_barrier();
+}
+
+template <int NPROD, int V>
+__device__ __forceinline__ void gemm3_v(const FragSrc &A, const FragSrc &B, int64_t nks, int tid,
                                         f16v (&acc)[4][PL<V>::WB]) {
   using L = PL<V>;
-  const int w = threadIdx.x >> 6;
-  gemm3<NPROD, L::WB, L::RST>(A, B, L::ta(w), L::tb(w), nks, acc);
+  if constexpr (L::LDS_STAGES > 0) {
+    extern __shared__ char gp_smem[];
+    gemm_lds<NPROD, V>(A, B, nks, tid, acc, gp_smem);
+  } else {
+    const int w = tid >> 6;
+    gemm3<NPROD, L::WB, L::RST>(A, B, L::ta(w), L::tb(w), nks, tid & 63, acc);
+  }
+}
+
+// The thread index behind a barrier the compiler cannot see through.  Each block of a pair
+// derives its lane-dependent addresses from its own read, so none are kept live across the
+// other block's product, where they would spill registers.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // Work entries (item, block, group of 256 templates, sub): half-group variants take the
 // half `sub`; full-group variants cover both halves at sub = 0 and skip sub = 1.
+//
+// Block pairs.  In a segment of nb blocks the products over block l (local index) run
+// over l + 1 blocks of K (forward, correction) or nb - l (backward), so a workgroup per
+// block would see lengths from 1 to nb and start at staggered times, which defeats the
+// L2 sharing of the work order.  A workgroup instead takes block l and its partner
+// nb - 1 - l (the middle block of an odd segment alone): every pair spans nb + 1 blocks of
+// K.  The second block's K range is walked in the opposite direction, which lines the
+// walks up in time: at a given k-step of their run, all workgroups of a segment read one
+// of just two template k-steps, whichever pair they hold.  The entry names the first
+// block of the pair (the lower index); `ph` selects the first (0) or second (1) block.
+__device__ __forceinline__ int pair_blocks(const MixItem &it, int first) {
+  return it.blk_first[first] + it.blk_last[first] - first != first ? 2 : 1;
+}
 
 // w0 = W h: rows of row block i (A = F(W)), templates of the group (B = F(Hs)); w0 is
-// written in F(w0^T).
-template <int V>
-__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_fwd(
-    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+// written in F(w0^T).  The first block of the pair walks K upwards, its partner downwards.
+template <int V, int ph>
+__device__ __forceinline__ void fwd_block(const MixItem *items, const int4 *work) {
   using L = PL<V>;
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int i = wk.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int bf = it.blk_first[i];
-  const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int tid = opaque_tid();
+  const int bf = it.blk_first[wk.y];
+  const int i = ph ? bf + it.blk_last[wk.y] - wk.y : wk.y;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
   const int64_t T0 = (int64_t)wk.z * 8 + (L::FULL ? 0 : 4 * wk.w);
-  const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
-  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0) * FRAG, it.hs_lo + (T0 * it.tks + ks0) * FRAG,
-                  it.tks * FRAG, FRAG};
+  const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int64_t k1 = ph ? nks - 1 : 0;  // first k-step
+  constexpr int64_t dir = ph ? -1 : 1;   // direction
+  const FragSrc A{it.wa_hi + it.wa_off[i] + k1 * 8 * FRAG, it.wa_lo + it.wa_off[i] + k1 * 8 * FRAG,
+                  FRAG, dir * 8 * FRAG};
+  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0 + k1) * FRAG,
+                  it.hs_lo + (T0 * it.tks + ks0 + k1) * FRAG, it.tks * FRAG, dir * FRAG};
   f16v acc[4][L::WB];
-  gemm3_v<3, V>(A, B, nks, acc);
-  // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8), pos p%8
+  gemm3_v<3, V>(A, B, nks, tid, acc);
+  // element (template b, row p) of F(w0^T): tile b/32, kstep p/16, lane b%32 + 32((p%16)/8),
+  // pos p%8.  With two waves per SIMD the thread index is read again, so that no address
+  // is held across the product.
+  const int tid2 = L::WPS > 1 ? opaque_tid() : tid, lane2 = tid2 & 63, w2 = tid2 >> 6;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int64_t rt_row = (int64_t)i * TB + 32 * (L::ta(w) + a);
+    const int64_t rt_row = (int64_t)i * TB + 32 * (L::ta(w2) + a);
 #pragma unroll
     for (int b = 0; b < L::WB; ++b) {
-      const int64_t T = T0 + L::tb(w) + b;
+      const int64_t T = T0 + L::tb(w2) + b;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int64_t base = rt_row + 8 * g;
         const int64_t ks = base >> 4;
-        const int lp = (lane & 31) + 32 * (g & 1);
-        const int64_t dst = ((T * it.tks + ks) * 64 + lp) * 8 + 4 * (lane >> 5);
+        const int lp = (lane2 & 31) + 32 * (g & 1);
+        const int64_t dst = ((T * it.tks + ks) * 64 + lp) * 8 + 4 * (lane2 >> 5);
         uint16_t h4[4], l4[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) split2f(acc[a][b][4 * g + v], h4[v], l4[v]);
@@ -467,33 +592,41 @@ __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_fwd(
   }
 }
 
-// y0^T = w0^T W over column block j (K = rows [j TB, (last_j + 1) TB)): A = F(w0^T)
-// (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for the
-// half-group variant).
 template <int V>
-__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_bwd(
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_fwd(
     const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  const int4 wk = work[blockIdx.x];
+  if (wk.y < 0 || (PL<V>::FULL && wk.w)) return;
+  const int np = pair_blocks(items[wk.x], wk.y);
+  fwd_block<V, 0>(items, work);
+  if (np == 2) fwd_block<V, 1>(items, work);
+}
+
+// y0^T = w0^T W over column block j (K = rows [j TB, (last + 1) TB)): A = F(w0^T)
+// (256 templates of the group), B = F(W^T) sample tiles of block j (half `sub` for the
+// half-group variant).  The first block of the pair (the longer K) walks K downwards from
+// the end of the segment, its partner upwards.
+template <int V, int ph>
+__device__ __forceinline__ void bwd_block(const MixItem *items, const int4 *work) {
   using L = PL<V>;
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int j = wk.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int last = it.blk_last[j];
-  const int64_t nks = (int64_t)(last + 1 - j) * (TB / 16);
-  const int64_t ks0 = (int64_t)j * (TB / 16);
+  const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6;
+  const int last = it.blk_last[wk.y];
+  const int j = ph ? it.blk_first[wk.y] + last - wk.y : wk.y;
   const int64_t T0 = (int64_t)wk.z * 8;
   const int st0 = L::FULL ? 0 : 4 * wk.w;
-  // K runs from the end of the segment down: the column blocks of one super-tile end at
-  // the same row, so walking K backwards keeps them on the same template k-steps (shared
-  // in L2) until the shorter ones finish.
-  const int64_t kl = nks - 1;
-  const FragSrc A{it.w0_hi + (T0 * it.tks + ks0 + kl) * FRAG, it.w0_lo + (T0 * it.tks + ks0 + kl) * FRAG,
-                  it.tks * FRAG, -FRAG};
-  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG + kl * 8 * FRAG,
-                  it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG + kl * 8 * FRAG, FRAG, -8 * FRAG};
+  const int64_t nks = (int64_t)(last + 1 - j) * (TB / 16);
+  const int64_t ks0 = (int64_t)j * (TB / 16);
+  const int64_t k1 = ph ? 0 : nks - 1;  // first k-step
+  constexpr int64_t dir = ph ? 1 : -1;   // direction
+  const FragSrc A{it.w0_hi + (T0 * it.tks + ks0 + k1) * FRAG,
+                  it.w0_lo + (T0 * it.tks + ks0 + k1) * FRAG, it.tks * FRAG, dir * FRAG};
+  const FragSrc B{it.wb_hi + it.wb_off[j] + (int64_t)st0 * FRAG + k1 * 8 * FRAG,
+                  it.wb_lo + it.wb_off[j] + (int64_t)st0 * FRAG + k1 * 8 * FRAG, FRAG,
+                  dir * 8 * FRAG};
   f16v acc[4][L::WB];
-  gemm3_v<3, V>(A, B, nks, acc);
+  gemm3_v<3, V>(A, B, nks, tid, acc);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int64_t trow0 = 32 * (T0 + L::ta(w) + a);
@@ -509,32 +642,46 @@ __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_bwd(
   }
 }
 
+template <int V>
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_trmm_bwd(
+    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  const int4 wk = work[blockIdx.x];
+  if (wk.y < 0 || (PL<V>::FULL && wk.w)) return;
+  const int np = pair_blocks(items[wk.x], wk.y);
+  bwd_block<V, 0>(items, work);
+  if (np == 2) bwd_block<V, 1>(items, work);
+}
+
 // Correction c_b = ||W e_b||^2: the forward product with the split residual (in the
 // template buffers) as B; the epilogue writes, per template, the sum of squares over the
 // 256 rows of block i to corr_part[i][b] (fixed order, no atomics).  CORR_PROD selects
-// 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.
+// 3 (hi*hi + hi*lo + lo*hi) or 1 (hi*hi) products.  Pairs as in the forward product.
 constexpr int CORR_PROD = 3;
-template <int V>
-__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
-    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+template <int V, int ph>
+__device__ __forceinline__ void corr_block(const MixItem *items, const int4 *work,
+                                           double (*red)[256]) {
   using L = PL<V>;
-  __shared__ double red[2][256];
   const int4 wk = work[blockIdx.x];
-  if (wk.y < 0 || (L::FULL && wk.w)) return;
   const MixItem &it = items[wk.x];
-  const int i = wk.y;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int bf = it.blk_first[i];
-  const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int tid = opaque_tid(), lane0 = tid & 63, w0 = tid >> 6;
+  const int bf = it.blk_first[wk.y];
+  const int i = ph ? bf + it.blk_last[wk.y] - wk.y : wk.y;
   const int64_t ks0 = (int64_t)bf * (TB / 16);
   const int64_t T0 = (int64_t)wk.z * 8 + (L::FULL ? 0 : 4 * wk.w);
-  const FragSrc A{it.wa_hi + it.wa_off[i], it.wa_lo + it.wa_off[i], FRAG, 8 * FRAG};
-  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0) * FRAG, it.hs_lo + (T0 * it.tks + ks0) * FRAG,
-                  it.tks * FRAG, FRAG};
+  const int64_t nks = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int64_t k1 = ph ? nks - 1 : 0;
+  constexpr int64_t dir = ph ? -1 : 1;
+  const FragSrc A{it.wa_hi + it.wa_off[i] + k1 * 8 * FRAG, it.wa_lo + it.wa_off[i] + k1 * 8 * FRAG,
+                  FRAG, dir * 8 * FRAG};
+  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0 + k1) * FRAG,
+                  it.hs_lo + (T0 * it.tks + ks0 + k1) * FRAG, it.tks * FRAG, dir * FRAG};
   f16v acc[4][L::WB];
-  gemm3_v<CORR_PROD, V>(A, B, nks, acc);
+  gemm3_v<CORR_PROD, V>(A, B, nks, tid, acc);
   // per column: sum of squares over the wave's 128 rows; the two row halves of the
-  // workgroup meet in LDS
+  // workgroup meet in LDS.  With two waves per SIMD the thread index is read again, as in
+  // the forward product.
+  const int tid2 = L::WPS > 1 ? opaque_tid() : tid;
+  const int lane = L::WPS > 1 ? tid2 & 63 : lane0, w = L::WPS > 1 ? tid2 >> 6 : w0;
 #pragma unroll
   for (int b = 0; b < L::WB; ++b) {
     double ss = 0.0;
@@ -548,8 +695,22 @@ __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
   }
   __syncthreads();
   const int ncol = L::FULL ? 256 : 128;
-  for (int col = threadIdx.x; col < ncol; col += 64 * L::NW)
+  for (int col = tid2; col < ncol; col += 64 * L::NW)
     it.corr_part[(int64_t)i * it.Bp + T0 * 32 + col] = red[0][col] + red[1][col];
+}
+
+template <int V>
+__global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
+    const MixItem *__restrict__ items, const int4 *__restrict__ work) {
+  __shared__ double red[2][256];
+  const int4 wk = work[blockIdx.x];
+  if (wk.y < 0 || (PL<V>::FULL && wk.w)) return;
+  const int np = pair_blocks(items[wk.x], wk.y);
+  corr_block<V, 0>(items, work, red);
+  if (np == 2) {
+    __syncthreads();  // the first block's sums have been read
+    corr_block<V, 1>(items, work, red);
+  }
 }
 
 // out[b] = -1/2 (qpart[b] + sum_i corr_part[i][b]) + cterm; entries (item, b)
@@ -573,6 +734,10 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
       break;                                                                                 \
     case 4:                                                                                  \
       hipLaunchKernelGGL(K<4>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);         \
+      break;                                                                                 \
+    case 5:                                                                                  \
+      hipLaunchKernelGGL(K<5>, dim3((unsigned)n_work), dim3(512), PL<5>::lds_bytes(), s,     \
+                         items, work);                                                       \
       break;                                                                                 \
     default:                                                                                 \
       hipLaunchKernelGGL(K<1>, dim3((unsigned)n_work), dim3(256), 0, s, items, work);         \
@@ -1603,6 +1768,12 @@ hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, doub
 }
 
 void register_mixed_attributes() {
+  hipFuncSetAttribute((const void *)k_trmm_fwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_trmm_bwd<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
+  hipFuncSetAttribute((const void *)k_corr<5>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)PL<5>::lds_bytes());
   hipFuncSetAttribute((const void *)k_refine_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)RL_LDS_BYTES);
   hipFuncSetAttribute((const void *)k_gs, hipFuncAttributeMaxDynamicSharedMemorySize,

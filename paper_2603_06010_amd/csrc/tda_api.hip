@@ -709,21 +709,20 @@ extern "C" tda_status tda_loglik(tda_handle h, const double *d, const double *H,
 
 namespace {
 
-// Work list in XCD-aware order: hardware dispatches workgroup g to XCD g % 8, so the
-// entries of one block (all template groups) are queued on the same XCD, where they
-// share that block's operator panel in L2; blocks are dealt to XCDs round-robin and
-// each XCD queue runs its largest blocks first.
+// A product job: one block pair of an item, with its template groups and halves.
 struct BlockJob {
   int32_t item, block, ntg, nsub;
-  int64_t k;  // work weight (K of the block)
+  int64_t k;  // work weight (K blocks the pair spans)
 };
 
 // Product work order.  Workgroup g runs on XCD g mod 8, and each XCD has its own L2, so
 // the list is built per XCD and interleaved.  Work is cut into super-tiles of kRB
-// consecutive blocks of one item x kTG template groups: the ~32 workgroups an XCD runs
-// at once then share each template k-step among kRB blocks and each operator block
-// among kTG groups in L2, instead of re-reading the templates for every block.
-// Super-tiles go to the XCD with the least work so far, longest first.
+// consecutive block pairs of one item x kTG template groups, the workgroups an XCD runs
+// at once (64 half-group or 32 full-group ones): they share each operator k-step among
+// kTG groups and each template k-step among kRB pairs in L2.  Pairs of one segment span
+// the same K and their K walks are aligned (see the product kernels), so a super-tile's
+// workgroups start and finish together and stay on the same k-steps.  Super-tiles go to
+// the XCD with the least work so far, longest first.
 constexpr int kRB = 4, kTG = 8;
 std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
   constexpr int NX = 8;
@@ -999,15 +998,23 @@ static void add_refine_pairs(int32_t item, int64_t B, std::vector<int4> &wr) {
     wr.push_back(int4{item, (int32_t)b, b + 1 < B ? (int32_t)(b + 1) : -1, 0});
 }
 
-// product jobs: (block, group of 256 templates, half); see the product kernels for halves
-static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, bool transposed,
+// product jobs: (block pair, group of 256 templates, half); see the product kernels for
+// pairs and halves.  A job is named by the first block of its pair, the lower index; its
+// weight is the K the pair spans, the same for both products.
+static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, int32_t nsub,
                            std::vector<BlockJob> &jobs) {
   for (int32_t i = 0; i < h->nblk; ++i) {
-    const int64_t k = transposed ? (int64_t)(h->blk_last_h[i] + 1 - i)
-                                 : (int64_t)(i + 1 - h->blk_first_h[i]);
-    jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), 2, k});
+    const int32_t bf = h->blk_first_h[i], bl = h->blk_last_h[i], partner = bf + bl - i;
+    if (partner < i) continue;  // second block of a pair
+    const int64_t k = partner == i ? (int64_t)(i + 1 - bf) : (int64_t)(bl - bf + 2);
+    jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), nsub, k});
   }
 }
+
+// Product variants whose workgroup covers a whole group of 256 templates take the work
+// list without halves: an entry that exits at once still holds a dispatch slot of its
+// CU, and half of such entries left half of the CUs idle.
+static bool variant_full_group(int v) { return v != 2; }
 
 // timing names carry the product variant the autotuner picked ("trmm_fwd/v2")
 static const char *const kTrmmFwdNames[] = {"trmm_fwd",    "trmm_fwd/v1", "trmm_fwd/v2",
@@ -1030,13 +1037,13 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   // refinement in LDS for items whose segments' circulants fit, paired with global
   // scratch for the others
   (void)max_m;
-  std::vector<BlockJob> jf, jb;
+  std::vector<BlockJob> jf, jh;
   std::vector<int4> wr;
   std::vector<int2> wfin, wrl;
   for (int64_t k = 0; k < n; ++k) {
     if (mis[k].B == 0) continue;
-    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, false, jf);
-    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, true, jb);
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, 1, jf);
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, 2, jh);
     const bool in_lds = hs[k]->max_m <= RL_MAX_M;
     if (!in_lds) add_refine_pairs((int32_t)k, mis[k].B, wr);
     for (int32_t b = 0; b < mis[k].B; ++b) {
@@ -1047,15 +1054,17 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   int64_t max_m_scratch = 0;
   for (int64_t k = 0; k < n; ++k)
     if (mis[k].B > 0 && hs[k]->max_m > RL_MAX_M) max_m_scratch = std::max(max_m_scratch, hs[k]->max_m);
-  const std::vector<int4> wf = xcd_order(jf), wbk = xcd_order(jb);
+  // the forward, backward and correction products share the work lists (block pairs):
+  // whole template groups, and half groups for the half-group variant
+  const std::vector<int4> wf = xcd_order(jf), wh = xcd_order(jh);
   HIP_TRY(ring.reserve(8192 + n * (64 + sizeof(MixItem) + sizeof(RefItem)) +
-                       (wf.size() + wbk.size() + wr.size()) * sizeof(int4) +
+                       (wf.size() + wh.size() + wr.size()) * sizeof(int4) +
                        (wfin.size() + wrl.size()) * sizeof(int2)));
-  void *d_mi, *d_ri, *d_wf, *d_wb, *d_wr, *d_fin, *d_rl = nullptr;
+  void *d_mi, *d_ri, *d_wf, *d_wh, *d_wr, *d_fin, *d_rl = nullptr;
   HIP_TRY(ring.push(mis.data(), mis.size() * sizeof(MixItem), s, &d_mi));
   HIP_TRY(ring.push(ris.data(), ris.size() * sizeof(RefItem), s, &d_ri));
   HIP_TRY(ring.push(wf.data(), wf.size() * sizeof(int4), s, &d_wf));
-  HIP_TRY(ring.push(wbk.data(), wbk.size() * sizeof(int4), s, &d_wb));
+  HIP_TRY(ring.push(wh.data(), wh.size() * sizeof(int4), s, &d_wh));
   d_wr = nullptr;
   if (!wr.empty()) HIP_TRY(ring.push(wr.data(), wr.size() * sizeof(int4), s, &d_wr));
   HIP_TRY(ring.push(wfin.data(), wfin.size() * sizeof(int2), s, &d_fin));
@@ -1069,13 +1078,14 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   }
   struct Ctx {
     const MixItem *dm;
-    const int4 *w;
-    int64_t nw;
+    const int4 *wf, *wh;  // whole-group and half-group work lists
+    int64_t nf, nh;
     hipStream_t s;
+    const int4 *w(int v) const { return variant_full_group(v) ? wf : wh; }
+    int64_t nw(int v) const { return variant_full_group(v) ? nf : nh; }
   };
-  static const int kVariants[3] = {1, 2, 4};
-  Ctx cf{dm, (const int4 *)d_wf, (int64_t)wf.size(), s};
-  Ctx cb{dm, (const int4 *)d_wb, (int64_t)wbk.size(), s};
+  static const int kVariants[4] = {1, 2, 4, 5};
+  Ctx cf{dm, (const int4 *)d_wf, (const int4 *)d_wh, (int64_t)wf.size(), (int64_t)wh.size(), s};
   int64_t max_chunks = 0;
   for (int64_t k = 0; k < n; ++k)
     max_chunks = std::max<int64_t>(max_chunks, (int64_t)(mis[k].Bp / 32) * (mis[k].n_pad / 16) * 64);
@@ -1083,23 +1093,23 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_h", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
   }
-  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 3, s,
+  const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
-                                 return launch_trmm_fwd(x->dm, x->w, x->nw, v, x->s);
+                                 return launch_trmm_fwd(x->dm, x->w(v), x->nw(v), v, x->s);
                                }, &cf);
   {
     TimedScope ts(variant_name(kTrmmFwdNames, vf), s);
-    HIP_TRY(launch_trmm_fwd(dm, (const int4 *)d_wf, (int64_t)wf.size(), vf, s));
+    HIP_TRY(launch_trmm_fwd(dm, cf.w(vf), cf.nw(vf), vf, s));
   }
-  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 3, s,
+  const int vb = autotune_pick("trmm_bwd", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
-                                 return launch_trmm_bwd(x->dm, x->w, x->nw, v, x->s);
-                               }, &cb);
+                                 return launch_trmm_bwd(x->dm, x->w(v), x->nw(v), v, x->s);
+                               }, &cf);
   {
     TimedScope ts(variant_name(kTrmmBwdNames, vb), s);
-    HIP_TRY(launch_trmm_bwd(dm, (const int4 *)d_wb, (int64_t)wbk.size(), vb, s));
+    HIP_TRY(launch_trmm_bwd(dm, cf.w(vb), cf.nw(vb), vb, s));
   }
   {
     TimedScope ts("refine_fft", s);
@@ -1113,14 +1123,14 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     TimedScope ts("split_e", s);
     HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
-  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 3, s,
+  const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
                                  Ctx *x = (Ctx *)c;
-                                 return launch_corr(x->dm, x->w, x->nw, v, x->s);
+                                 return launch_corr(x->dm, x->w(v), x->nw(v), v, x->s);
                                }, &cf);
   {
     TimedScope ts(variant_name(kTrmmCorrNames, vc), s);
-    HIP_TRY(launch_corr(dm, (const int4 *)d_wf, (int64_t)wf.size(), vc, s));
+    HIP_TRY(launch_corr(dm, cf.w(vc), cf.nw(vc), vc, s));
   }
   {
     TimedScope ts("finish", s);

@@ -65,6 +65,32 @@ def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
     h.close()
 
 
+@pytest.mark.parametrize("N,n_gaps,B,segments", [
+    (3000, 2, 300, None),
+    (2600, 1, 130, [(0, 1000), (1200, 1300), (2550, 50)]),
+])
+def test_product_variants(tda, monkeypatch, N, n_gaps, B, segments):
+    """Every tile variant of the three products, forced in turn, meets the mixed bound, and
+    all of them give the same bits (the same per-tile accumulation order)."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(300 + N + B, N, 1, n_gaps, B, segments=segments)
+    f = oracle.factor(inst.acf, N, inst.masks[0], segments)
+    want = oracle.loglik(f, inst.d[0], inst.H)
+    h = tda.Handle(inst.acf, N, inst.masks[0], segments, precision="mixed").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    outs = {}
+    for v in (1, 2, 4, 5):
+        print(f"case N={N} B={B} segments={segments} variant {v}", flush=True)
+        monkeypatch.setenv("TDA_PRODUCT_VARIANT", str(v))
+        outs[v] = h.loglik(d, H).cpu().numpy()
+        torch.cuda.synchronize()
+        _check_mixed(outs[v], want)
+    for v in (2, 4, 5):
+        np.testing.assert_array_equal(outs[v], outs[1])
+    h.close()
+
+
 def test_mixed_invariants(tda):
     from gpu_util import to_dev
     import torch
