@@ -231,6 +231,32 @@ def main():
         for h in hg:
             h.close()
 
+    # inner products behind the SNRs (tda_loglik_terms): mixed per detector, timed, and
+    # compared with the FP64 evaluation of the same terms on the GPU
+    tsteps = max(3, args.steps // 4)
+    terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(tsteps):
+        terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
+    torch.cuda.synchronize()
+    wall_t = time.perf_counter() - t
+    terms_f = [h.loglik_terms(dk, H, precision="fp64") for h, dk in zip(hs, d)]
+    torch.cuda.synchronize()
+    dh_m = sum(x[1] for x in terms_m).cpu().numpy()
+    hh_m = sum(x[2] for x in terms_m).cpu().numpy()
+    dh_f = sum(x[1] for x in terms_f).cpu().numpy()
+    hh_f = sum(x[2] for x in terms_f).cpu().numpy()
+    rho_m, rho_f = dh_m / np.sqrt(hh_m), dh_f / np.sqrt(hh_f)
+    snr_terms = {"value": inst.B * tsteps / wall_t, "unit": "evals/s (logL + <d,h> + <h,h>, "
+                 "network sums)", "ms_per_step": wall_t / tsteps * 1e3, "steps": tsteps,
+                 "max_abs_d_dh_mixed_vs_fp64_gpu": float(np.abs(dh_m - dh_f).max()),
+                 "max_abs_d_hh_mixed_vs_fp64_gpu": float(np.abs(hh_m - hh_f).max()),
+                 "max_abs_d_rho_mf_mixed_vs_fp64_gpu": float(np.abs(rho_m - rho_f).max()),
+                 "rho_mf_range": [float(rho_f.min()), float(rho_f.max())]}
+    log("snr terms", snr_terms)
+    del terms_m, terms_f
+
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
 
@@ -274,6 +300,7 @@ def main():
                               "frac": ach_f / PEAK_FP64, "avg_ms": tf / cf}},
         "speedup_mixed_vs_fp64": evals_m / evals_f,
         "gs_fp64": gs,
+        "snr_terms": snr_terms,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
                      "templates_compared": int(inst.B)},

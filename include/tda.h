@@ -184,6 +184,30 @@ tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t
                          double *out, int32_t precision, void *hip_stream);
 
 /*
+ * tda_loglik_terms -- logL together with the two noise-weighted inner products
+ * behind the paper's time-domain SNRs (Sec. II.B item 7: the matched-filter
+ * SNR rho_mf = <d,h>/sqrt(<h,h>) and the effective SNR rho_eff^2 =
+ * <d,d> - <r,r>, r = d - h), where <a,b> = a^T C^-1 b over the retained
+ * samples of this detector:
+ *   out[b]    = logL, exactly as tda_loglik_ex with the same precision,
+ *   out_dh[b] = <d, h_b>      (may be NULL: not computed),
+ *   out_hh[b] = <h_b, h_b>    (may be NULL: not computed).
+ * <d,d> = q + 2 <d,h> - <h,h> follows with q = -2 (logL + 1/2 log det C +
+ * N_eff/2 log 2 pi), and <r,r> = q.  All arrays are device float64[B] and
+ * distinct.
+ * Mixed precision computes <d,h> in FP64 from the cached C^-1 d and <h,h> as
+ * the refined (FP64-residual) form plus the correction, in the same launches
+ * as logL.  FP64 and Gohberg-Semencul evaluations obtain <h,h> from a second
+ * evaluation against zero data and <d,d> from one of the data against a zero
+ * template (about twice the cost of tda_loglik_ex when out_hh or out_dh is
+ * requested).  NaN/Inf in a template gives NaN in its three outputs.
+ * Errors and asynchrony as tda_loglik_ex.
+ */
+tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int64_t B,
+                            int64_t ldh, double *out, double *out_dh, double *out_hh,
+                            int32_t precision, void *hip_stream);
+
+/*
  * tda_loglik_multi -- one batched evaluation over many (handle, data,
  * templates) items, e.g. all detectors of all instances (Sec. II.B item 3).
  * Items whose `out` pointers are equal are summed into that array in item

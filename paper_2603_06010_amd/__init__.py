@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
 PREC_FP64, PREC_MIXED, PREC_GS = 0, 1, 2
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-    "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_terms", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_set_data.argtypes = [vp, vp, vp]
     L.tda_loglik.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
+    L.tda_loglik_terms.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, i32, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
     L.tda_info.argtypes = [vp, ctypes.POINTER(_Info)]
     L.tda_destroy.argtypes = [vp]
@@ -95,7 +96,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_timing_enable.argtypes = [i32]
     L.tda_timing_read.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-              "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
+              "tda_loglik_terms", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
               "tda_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -192,6 +193,35 @@ class Handle:
         _check(_lib.tda_loglik_ex(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), p,
                                   _stream(stream)))
         return out
+
+    def loglik_terms(self, d, H, precision=None, want_dh=True, want_hh=True, stream=None):
+        """(logL, <d,h>, <h,h>) per template through tda_loglik_terms; an inner product
+        not asked for comes back as None."""
+        import torch
+        if H.dim() != 2:
+            raise ValueError("H must be 2-D")
+        if H.stride(1) != 1:
+            raise ValueError("H rows must be contiguous")
+        B = H.shape[0]
+        mk = lambda: torch.empty(B, dtype=torch.float64, device=H.device)
+        out = mk()
+        dh = mk() if want_dh else None
+        hh = mk() if want_hh else None
+        if B == 0:
+            return out, dh, hh
+        p = self.precision if precision is None else _precision(precision)
+        _check(_lib.tda_loglik_terms(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
+                                     _ptr(dh) if dh is not None else None,
+                                     _ptr(hh) if hh is not None else None, p, _stream(stream)))
+        return out, dh, hh
+
+    def snr(self, d, H, precision=None, stream=None):
+        """Time-domain SNRs per template (Sec. II.B item 7): rho_mf = <d,h>/sqrt(<h,h>),
+        rho_opt = sqrt(<h,h>) and rho_eff^2 = <d,d> - <r,r> = 2 <d,h> - <h,h>."""
+        import torch
+        _, dh, hh = self.loglik_terms(d, H, precision=precision, stream=stream)
+        return {"rho_mf": dh / torch.sqrt(hh), "rho_opt": torch.sqrt(hh),
+                "rho_eff2": 2.0 * dh - hh, "dh": dh, "hh": hh}
 
     def info(self) -> dict:
         i = _Info()

@@ -499,4 +499,27 @@ hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hip
   return hipGetLastError();
 }
 
+// Inner products from three log-likelihoods with the same constant c: an evaluation
+// against the data (out), one against zero data (hh: logL = c - <h,h>/2) and one of the
+// data against a zero template (dd: logL = c - <d,d>/2).  From q = <d,d> - 2 <d,h> + <h,h>
+// with q = -2 (logL - c): <h,h> = -2 (hh - c) and <d,h> = out - dd + <h,h>/2.  hh is
+// overwritten with <h,h>; dh may be NULL.
+__global__ void k_terms_combine(const double *__restrict__ out, double *__restrict__ hh,
+                                const double *__restrict__ dd, double cterm, int64_t B,
+                                double *__restrict__ dh) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const double v = -2.0 * (hh[b] - cterm);
+  hh[b] = v;
+  if (dh) dh[b] = out[b] - dd[0] + 0.5 * v;
+}
+
+hipError_t launch_terms_combine(const double *out, double *hh, const double *dd, double cterm,
+                                int64_t B, double *dh, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_terms_combine, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, out, hh,
+                     dd, cterm, B, dh);
+  return hipGetLastError();
+}
+
 }  // namespace tda

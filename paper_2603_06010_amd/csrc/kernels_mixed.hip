@@ -446,7 +446,7 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
                                          f16v (&acc)[4][PL<V>::WB], char *smem) {
   using L = PL<V>;
   constexpr int NS = L::LDS_STAGES, SB = 32 * FRAG * 2;
-  static_assert(L::NW == 8 && NS == 4, "LDS path: 8 waves, 4 stages");
+  static_assert(L::NW == 8 && NS >= 3, "LDS path: 8 waves, at least 3 stages");
   const int lane = tid & 63, w = tid >> 6;
   const int ta = L::ta(w), tb = L::tb(w);
   // this wave's copies: array w >> 1, tiles 4 (w & 1) .. + 3
@@ -463,22 +463,23 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
       __builtin_amdgcn_global_load_lds((const void *)(q + u * s_tile),
                                        (lds_void_t *)(dst0 + slot * SB + u * 1024), 16, 0, 0);
   };
+  auto next_slot = [](int sl) __attribute__((always_inline)) { return sl + 1 == NS ? 0 : sl + 1; };
   zero_acc<L::WB>(acc);
   if (nks <= 0) return;
-  issue(0, 0);
-  issue(1, 1);
-  issue(2, 2);
-  wait_vmcnt<8>();
+#pragma unroll
+  for (int p = 0; p < NS - 1; ++p) issue(p, p);
+  wait_vmcnt<4 * (NS - 2)>();
   __builtin_amdgcn_s_barrier();
   Step<L::WB> r0, r1;
   lds_read_step<L::WB>(smem, ta, tb, lane, r0);
-  // one k-step: wait for stage t + 1, barrier, copies for stage t + 3, LDS reads of stage
-  // t + 1 spread through the matrix-core ops of stage t
-  auto kstep = [&](int64_t t, const Step<L::WB> &cur, Step<L::WB> &nxt) __attribute__((always_inline)) {
-    wait_vmcnt<4>();
+  // one k-step: wait for stage t + 1, barrier, copies for stage t + NS - 1 (into the slot
+  // of stage t - 1), LDS reads of stage t + 1 spread through the matrix-core ops of
+  // stage t.  s1 is the slot of stage t + 1.
+  auto kstep = [&](int64_t t, int s1, const Step<L::WB> &cur, Step<L::WB> &nxt) __attribute__((always_inline)) {
+    wait_vmcnt<4 * (NS - 3)>();
     __builtin_amdgcn_s_barrier();
-    issue(t + 3, (int)((t + 3) & 3));
-    lds_read_step<L::WB>(smem + ((t + 1) & 3) * SB, ta, tb, lane, nxt);
+    issue(t + NS - 1, s1 == 0 ? NS - 2 : s1 == 1 ? NS - 1 : s1 - 2);
+    lds_read_step<L::WB>(smem + s1 * SB, ta, tb, lane, nxt);
     mma_step<NPROD, L::WB>(cur, acc);
     // matrix-core ops first: their operands were read a k-step ago, so the wait for them
     // does not also wait for the reads of the next stage
@@ -494,9 +495,12 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
     __builtin_amdgcn_sched_barrier(0);
   };
   int64_t t = 0;
+  int s1 = 1;  // slot of stage t + 1
   for (; t + 2 <= nks; t += 2) {
-    kstep(t, r0, r1);
-    kstep(t + 1, r1, r0);
+    kstep(t, s1, r0, r1);
+    s1 = next_slot(s1);
+    kstep(t + 1, s1, r1, r0);
+    s1 = next_slot(s1);
   }
   if (t < nks) mma_step<NPROD, L::WB>(r0, acc);
   // no copy may still be landing in LDS when the workgroup reuses or releases it
@@ -699,10 +703,23 @@ __device__ __forceinline__ void corr_block(const MixItem *items, const int4 *wor
     it.corr_part[(int64_t)i * it.Bp + T0 * 32 + col] = red[0][col] + red[1][col];
 }
 
+// LDS for the column sums: the LDS variant uses its operand ring, idle by then (a static
+// array would not fit beside its stages)
+template <int V>
+__device__ __forceinline__ double (*corr_red())[256] {
+  if constexpr (PL<V>::LDS_STAGES > 0) {
+    extern __shared__ char gp_smem[];
+    return (double (*)[256])gp_smem;
+  } else {
+    __shared__ double red[2][256];
+    return red;
+  }
+}
+
 template <int V>
 __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
     const MixItem *__restrict__ items, const int4 *__restrict__ work) {
-  __shared__ double red[2][256];
+  double (*red)[256] = corr_red<V>();
   const int4 wk = work[blockIdx.x];
   if (wk.y < 0 || (PL<V>::FULL && wk.w)) return;
   const int np = pair_blocks(items[wk.x], wk.y);
@@ -713,7 +730,8 @@ __global__ __launch_bounds__(64 * PL<V>::NW, PL<V>::OCC) void k_corr(
   }
 }
 
-// out[b] = -1/2 (qpart[b] + sum_i corr_part[i][b]) + cterm; entries (item, b)
+// out[b] = -1/2 (qpart[b] + sum_i corr_part[i][b]) + cterm; entries (item, b).  With
+// hh_out, the refinement left the refined h^T C^-1 h there and the correction is added.
 __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restrict__ work,
                          int64_t n_work) {
   const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -724,6 +742,7 @@ __global__ void k_finish(const MixItem *__restrict__ items, const int2 *__restri
   double c = 0.0;
   for (int i = 0; i < it.nblk; ++i) c += it.corr_part[(int64_t)i * it.Bp + b];
   it.out[b] = -0.5 * (it.qpart[b] + c) + it.cterm;
+  if (it.hh_out) it.hh_out[b] += c;  // refined h^T C^-1 h plus the correction
 }
 
 #define TDA_LAUNCH_VARIANT(K)                                                                 \
@@ -1054,6 +1073,14 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const RefItem *__restrict
       const double nan = __builtin_nan("");
       it.qpart[ba] = s_bada > 0 ? nan : it.qdd[0] - 2.0 * s_ydha + 2.0 * s_hya - s_yca;
       if (two) it.qpart[bb] = s_badb > 0 ? nan : it.qdd[0] - 2.0 * s_ydhb + 2.0 * s_hyb - s_ycb;
+      if (it.dh_out) {
+        it.dh_out[ba] = s_bada > 0 ? nan : s_ydha;
+        if (two) it.dh_out[bb] = s_badb > 0 ? nan : s_ydhb;
+      }
+      if (it.hh_out) {
+        it.hh_out[ba] = s_bada > 0 ? nan : 2.0 * s_hya - s_yca;
+        if (two) it.hh_out[bb] = s_badb > 0 ? nan : 2.0 * s_hyb - s_ycb;
+      }
     }
   }
 }
@@ -1452,8 +1479,12 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
     }
     const double s_hy = block_sum(acc.hy, red), s_ydh = block_sum(acc.ydh, red);
     const double s_yc = block_sum(acc.yc, red), s_bad = block_sum(acc.bad, red);
-    if (threadIdx.x == 0)
-      it.qpart[b] = s_bad > 0 ? __builtin_nan("") : it.qdd[0] - 2.0 * s_ydh + 2.0 * s_hy - s_yc;
+    if (threadIdx.x == 0) {
+      const double nan = __builtin_nan("");
+      it.qpart[b] = s_bad > 0 ? nan : it.qdd[0] - 2.0 * s_ydh + 2.0 * s_hy - s_yc;
+      if (it.dh_out) it.dh_out[b] = s_bad > 0 ? nan : s_ydh;
+      if (it.hh_out) it.hh_out[b] = s_bad > 0 ? nan : 2.0 * s_hy - s_yc;
+    }
   }
 }
 

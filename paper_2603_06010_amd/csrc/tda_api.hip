@@ -223,6 +223,7 @@ struct tda_ctx {
   // workspaces
   DevBuf ws_scratch, ws_tiles, ws_items;
   DevBuf ws_hs_hi, ws_hs_lo, ws_w0_hi, ws_w0_lo, ws_y0, ws_fft, ws_work, ws_mix, ws_ref;
+  DevBuf ws_zero, ws_terms;  // inner-product entry point: zero vector [N], <h,h> and <d,d>
   hipEvent_t done = nullptr;  // last enqueued work of this handle
   DescRing ring;
   std::vector<SegDev> segdev_h;
@@ -663,11 +664,12 @@ static tda_status loglik_f64(tda_ctx *h, const double *d, const double *H, int64
 }
 
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
-                               int64_t ldh, double *out, hipStream_t s);
+                               int64_t ldh, double *out, hipStream_t s, double *out_dh = nullptr,
+                               double *out_hh = nullptr);
 
-extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t B,
-                                    int64_t ldh, double *out, int32_t precision,
-                                    void *hip_stream) {
+// Argument checks shared by the single-handle evaluation entry points.
+static tda_status check_eval(tda_handle h, const double *d, const double *H, int64_t B,
+                             int64_t ldh, const double *out, int32_t precision) {
   if (!h) return fail_with(TDA_EINVAL, "NULL handle");
   if (!h->factored) return fail_with(TDA_ESTATE, "tda_loglik before a successful tda_factor");
   if (B < 0) return fail_with(TDA_EINVAL, "B < 0");
@@ -683,12 +685,25 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
     return fail_with(TDA_ESTATE, "a GS handle evaluates only (and only it) in TDA_PREC_GS");
   if (h->compacted && (precision == TDA_PREC_FP64 || d != h->data_ptr))
     return fail_with(TDA_ESTATE, "compact handle: only mixed evaluation with its cached data");
-  DeviceGuard guard(h->device);
-  hipStream_t s = (hipStream_t)hip_stream;
+  return TDA_OK;
+}
+
+static tda_status refuse_capture(hipStream_t s) {
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing(s, &cap));
   if (cap != hipStreamCaptureStatusNone)
     return fail_with(TDA_ESTATE, "stream capture outside a plan: use tda_plan_execute");
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t B,
+                                    int64_t ldh, double *out, int32_t precision,
+                                    void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, precision));
+  if (B == 0) return TDA_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(refuse_capture(s));
   TDA_TRY(order_after_previous(h, s));
   if (precision == TDA_PREC_FP64)
     TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
@@ -696,6 +711,44 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
     TDA_TRY(loglik_gs(h, d, H, B, ldh, out, s));
   else
     TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s));
+  return mark_done(h, s);
+}
+
+extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int64_t B,
+                                       int64_t ldh, double *out, double *out_dh, double *out_hh,
+                                       int32_t precision, void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, precision));
+  if (B == 0) return TDA_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(refuse_capture(s));
+  TDA_TRY(order_after_previous(h, s));
+  if (precision == TDA_PREC_MIXED) {
+    // <d,h> = y_d^T h is an FP64 term of the split form and <h,h> its refined part plus
+    // the correction: both come out of the same launches
+    TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s, out_dh, out_hh));
+    return mark_done(h, s);
+  }
+  auto eval = [&](const double *dd, const double *HH, int64_t BB, int64_t ld, double *o) {
+    return precision == TDA_PREC_FP64 ? loglik_f64(h, dd, HH, BB, ld, o, s)
+                                      : loglik_gs(h, dd, HH, BB, ld, o, s);
+  };
+  TDA_TRY(eval(d, H, B, ldh, out));
+  if (out_dh || out_hh) {
+    // the same evaluation against zero data gives <h,h>, and the data against a zero
+    // template <d,d>; <d,h> follows from the three
+    if (!h->ws_zero.p) {
+      TDA_TRY(h->alloc(h->ws_zero, (size_t)h->N * sizeof(double)));
+      HIP_TRY(hipMemsetAsync(h->ws_zero.p, 0, (size_t)h->N * sizeof(double), s));
+    }
+    TDA_TRY(h->alloc(h->ws_terms, (size_t)(B + 1) * sizeof(double)));
+    const double *zero = (const double *)h->ws_zero.p;
+    double *hh = out_hh ? out_hh : (double *)h->ws_terms.p + 1;
+    double *dd = (double *)h->ws_terms.p;
+    TDA_TRY(eval(zero, H, B, ldh, hh));
+    if (out_dh) TDA_TRY(eval(d, zero, 1, h->N, dd));
+    HIP_TRY(launch_terms_combine(out, hh, dd, h->cterm(), B, out_dh, s));
+  }
   return mark_done(h, s);
 }
 
@@ -1140,14 +1193,18 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
 }
 
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
-                               int64_t ldh, double *out, hipStream_t s) {
+                               int64_t ldh, double *out, hipStream_t s, double *out_dh,
+                               double *out_hh) {
   if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
   const int64_t Bp = (B + MT - 1) / MT * MT;
   TDA_TRY(h->alloc(h->ws_mix, mix_ws_bytes(h, Bp)));
   if (h->max_m > RL_MAX_M) TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
   const MixWs ws = carve_mix_ws(h, Bp, (char *)h->ws_mix.p);
   std::vector<MixItem> mis{make_mix_item(h, H, ldh, B, Bp, ws, out)};
+  mis[0].hh_out = out_hh;
   std::vector<RefItem> ris{make_ref_item(h, mis[0])};
+  ris[0].dh_out = out_dh;
+  ris[0].hh_out = out_hh;
   std::vector<const tda_ctx *> hs{h};
   TDA_TRY(enqueue_mixed(h->ring, mis, ris, hs, (double *)h->ws_fft.p, h->max_m, s));
   HIP_TRY(h->ring.seal(s));

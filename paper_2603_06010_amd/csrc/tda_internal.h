@@ -71,6 +71,7 @@ struct MixItem {
   double *corr_part;               // [nblk][Bp] per-block sums of (W e)^2
   double *qpart;                   // [Bp] FP64 part of the quadratic form
   double *out;
+  double *hh_out;                  // optional [B]: h^T C^-1 h (refined part added here)
   double cterm;
   int32_t B, Bp;                   // templates, padded to a multiple of MT
   int32_t nblk;
@@ -128,6 +129,8 @@ struct RefItem {
   double *e64;             // [Bp][n_pad] residual output
   double *qpart;           // [Bp] FP64 part of q output
   double *out;
+  double *dh_out;          // optional [B]: d^T C^-1 h
+  double *hh_out;          // optional [B]: the refined h^T C^-1 h before the correction
   double cterm;
   int32_t n_pad;
   int32_t pad0;
@@ -170,6 +173,9 @@ hipError_t launch_combine(const double *parts, const int64_t *part_off, const in
                           int64_t n_groups, int64_t max_B, hipStream_t s);
 void register_kernel_attributes();
 hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hipStream_t s);
+// <h,h> = -2 (hh - cterm) in place and, if dh != NULL, <d,h> = out - dd[0] + <h,h>/2
+hipError_t launch_terms_combine(const double *out, double *hh, const double *dd, double cterm,
+                                int64_t B, double *dh, hipStream_t s);
 
 // mixed
 hipError_t launch_split_w(const double *w64, const int64_t *w64_off, const int32_t *w64_rb,

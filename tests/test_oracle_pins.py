@@ -218,6 +218,76 @@ def test_gapped_whitened_noise_chi2():
     assert np.all(np.abs(q - f.n_eff) < 5 * np.sqrt(2 * f.n_eff))
 
 
+# ---------------------------------------------------------------- inner products and SNRs
+
+@pytest.mark.parametrize("segments,gaps", [
+    (None, []),
+    ([(0, 150), (170, 200), (400, 112)], [(30, 5), (180, 9)]),
+])
+def test_inner_products_white_noise(segments, gaps):
+    """White noise: <a, b> = sum over retained samples of a b / sigma^2."""
+    N, sig2 = 512, 2.5
+    rng = np.random.default_rng(11)
+    mask = np.zeros(N, dtype=bool)
+    for a, ln in gaps:
+        mask[a:a + ln] = True
+    acf = np.zeros(N)
+    acf[0] = sig2
+    f = oracle.factor(acf, N, mask, segments)
+    keep = np.zeros(N, dtype=bool)
+    keep[np.concatenate(oracle.retained_indices(N, mask, segments))] = True
+    d, H = rng.standard_normal(N), rng.standard_normal((5, N))
+    dh, hh = oracle.snr.inner_products(f, d, H)
+    np.testing.assert_allclose(dh, (H[:, keep] @ d[keep]) / sig2, rtol=1e-13)
+    np.testing.assert_allclose(hh, np.sum(H[:, keep] ** 2, axis=1) / sig2, rtol=1e-13)
+
+
+def test_inner_products_ar1_closed_form():
+    """AR(1): <a, b> = (Prais-Winsten whitened a) . (Prais-Winsten whitened b)."""
+    N, s, phi = 700, 0.7, 0.83
+    rng = np.random.default_rng(12)
+    f = oracle.factor(ar1_acf(N, s, phi), N)
+    d, H = rng.standard_normal(N), rng.standard_normal((4, N))
+    dh, hh = oracle.snr.inner_products(f, d, H)
+    wd, wh = ar1_whiten_closed(d, s, phi), ar1_whiten_closed(H, s, phi)
+    np.testing.assert_allclose(dh, wh @ wd, rtol=1e-11)
+    np.testing.assert_allclose(hh, np.sum(wh * wh, axis=1), rtol=1e-11)
+
+
+def test_inner_products_gs_route_and_split_identity():
+    """Gap-free Toeplitz: <h,h> from the Gohberg-Semencul quadratic form, <d,h> by
+    polarisation (q(d+h) - q(d-h))/4, and the split q = <d,d> - 2<d,h> + <h,h> of logL."""
+    N = 600
+    acf = synth.make_acf(N, eps=1e-4)
+    rng = np.random.default_rng(13)
+    d, H = rng.standard_normal(N), rng.standard_normal((3, N))
+    f = oracle.factor(acf, N)
+    dh, hh = oracle.snr.inner_products(f, d, H)
+    np.testing.assert_allclose(hh, gsce.gs_quadratic_form(acf, H), rtol=1e-9)
+    pol = (gsce.gs_quadratic_form(acf, d[None] + H) - gsce.gs_quadratic_form(acf, d[None] - H)) / 4
+    np.testing.assert_allclose(dh, pol, rtol=1e-8, atol=1e-8 * np.abs(hh).max())
+    dd = float(gsce.gs_quadratic_form(acf, d[None])[0])
+    q = -2.0 * (oracle.loglik(f, d, H) + 0.5 * f.logdet + 0.5 * f.n_eff * LOG2PI)
+    np.testing.assert_allclose(q, dd - 2 * dh + hh, rtol=1e-10)
+    rho_mf, rho_eff2 = oracle.snr.snrs(f, d, H)
+    np.testing.assert_allclose(rho_mf, dh / np.sqrt(hh), rtol=1e-12)
+    np.testing.assert_allclose(rho_eff2, 2 * dh - hh, rtol=1e-9, atol=1e-9 * np.abs(hh).max())
+
+
+def test_planted_inner_product_mistake_is_caught():
+    """A <d,h> taken with C instead of C^-1 fails the white-noise pin (sigma^2 != 1)."""
+    N, sig2 = 64, 3.0
+    acf = np.zeros(N)
+    acf[0] = sig2
+    f = oracle.factor(acf, N)
+    rng = np.random.default_rng(14)
+    d, H = rng.standard_normal(N), rng.standard_normal((2, N))
+    wrong = H @ (sig2 * d)
+    dh, _ = oracle.snr.inner_products(f, d, H)
+    assert not np.allclose(wrong, dh, rtol=1e-3)
+    np.testing.assert_allclose(dh, H @ d / sig2, rtol=1e-13)
+
+
 # ---------------------------------------------------------------- invariants
 
 def test_invariants():
