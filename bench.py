@@ -231,6 +231,32 @@ def main():
         for h in hg:
             h.close()
 
+    # explicit-inverse FP64 evaluation (the paper's CDO form) on the same mixed handles:
+    # one call per detector, network sum on the host side of the comparison
+    csteps = max(3, args.steps // 4)
+    cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
+    torch.cuda.synchronize()
+    tda.timing_read(reset=True)
+    tda.timing_enable(True)
+    t = time.perf_counter()
+    for _ in range(csteps):
+        cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
+    torch.cuda.synchronize()
+    wall_c = time.perf_counter() - t
+    tda.timing_enable(False)
+    kt_c = tda.timing_read(reset=True)
+    res_c = sum(o.cpu().numpy() for o in cdo_out)
+    cc, tc = kt_c["cdo_f64"]
+    ach_c = float(sum(n * n for n in n_eff)) / len(n_eff) * inst.B / (tc / cc * 1e-3)
+    cdo = {"value": inst.B * csteps / wall_c, "unit": "evals/s", "ms_per_step": wall_c / csteps * 1e3,
+           "steps": csteps, "max_abs_dlogL_vs_fp64_gpu": float(np.abs(res_c - res_f).max()),
+           "kernels_ms": {k: v[1] / v[0] for k, v in kt_c.items()},
+           "roofline": {"bound": "mfma", "kernel": "cdo_f64", "achieved": ach_c / 1e12,
+                        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach_c / PEAK_FP64,
+                        "avg_ms": tc / cc}}
+    log("cdo", cdo)
+    del cdo_out
+
     # inner products behind the SNRs (tda_loglik_terms): mixed per detector, timed, and
     # compared with the FP64 evaluation of the same terms on the GPU
     tsteps = max(3, args.steps // 4)
@@ -300,6 +326,7 @@ def main():
                               "frac": ach_f / PEAK_FP64, "avg_ms": tf / cf}},
         "speedup_mixed_vs_fp64": evals_m / evals_f,
         "gs_fp64": gs,
+        "cdo_fp64": cdo,
         "snr_terms": snr_terms,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),

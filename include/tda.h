@@ -42,6 +42,15 @@
  *                     template, no factorisation).  Only for segments without
  *                     excluded samples and of at most 16384 samples; a GS handle
  *                     evaluates only in TDA_PREC_GS.
+ *   TDA_PREC_CDO   -- an evaluation precision of mixed handles (not a handle
+ *                     precision): FP64 through the explicit inverse, the
+ *                     paper's CDO form (Sec. III.A.2: w = W (d - h) with
+ *                     W = L^-1 precomputed), as one FP64 matrix-core product
+ *                     per block instead of the forward substitution of
+ *                     TDA_PREC_FP64.  It uses the FP64 W = L^-1 that a mixed
+ *                     handle keeps for its data whitening; the explicit
+ *                     inverse is less stable than the substitution (its
+ *                     forward error grows with kappa(L)).
  *
  * Conventions for every entry point:
  *   - Returns a tda_status; nothing is thrown across the ABI.  On failure a
@@ -77,7 +86,7 @@ typedef enum {
   TDA_EAGAIN = 8     /* serving: request not admitted now, retry later */
 } tda_status;
 
-typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1, TDA_PREC_GS = 2 } tda_precision;
+typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1, TDA_PREC_GS = 2, TDA_PREC_CDO = 3 } tda_precision;
 
 /* TDA_FLAG_COMPACT (mixed handles): once tda_set_data has cached the whitened
  * data, release the FP64 solve panels and the FP64 whitening operator, keeping
@@ -178,8 +187,8 @@ tda_status tda_loglik(tda_handle h, const double *d, const double *H, int64_t B,
                       double *out, void *hip_stream);
 
 /* As tda_loglik, with the precision chosen per call: a mixed handle may
- * also be evaluated in TDA_PREC_FP64; an FP64 handle rejects
- * TDA_PREC_MIXED with ESTATE. */
+ * also be evaluated in TDA_PREC_FP64 and TDA_PREC_CDO; an FP64 handle
+ * rejects TDA_PREC_MIXED and TDA_PREC_CDO with ESTATE. */
 tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t B, int64_t ldh,
                          double *out, int32_t precision, void *hip_stream);
 
@@ -212,7 +221,8 @@ tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int6
  * templates) items, e.g. all detectors of all instances (Sec. II.B item 3).
  * Items whose `out` pointers are equal are summed into that array in item
  * order (network logL); otherwise each out is written.  All handles must be
- * factored, live on one device and be evaluated in `precision`.  The work of
+ * factored, live on one device and be evaluated in `precision` (FP64, MIXED
+ * or GS; TDA_PREC_CDO is per handle only and gives EINVAL here).  The work of
  * all items of one precision runs in the same kernel launches.
  * Asynchronous on hip_stream.
  */

@@ -18,7 +18,7 @@ __all__ = ["TdaError", "Handle", "loglik_multi", "load_library", "LIB_PATH",
            "PREC_FP64", "PREC_MIXED", "EXPORTED_SYMBOLS"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
-PREC_FP64, PREC_MIXED, PREC_GS = 0, 1, 2
+PREC_FP64, PREC_MIXED, PREC_GS, PREC_CDO = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
     "tda_loglik_terms", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
@@ -129,7 +129,7 @@ def _precision(p) -> int:
     if p in (None,):
         return None
     if isinstance(p, str):
-        return {"fp64": PREC_FP64, "mixed": PREC_MIXED, "gs": PREC_GS}[p.lower()]
+        return {"fp64": PREC_FP64, "mixed": PREC_MIXED, "gs": PREC_GS, "cdo": PREC_CDO}[p.lower()]
     return int(p)
 
 

@@ -461,6 +461,148 @@ void register_kernel_attributes() {
                       (int)(sizeof(double) * CP * TS));
 }
 
+// ---------------------------------------------------------------- explicit-inverse (CDO) FP64 form
+// Residual rows per template: R[b][r] = d[idx[r]] - h_b[idx[r]] on retained rows, 0 on
+// padding rows and on the padded templates b >= B.  grid (n_pad / 256, <= 65535), the
+// templates strided over grid.y
+__global__ void k_cdo_pack(const CdoItem *__restrict__ items) {
+  const CdoItem &it = items[0];
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= it.n_pad) return;
+  const int32_t p = it.idx[r];
+  for (int64_t b = blockIdx.y; b < it.Bp; b += gridDim.y) {
+    double v = 0.0;
+    if (b < it.B && p >= 0) v = it.d[p] - it.H[b * it.ldh + p];
+    it.R[b * it.n_pad + r] = v;
+  }
+}
+
+hipError_t launch_cdo_pack(const CdoItem *it_dev, const CdoItem &it, hipStream_t s) {
+  dim3 grid((unsigned)((it.n_pad + 255) / 256), (unsigned)(it.Bp < 65535 ? it.Bp : 65535));
+  hipLaunchKernelGGL(k_cdo_pack, grid, dim3(256), 0, s, it_dev);
+  return hipGetLastError();
+}
+
+// One 16-column group of the K loop: every lane loads four consecutive columns of its row
+// of W (A) and of its template's residual (B).  Matrix-core k-step j of the group takes
+// column 16 q + 4 g + j from lane group g = lane / 16, for A and B alike; the order of
+// the columns inside the sum is the only thing this permutes.
+struct CdoStep {
+  d4 a[4], b[4];
+};
+
+// w[rows of block i][templates T0 .. T0 + 63] over the 16-column groups q of [q0, q0 + nq)
+// (walked downwards when dir < 0), four waves of 64 rows x 64 templates.
+__device__ __forceinline__ void cdo_block(const CdoItem &it, int i, int64_t T0, int dir,
+                                          double *partrow) {
+  __shared__ double red[4][CDO_T];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, lc = lane & 15;
+  const int bf = it.blk_first[i];
+  const int64_t q0 = (int64_t)bf * (TB / 16), nq = (int64_t)(i + 1 - bf) * (TB / 16);
+  const int64_t row0 = (int64_t)i * TB + 64 * w + lc;
+  const double *Rb = it.R + (T0 + lc) * it.n_pad + 4 * g;
+  auto load = [&](int64_t k, CdoStep &st) __attribute__((always_inline)) {
+    const int64_t kk = k < nq ? k : nq - 1;
+    const int64_t q = dir > 0 ? q0 + kk : q0 + nq - 1 - kk;
+    const int64_t ct = q >> 1;
+    const double *Wt = it.w64 + it.w64_off[ct] + 16 * (q & 1) + 4 * g;
+    const int64_t rb = it.w64_rb[ct];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      st.a[t] = *(const d4 *)(Wt + (row0 + 16 * t - rb) * 32);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      st.b[c] = *(const d4 *)(Rb + (int64_t)16 * c * it.n_pad + 16 * q);
+  };
+  d4 acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[t][c] = d4{0, 0, 0, 0};
+  CdoStep st[3];
+  load(0, st[0]);
+  load(1, st[1]);
+  int64_t k = 0;
+  for (; k + 3 <= nq; k += 3) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      load(k + u + 2, st[(u + 2) % 3]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[t][c] = mfma64(st[u].a[t][j], st[u].b[c][j], acc[t][c]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // the K range is a multiple of 16 groups: 0, 1 or 2 groups remain, in the first stages
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+    if (k + u < nq)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            acc[t][c] = mfma64(st[u].a[t][j], st[u].b[c][j], acc[t][c]);
+  // per template: sum of squares over the wave's 64 rows (lanes g = 0..3 of a column hold
+  // four rows each of every 16-row tile), then over the four waves in LDS
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double ss = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ss += acc[t][c][v] * acc[t][c][v];
+    ss += __shfl_xor(ss, 16);
+    ss += __shfl_xor(ss, 32);
+    if (g == 0) red[w][16 * c + lc] = ss;
+  }
+  __syncthreads();
+  if (threadIdx.x < CDO_T)
+    partrow[T0 + threadIdx.x] = red[0][threadIdx.x] + red[1][threadIdx.x] +
+                                red[2][threadIdx.x] + red[3][threadIdx.x];
+  __syncthreads();
+}
+
+// Work entries (item 0, block, template group of 64, 0): block l of a segment and its
+// partner nb - 1 - l, the second with K walked downwards (as the BF16x3 products).
+__global__ __launch_bounds__(256, 1) void k_cdo(const CdoItem *__restrict__ items,
+                                                const int4 *__restrict__ work) {
+  const int4 wk = work[blockIdx.x];
+  if (wk.y < 0) return;
+  const CdoItem &it = items[wk.x];
+  const int64_t T0 = (int64_t)wk.z * CDO_T;
+  const int partner = it.blk_first[wk.y] + it.blk_last[wk.y] - wk.y;
+  cdo_block(it, wk.y, T0, 1, it.part + (int64_t)wk.y * it.Bp);
+  if (partner != wk.y) cdo_block(it, partner, T0, -1, it.part + (int64_t)partner * it.Bp);
+}
+
+hipError_t launch_cdo(const CdoItem *it_dev, const int4 *work, int64_t n_work, hipStream_t s) {
+  if (n_work <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cdo, dim3((unsigned)n_work), dim3(256), 0, s, it_dev, work);
+  return hipGetLastError();
+}
+
+// out[b] = -1/2 sum_i part[i][b] + cterm, blocks in order
+__global__ void k_cdo_finish(const CdoItem *__restrict__ items, int64_t B) {
+  const CdoItem &it = items[0];
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  double q = 0.0;
+  for (int i = 0; i < it.nblk; ++i) q += it.part[(int64_t)i * it.Bp + b];
+  it.out[b] = -0.5 * q + it.cterm;
+}
+
+hipError_t launch_cdo_finish(const CdoItem *it_dev, int64_t B, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cdo_finish, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, it_dev, B);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- network sums
 // out_g[b] = sum over the items of group g (in item order) of parts_item[b].
 __global__ void k_combine(const double *__restrict__ parts, const int64_t *__restrict__ part_off,

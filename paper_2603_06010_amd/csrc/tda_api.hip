@@ -224,6 +224,7 @@ struct tda_ctx {
   DevBuf ws_scratch, ws_tiles, ws_items;
   DevBuf ws_hs_hi, ws_hs_lo, ws_w0_hi, ws_w0_lo, ws_y0, ws_fft, ws_work, ws_mix, ws_ref;
   DevBuf ws_zero, ws_terms;  // inner-product entry point: zero vector [N], <h,h> and <d,d>
+  DevBuf ws_cdo;             // explicit-inverse evaluation: residual rows and block sums
   hipEvent_t done = nullptr;  // last enqueued work of this handle
   DescRing ring;
   std::vector<SegDev> segdev_h;
@@ -666,6 +667,8 @@ static tda_status loglik_f64(tda_ctx *h, const double *d, const double *H, int64
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
                                int64_t ldh, double *out, hipStream_t s, double *out_dh = nullptr,
                                double *out_hh = nullptr);
+static tda_status loglik_cdo(tda_ctx *h, const double *d, const double *H, int64_t B,
+                             int64_t ldh, double *out, hipStream_t s);
 
 // Argument checks shared by the single-handle evaluation entry points.
 static tda_status check_eval(tda_handle h, const double *d, const double *H, int64_t B,
@@ -677,10 +680,13 @@ static tda_status check_eval(tda_handle h, const double *d, const double *H, int
   if (B > (int64_t)1 << 30) return fail_with(TDA_EINVAL, "B too large");
   if (!d || !H || !out) return fail_with(TDA_EINVAL, "NULL device pointer");
   if (ldh < h->N) return fail_with(TDA_EINVAL, "ldh < N");
-  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED && precision != TDA_PREC_GS)
+  if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED && precision != TDA_PREC_GS &&
+      precision != TDA_PREC_CDO)
     return fail_with(TDA_EINVAL, "unknown precision");
   if (precision == TDA_PREC_MIXED && h->precision != TDA_PREC_MIXED)
     return fail_with(TDA_ESTATE, "mixed evaluation needs a handle built with TDA_PREC_MIXED");
+  if (precision == TDA_PREC_CDO && (h->precision != TDA_PREC_MIXED || h->compacted))
+    return fail_with(TDA_ESTATE, "explicit-inverse evaluation needs a (non-compact) mixed handle");
   if ((precision == TDA_PREC_GS) != (h->precision == TDA_PREC_GS))
     return fail_with(TDA_ESTATE, "a GS handle evaluates only (and only it) in TDA_PREC_GS");
   if (h->compacted && (precision == TDA_PREC_FP64 || d != h->data_ptr))
@@ -709,6 +715,8 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
     TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
   else if (precision == TDA_PREC_GS)
     TDA_TRY(loglik_gs(h, d, H, B, ldh, out, s));
+  else if (precision == TDA_PREC_CDO)
+    TDA_TRY(loglik_cdo(h, d, H, B, ldh, out, s));
   else
     TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s));
   return mark_done(h, s);
@@ -730,8 +738,9 @@ extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const doub
     return mark_done(h, s);
   }
   auto eval = [&](const double *dd, const double *HH, int64_t BB, int64_t ld, double *o) {
-    return precision == TDA_PREC_FP64 ? loglik_f64(h, dd, HH, BB, ld, o, s)
-                                      : loglik_gs(h, dd, HH, BB, ld, o, s);
+    return precision == TDA_PREC_FP64  ? loglik_f64(h, dd, HH, BB, ld, o, s)
+           : precision == TDA_PREC_CDO ? loglik_cdo(h, dd, HH, BB, ld, o, s)
+                                       : loglik_gs(h, dd, HH, BB, ld, o, s);
   };
   TDA_TRY(eval(d, H, B, ldh, out));
   if (out_dh || out_hh) {
@@ -1051,16 +1060,16 @@ static void add_refine_pairs(int32_t item, int64_t B, std::vector<int4> &wr) {
     wr.push_back(int4{item, (int32_t)b, b + 1 < B ? (int32_t)(b + 1) : -1, 0});
 }
 
-// product jobs: (block pair, group of 256 templates, half); see the product kernels for
-// pairs and halves.  A job is named by the first block of its pair, the lower index; its
+// product jobs: (block pair, template group, half); see the product kernels for pairs
+// and halves.  A job is named by the first block of its pair, the lower index; its
 // weight is the K the pair spans, the same for both products.
-static void add_block_jobs(const tda_ctx *h, int32_t item, int64_t Bp, int32_t nsub,
+static void add_block_jobs(const tda_ctx *h, int32_t item, int32_t ntg, int32_t nsub,
                            std::vector<BlockJob> &jobs) {
   for (int32_t i = 0; i < h->nblk; ++i) {
     const int32_t bf = h->blk_first_h[i], bl = h->blk_last_h[i], partner = bf + bl - i;
     if (partner < i) continue;  // second block of a pair
     const int64_t k = partner == i ? (int64_t)(i + 1 - bf) : (int64_t)(bl - bf + 2);
-    jobs.push_back(BlockJob{item, i, (int32_t)(Bp / 256), nsub, k});
+    jobs.push_back(BlockJob{item, i, ntg, nsub, k});
   }
 }
 
@@ -1095,8 +1104,8 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   std::vector<int2> wfin, wrl;
   for (int64_t k = 0; k < n; ++k) {
     if (mis[k].B == 0) continue;
-    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, 1, jf);
-    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp, 2, jh);
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp / 256, 1, jf);
+    add_block_jobs(hs[k], (int32_t)k, mis[k].Bp / 256, 2, jh);
     const bool in_lds = hs[k]->max_m <= RL_MAX_M;
     if (!in_lds) add_refine_pairs((int32_t)k, mis[k].B, wr);
     for (int32_t b = 0; b < mis[k].B; ++b) {
@@ -1192,6 +1201,52 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   return TDA_OK;
 }
 
+// Explicit-inverse FP64 evaluation: residual rows packed per template, one FP64
+// matrix-core product per (block pair, 64 templates) against the FP64 W = L^-1 of the
+// mixed handle, block sums of squares added in block order.
+static tda_status loglik_cdo(tda_ctx *h, const double *d, const double *H, int64_t B,
+                             int64_t ldh, double *out, hipStream_t s) {
+  const int64_t Bp = (B + CDO_T - 1) / CDO_T * CDO_T;
+  const size_t r_bytes = (size_t)Bp * h->n_pad * sizeof(double);
+  TDA_TRY(h->alloc(h->ws_cdo, r_bytes + (size_t)h->nblk * Bp * sizeof(double)));
+  CdoItem it{};
+  it.w64 = (const double *)h->w64_d.p;
+  it.w64_off = (const int64_t *)h->w64_off_d.p;
+  it.w64_rb = (const int32_t *)h->w64_rb_d.p;
+  it.blk_first = (const int32_t *)h->blk_first_d.p;
+  it.blk_last = (const int32_t *)h->blk_last_d.p;
+  it.idx = (const int32_t *)h->idx_d.p;
+  it.d = d;
+  it.H = H;
+  it.ldh = ldh;
+  it.R = (double *)h->ws_cdo.p;
+  it.part = (double *)((char *)h->ws_cdo.p + r_bytes);
+  it.out = out;
+  it.cterm = h->cterm();
+  it.B = (int32_t)B;
+  it.Bp = (int32_t)Bp;
+  it.nblk = h->nblk;
+  it.n_pad = (int32_t)h->n_pad;
+  std::vector<BlockJob> jobs;
+  add_block_jobs(h, 0, (int32_t)(Bp / CDO_T), 1, jobs);
+  const std::vector<int4> work = xcd_order(jobs);
+  HIP_TRY(h->ring.reserve(1024 + sizeof(CdoItem) + work.size() * sizeof(int4)));
+  void *d_it, *d_w;
+  HIP_TRY(h->ring.push(&it, sizeof(CdoItem), s, &d_it));
+  HIP_TRY(h->ring.push(work.data(), work.size() * sizeof(int4), s, &d_w));
+  {
+    TimedScope ts("cdo_pack", s);
+    HIP_TRY(launch_cdo_pack((const CdoItem *)d_it, it, s));
+  }
+  {
+    TimedScope ts("cdo_f64", s);
+    HIP_TRY(launch_cdo((const CdoItem *)d_it, (const int4 *)d_w, (int64_t)work.size(), s));
+  }
+  HIP_TRY(launch_cdo_finish((const CdoItem *)d_it, B, s));
+  HIP_TRY(h->ring.seal(s));
+  return TDA_OK;
+}
+
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
                                int64_t ldh, double *out, hipStream_t s, double *out_dh,
                                double *out_hh) {
@@ -1284,6 +1339,8 @@ namespace {
 tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *const *hrows,
                       int64_t n_items, int32_t precision, hipStream_t s, bool order_handles) {
   if (n_items == 0) return TDA_OK;
+  if (precision == TDA_PREC_CDO)
+    return fail_with(TDA_EINVAL, "explicit-inverse evaluation is per handle (tda_loglik_ex)");
   if (precision != TDA_PREC_FP64 && precision != TDA_PREC_MIXED && precision != TDA_PREC_GS)
     return fail_with(TDA_EINVAL, "unknown precision");
   const int dev = items[0].h ? items[0].h->device : -1;

@@ -41,6 +41,32 @@ struct TrsmItem {
 
 enum { MODE_LOGLIK = 0, MODE_IDENTITY = 1 };
 
+// Explicit-inverse FP64 evaluation (the paper's CDO form, Sec. III.A.2): w = W (d - h)
+// with W = L^-1 held in FP64 in compact column tiles (tile ct of 32 columns holds rows
+// [rb[ct], segment end) at w64[off[ct] + (r - rb[ct]) 32 + c % 32]) and the residuals
+// packed per template, R[b][r] = d[idx[r]] - h_b[idx[r]] (0 at padding), row stride n_pad.
+// A workgroup forms a 256-row block of w for 64 templates and writes per template the
+// sum of squares of its rows to part[block][b]; cdo_finish sums the blocks in order.
+constexpr int CDO_T = 64;  // templates per workgroup
+struct CdoItem {
+  const double *w64;
+  const int64_t *w64_off;  // [n_pad / 32]
+  const int32_t *w64_rb;   // [n_pad / 32]
+  const int32_t *blk_first, *blk_last;
+  const int32_t *idx;      // [n_pad]
+  const double *d;
+  const double *H;
+  int64_t ldh;
+  double *R;               // [Bp][n_pad]
+  double *part;            // [nblk][Bp]
+  double *out;             // [B]
+  double cterm;
+  int32_t B, Bp, nblk, n_pad;
+};
+hipError_t launch_cdo_pack(const CdoItem *it_dev, const CdoItem &it, hipStream_t s);
+hipError_t launch_cdo(const CdoItem *it_dev, const int4 *work, int64_t n_work, hipStream_t s);
+hipError_t launch_cdo_finish(const CdoItem *it_dev, int64_t B, hipStream_t s);
+
 // One workgroup of the FP64 solve: 32 columns of one item over block rows [blk_begin, blk_end).
 struct TrsmTile {
   int32_t item;
