@@ -231,6 +231,28 @@ def main():
         for h in hg:
             h.close()
 
+    # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
+    # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
+    # N = 16384 covariance
+    xs = torch.from_numpy(synth.stationary_noise(np.random.default_rng(7), 1 << 20, 1)[0]).to(dev)
+    acf_line = {}
+    for meth, seg in (("welch", 32768), ("direct", None)):
+        tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            est = tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) / 3 * 1e3
+        n_x = xs.shape[0]
+        macs = ((n_x - seg) // (seg // 2) + 1) * seg * 16384 if seg else n_x * 16384
+        true = synth.make_acf(8)
+        acf_line[meth] = {"ms": ms, "gmac_per_s": macs / ms * 1e-6,
+                          "max_abs_err_first_8_lags_vs_true": float(np.abs(est[:8].cpu().numpy() - true).max())}
+    acf_line["input"] = "2^20 samples of noise with the benchmark covariance; 16384 lags; Welch 32768-sample segments"
+    log("acf", acf_line)
+    del xs
+
     # explicit-inverse FP64 evaluation (the paper's CDO form) on the same mixed handles:
     # one call per detector, network sum on the host side of the comparison
     csteps = max(3, args.steps // 4)
@@ -327,6 +349,7 @@ def main():
         "speedup_mixed_vs_fp64": evals_m / evals_f,
         "gs_fp64": gs,
         "cdo_fp64": cdo,
+        "acf_estimate": acf_line,
         "snr_terms": snr_terms,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),

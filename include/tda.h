@@ -217,6 +217,33 @@ tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int6
                             int32_t precision, void *hip_stream);
 
 /*
+ * tda_acf_estimate -- autocovariance of a stretch of strain, for building the
+ * covariance (Sec. II.B item 6: correlate the data directly, or take a Welch
+ * PSD and its inverse Fourier transform, then truncate to the lags needed).
+ *   x        device float64[n]: the strain (no signal in it).
+ *   n_lags   lags written to acf[0 .. n_lags).
+ *   method   TDA_ACF_DIRECT: acf[k] = (1/n) sum_{t < n-k} x_t x_{t+k}
+ *            (biased sample autocovariance; n_lags <= n).
+ *            TDA_ACF_WELCH: segments of seg_len samples, half overlapping
+ *            (K = (n - seg_len) / (seg_len/2) + 1 of them), each with its mean
+ *            removed and multiplied by the periodic Hann window w; then
+ *            acf[k] = (1/K) sum_s sum_j y_s[j] y_s[(j+k) mod seg_len] / sum_j w_j^2,
+ *            which equals the inverse DFT of the two-sided, mean-averaged Welch
+ *            PSD (density scaling) times the sampling rate.  seg_len even and
+ *            >= 2, n >= seg_len, n_lags <= seg_len / 2.
+ *   seg_len  Welch segment length (ignored by TDA_ACF_DIRECT).
+ *   acf      device float64[n_lags], written.
+ * Units are those of x squared, as tda_cov_build takes them (a prefix of the
+ * result serves a shorter segment).  Sums run in a fixed
+ * order (reproducible).  The workspace is stream-ordered device memory
+ * released on the stream.  Asynchronous on hip_stream.
+ * Errors: EINVAL (sizes, method), ENOMEM, EHIP, ESTATE (capturing stream).
+ */
+typedef enum { TDA_ACF_DIRECT = 0, TDA_ACF_WELCH = 1 } tda_acf_method;
+tda_status tda_acf_estimate(const double *x, int64_t n, int64_t n_lags, int32_t method,
+                            int64_t seg_len, double *acf, void *hip_stream);
+
+/*
  * tda_loglik_multi -- one batched evaluation over many (handle, data,
  * templates) items, e.g. all detectors of all instances (Sec. II.B item 3).
  * Items whose `out` pointers are equal are summed into that array in item

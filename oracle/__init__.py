@@ -13,6 +13,8 @@ Contents
             recursion (C x = e1 and log det) and the Gohberg-Semencul quadratic
             form evaluated with circulant-embedded FFT Toeplitz products.
   snr    -- matched-filter and effective SNR from the same inner product.
+  acf    -- autocovariance estimates from strain: direct correlation, and a
+            Welch PSD followed by its inverse Fourier transform.
 
 Pinning: every function here is checked by ``tests/test_oracle_pins.py``
 against closed forms (white noise, AR(1), gapped AR(1)), brute force at 50
@@ -23,4 +25,4 @@ from .tdlik import (  # noqa: F401
     LOG2PI, retained_indices, segment_covariance, Factor, factor, whiten,
     loglik, loglik_network, quad_forms,
 )
-from . import gsce, snr  # noqa: F401
+from . import acf, gsce, snr  # noqa: F401

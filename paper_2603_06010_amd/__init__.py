@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["TdaError", "Handle", "loglik_multi", "load_library", "LIB_PATH",
+__all__ = ["TdaError", "Handle", "loglik_multi", "acf_estimate", "load_library", "LIB_PATH",
            "timing_enable", "timing_read", "Server", "Plan",
            "PREC_FP64", "PREC_MIXED", "EXPORTED_SYMBOLS"]
 
@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
 PREC_FP64, PREC_MIXED, PREC_GS, PREC_CDO = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-    "tda_loglik_terms", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_terms", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_loglik.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
     L.tda_loglik_terms.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, i32, vp]
+    L.tda_acf_estimate.argtypes = [vp, i64, i64, i32, i64, vp, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
     L.tda_info.argtypes = [vp, ctypes.POINTER(_Info)]
     L.tda_destroy.argtypes = [vp]
@@ -96,7 +97,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_timing_enable.argtypes = [i32]
     L.tda_timing_read.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-              "tda_loglik_terms", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
+              "tda_loglik_terms", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
               "tda_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -253,6 +254,23 @@ def timing_read(reset: bool = True) -> dict:
     _check(L.tda_timing_read(ctypes.cast(arr, ctypes.c_void_p), 64, ctypes.byref(n),
                              1 if reset else 0))
     return {arr[k].name.decode(): (arr[k].count, arr[k].total_ms) for k in range(min(n.value, 64))}
+
+
+ACF_DIRECT, ACF_WELCH = 0, 1
+
+
+def acf_estimate(x, n_lags, method="welch", seg_len=None, stream=None):
+    """Autocovariance of the device float64 strain x through tda_acf_estimate; returns a
+    new device tensor of n_lags values."""
+    import torch
+    L = load_library()
+    m = {"direct": ACF_DIRECT, "welch": ACF_WELCH}[method] if isinstance(method, str) else int(method)
+    if x.dtype != torch.float64 or x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous 1-D float64 tensor")
+    out = torch.empty(n_lags, dtype=torch.float64, device=x.device)
+    _check(L.tda_acf_estimate(_ptr(x), x.shape[0], n_lags, m, int(seg_len or 0), _ptr(out),
+                              _stream(stream)))
+    return out
 
 
 def loglik_multi(items, precision="fp64", stream=None):

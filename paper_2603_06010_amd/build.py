@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtda.so")
-SOURCES = ["tda_api.hip", "kernels_f64.hip", "kernels_mixed.hip", "serve.hip", "autotune.hip"]
+SOURCES = ["tda_api.hip", "kernels_f64.hip", "kernels_mixed.hip", "serve.hip", "autotune.hip",
+           "acf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

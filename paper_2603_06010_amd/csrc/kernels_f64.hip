@@ -455,6 +455,7 @@ hipError_t launch_trsm_f64_single(const TrsmItem &it, int32_t nblk, int64_t n_ti
 
 void register_kernel_attributes() {
   register_mixed_attributes();
+  register_acf_attributes();
   hipFuncSetAttribute((const void *)k_potf2, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)(sizeof(double) * CP * TS));
   hipFuncSetAttribute((const void *)k_diag_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,

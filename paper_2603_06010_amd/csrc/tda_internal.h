@@ -304,5 +304,6 @@ size_t handle_bytes(tda_handle h);
 bool handle_ready(tda_handle h, int32_t precision);
 tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s);
 tda_status set_error(tda_status st, const char *msg);
+void register_acf_attributes();
 
 }  // namespace tda

@@ -288,6 +288,57 @@ def test_planted_inner_product_mistake_is_caught():
     np.testing.assert_allclose(dh, H @ d / sig2, rtol=1e-13)
 
 
+# ---------------------------------------------------------------- autocovariance estimates
+
+def test_acf_direct_closed_forms_and_brute_force():
+    """Constant input: acf[k] = c^2 (n-k)/n; an impulse: acf = (1/n, 0, ...); and a
+    double loop on a small random input."""
+    n = 50
+    c = 1.7
+    np.testing.assert_allclose(oracle.acf.acf_direct(np.full(n, c), 20),
+                               c * c * (n - np.arange(20)) / n, rtol=1e-14)
+    x = np.zeros(n)
+    x[13] = 1.0
+    want = np.zeros(10)
+    want[0] = 1.0 / n
+    np.testing.assert_allclose(oracle.acf.acf_direct(x, 10), want, atol=1e-16)
+    x = np.random.default_rng(21).standard_normal(37)
+    brute = [sum(x[t] * x[t + k] for t in range(37 - k)) / 37 for k in range(37)]
+    np.testing.assert_allclose(oracle.acf.acf_direct(x, 37), brute, rtol=1e-12, atol=1e-15)
+
+
+def test_acf_welch_library_route_and_lag_domain_identity():
+    """The Welch estimate equals scipy.signal.welch (two-sided, density, mean) followed by
+    the inverse DFT, and equals the lag-domain circular autocorrelation of the windowed,
+    mean-removed segments (Wiener-Khinchin), summed by plain loops."""
+    import scipy.signal as ss
+    rng = np.random.default_rng(22)
+    L, n, fs = 64, 64 * 5 + 17, 4096.0
+    x = rng.standard_normal(n) + 0.3
+    got = oracle.acf.acf_welch(x, L, L // 2, fs=fs)
+    f, P = ss.welch(x, fs=fs, window="hann", nperseg=L, noverlap=L // 2, detrend="constant",
+                    return_onesided=False, scaling="density", average="mean")
+    np.testing.assert_allclose(got, (fs * np.fft.ifft(P).real)[:L // 2], rtol=1e-12, atol=1e-15)
+    w = 0.5 - 0.5 * np.cos(2 * np.pi * np.arange(L) / L)
+    segs = [x[s:s + L] for s in range(0, n - L + 1, L // 2)]
+    lag = np.zeros(L // 2)
+    for seg in segs:
+        y = w * (seg - seg.mean())
+        for k in range(L // 2):
+            lag[k] += sum(y[j] * y[(j + k) % L] for j in range(L)) / np.sum(w * w)
+    np.testing.assert_allclose(got, lag / len(segs), rtol=1e-11, atol=1e-14)
+
+
+def test_acf_welch_white_noise_and_constant():
+    """Statistics of white noise of variance 4 (lag 0 near 4, other lags near 0), and
+    exactly zero for a constant input (mean removal)."""
+    rng = np.random.default_rng(23)
+    x = 2.0 * rng.standard_normal(1 << 16)
+    a = oracle.acf.acf_welch(x, 1024, 64)
+    assert abs(a[0] - 4.0) < 0.1 and np.max(np.abs(a[1:])) < 0.1
+    np.testing.assert_allclose(oracle.acf.acf_welch(np.full(4096, 3.0), 256, 16), 0.0, atol=1e-12)
+
+
 # ---------------------------------------------------------------- invariants
 
 def test_invariants():
