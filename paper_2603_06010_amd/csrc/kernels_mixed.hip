@@ -446,20 +446,22 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
                                          f16v (&acc)[4][PL<V>::WB], char *smem) {
   using L = PL<V>;
   constexpr int NS = L::LDS_STAGES, SB = 32 * FRAG * 2;
+  constexpr int FPW = 32 / L::NW;  // fragments each wave copies per stage
   static_assert(L::NW == 8 && NS >= 3, "LDS path: 8 waves, at least 3 stages");
   const int lane = tid & 63, w = tid >> 6;
   const int ta = L::ta(w), tb = L::tb(w);
-  // this wave's copies: array w >> 1, tiles 4 (w & 1) .. + 3
-  const int arr = w >> 1;
+  // this wave's copies: fragments FPW w .. FPW w + FPW - 1 of the stage, which lie in one
+  // array (A hi, A lo, B hi, B lo: 8 tiles each)
+  const int f0 = FPW * w, arr = f0 >> 3;
   const bool isA = arr < 2;
   const uint16_t *src = arr == 0 ? A.hi : arr == 1 ? A.lo : arr == 2 ? B.hi : B.lo;
   const int64_t s_tile = isA ? A.s_tile : B.s_tile, s_ks = isA ? A.s_ks : B.s_ks;
-  const uint16_t *gp = src + 4 * (w & 1) * s_tile + lane * 8;
-  char *const dst0 = smem + 4 * w * 1024;
+  const uint16_t *gp = src + (f0 & 7) * s_tile + lane * 8;
+  char *const dst0 = smem + f0 * 1024;
   auto issue = [&](int64_t ks, int slot) __attribute__((always_inline)) {
     const uint16_t *q = gp + (ks < nks ? ks : nks - 1) * s_ks;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < FPW; ++u)
       __builtin_amdgcn_global_load_lds((const void *)(q + u * s_tile),
                                        (lds_void_t *)(dst0 + slot * SB + u * 1024), 16, 0, 0);
   };
@@ -468,7 +470,7 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
   if (nks <= 0) return;
 #pragma unroll
   for (int p = 0; p < NS - 1; ++p) issue(p, p);
-  wait_vmcnt<4 * (NS - 2)>();
+  wait_vmcnt<FPW * (NS - 2)>();
   __builtin_amdgcn_s_barrier();
   Step<L::WB> r0, r1;
   lds_read_step<L::WB>(smem, ta, tb, lane, r0);
@@ -476,7 +478,7 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
   // of stage t - 1), LDS reads of stage t + 1 spread through the matrix-core ops of
   // stage t.  s1 is the slot of stage t + 1.
   auto kstep = [&](int64_t t, int s1, const Step<L::WB> &cur, Step<L::WB> &nxt) __attribute__((always_inline)) {
-    wait_vmcnt<4 * (NS - 3)>();
+    wait_vmcnt<FPW * (NS - 3)>();
     __builtin_amdgcn_s_barrier();
     issue(t + NS - 1, s1 == 0 ? NS - 2 : s1 == 1 ? NS - 1 : s1 - 2);
     lds_read_step<L::WB>(smem + s1 * SB, ta, tb, lane, nxt);
@@ -484,7 +486,7 @@ __device__ __forceinline__ void gemm_lds(const FragSrc &A, const FragSrc &B, int
     // matrix-core ops first: their operands were read a k-step ago, so the wait for them
     // does not also wait for the reads of the next stage
     constexpr int NR = 4 + 2 * L::WB + 4, NM = NPROD * 4 * L::WB;
-    __builtin_amdgcn_sched_group_barrier(0x020, 4, 0);        // the four copies
+    __builtin_amdgcn_sched_group_barrier(0x020, FPW, 0);      // the copies
     __builtin_amdgcn_sched_group_barrier(0x008, NM / NR, 0);  // matrix-core ops
 #pragma unroll
     for (int q = 0; q < NR - 1; ++q) {
