@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--core-only", action="store_true",
+                    help="c2: only the batched mixed and FP64 evaluations (for profiling runs); "
+                         "the Gohberg-Semencul, explicit-inverse, inner-product and ACF lines are null")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
                     help="c2 (default): two detectors x N=16384, 4096 templates per launch; "
                          "c4: 64 ragged instances in one batched evaluation; "
@@ -211,7 +214,7 @@ def main():
 
     # Gohberg-Semencul FP64 path on the same inputs (segments without excluded samples)
     gs = None
-    if not any(m is not None and np.any(m) for m in inst.masks):
+    if not args.core_only and not any(m is not None and np.any(m) for m in inst.masks):
         t0 = time.perf_counter()
         hg = [tda.Handle(inst.acf, inst.N, inst.masks[k], precision="gs").factor()
               for k in range(inst.n_det)]
@@ -231,79 +234,81 @@ def main():
         for h in hg:
             h.close()
 
-    # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
-    # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
-    # N = 16384 covariance
-    xs = torch.from_numpy(synth.stationary_noise(np.random.default_rng(7), 1 << 20, 1)[0]).to(dev)
-    acf_line = {}
-    for meth, seg in (("welch", 32768), ("direct", None)):
-        tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+    acf_line = cdo = snr_terms = None
+    if not args.core_only:
+        # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
+        # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
+        # N = 16384 covariance
+        xs = torch.from_numpy(synth.stationary_noise(np.random.default_rng(7), 1 << 20, 1)[0]).to(dev)
+        acf_line = {}
+        for meth, seg in (("welch", 32768), ("direct", None)):
+            tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                est = tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) / 3 * 1e3
+            n_x = xs.shape[0]
+            macs = ((n_x - seg) // (seg // 2) + 1) * seg * 16384 if seg else n_x * 16384
+            true = synth.make_acf(8)
+            acf_line[meth] = {"ms": ms, "gmac_per_s": macs / ms * 1e-6,
+                              "max_abs_err_first_8_lags_vs_true": float(np.abs(est[:8].cpu().numpy() - true).max())}
+        acf_line["input"] = "2^20 samples of noise with the benchmark covariance; 16384 lags; Welch 32768-sample segments"
+        log("acf", acf_line)
+        del xs
+
+        # explicit-inverse FP64 evaluation (the paper's CDO form) on the same mixed handles:
+        # one call per detector, network sum on the host side of the comparison
+        csteps = max(3, args.steps // 4)
+        cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
+        torch.cuda.synchronize()
+        tda.timing_read(reset=True)
+        tda.timing_enable(True)
+        t = time.perf_counter()
+        for _ in range(csteps):
+            cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
+        torch.cuda.synchronize()
+        wall_c = time.perf_counter() - t
+        tda.timing_enable(False)
+        kt_c = tda.timing_read(reset=True)
+        res_c = sum(o.cpu().numpy() for o in cdo_out)
+        cc, tc = kt_c["cdo_f64"]
+        ach_c = float(sum(n * n for n in n_eff)) / len(n_eff) * inst.B / (tc / cc * 1e-3)
+        cdo = {"value": inst.B * csteps / wall_c, "unit": "evals/s", "ms_per_step": wall_c / csteps * 1e3,
+               "steps": csteps, "max_abs_dlogL_vs_fp64_gpu": float(np.abs(res_c - res_f).max()),
+               "kernels_ms": {k: v[1] / v[0] for k, v in kt_c.items()},
+               "roofline": {"bound": "mfma", "kernel": "cdo_f64", "achieved": ach_c / 1e12,
+                            "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach_c / PEAK_FP64,
+                            "avg_ms": tc / cc}}
+        log("cdo", cdo)
+        del cdo_out
+
+        # inner products behind the SNRs (tda_loglik_terms): mixed per detector, timed, and
+        # compared with the FP64 evaluation of the same terms on the GPU
+        tsteps = max(3, args.steps // 4)
+        terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        for _ in range(3):
-            est = tda.acf_estimate(xs, 16384, method=meth, seg_len=seg)
+        for _ in range(tsteps):
+            terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t) / 3 * 1e3
-        n_x = xs.shape[0]
-        macs = ((n_x - seg) // (seg // 2) + 1) * seg * 16384 if seg else n_x * 16384
-        true = synth.make_acf(8)
-        acf_line[meth] = {"ms": ms, "gmac_per_s": macs / ms * 1e-6,
-                          "max_abs_err_first_8_lags_vs_true": float(np.abs(est[:8].cpu().numpy() - true).max())}
-    acf_line["input"] = "2^20 samples of noise with the benchmark covariance; 16384 lags; Welch 32768-sample segments"
-    log("acf", acf_line)
-    del xs
-
-    # explicit-inverse FP64 evaluation (the paper's CDO form) on the same mixed handles:
-    # one call per detector, network sum on the host side of the comparison
-    csteps = max(3, args.steps // 4)
-    cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
-    torch.cuda.synchronize()
-    tda.timing_read(reset=True)
-    tda.timing_enable(True)
-    t = time.perf_counter()
-    for _ in range(csteps):
-        cdo_out = [h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)]
-    torch.cuda.synchronize()
-    wall_c = time.perf_counter() - t
-    tda.timing_enable(False)
-    kt_c = tda.timing_read(reset=True)
-    res_c = sum(o.cpu().numpy() for o in cdo_out)
-    cc, tc = kt_c["cdo_f64"]
-    ach_c = float(sum(n * n for n in n_eff)) / len(n_eff) * inst.B / (tc / cc * 1e-3)
-    cdo = {"value": inst.B * csteps / wall_c, "unit": "evals/s", "ms_per_step": wall_c / csteps * 1e3,
-           "steps": csteps, "max_abs_dlogL_vs_fp64_gpu": float(np.abs(res_c - res_f).max()),
-           "kernels_ms": {k: v[1] / v[0] for k, v in kt_c.items()},
-           "roofline": {"bound": "mfma", "kernel": "cdo_f64", "achieved": ach_c / 1e12,
-                        "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "frac": ach_c / PEAK_FP64,
-                        "avg_ms": tc / cc}}
-    log("cdo", cdo)
-    del cdo_out
-
-    # inner products behind the SNRs (tda_loglik_terms): mixed per detector, timed, and
-    # compared with the FP64 evaluation of the same terms on the GPU
-    tsteps = max(3, args.steps // 4)
-    terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for _ in range(tsteps):
-        terms_m = [h.loglik_terms(dk, H, precision="mixed") for h, dk in zip(hs, d)]
-    torch.cuda.synchronize()
-    wall_t = time.perf_counter() - t
-    terms_f = [h.loglik_terms(dk, H, precision="fp64") for h, dk in zip(hs, d)]
-    torch.cuda.synchronize()
-    dh_m = sum(x[1] for x in terms_m).cpu().numpy()
-    hh_m = sum(x[2] for x in terms_m).cpu().numpy()
-    dh_f = sum(x[1] for x in terms_f).cpu().numpy()
-    hh_f = sum(x[2] for x in terms_f).cpu().numpy()
-    rho_m, rho_f = dh_m / np.sqrt(hh_m), dh_f / np.sqrt(hh_f)
-    snr_terms = {"value": inst.B * tsteps / wall_t, "unit": "evals/s (logL + <d,h> + <h,h>, "
-                 "network sums)", "ms_per_step": wall_t / tsteps * 1e3, "steps": tsteps,
-                 "max_abs_d_dh_mixed_vs_fp64_gpu": float(np.abs(dh_m - dh_f).max()),
-                 "max_abs_d_hh_mixed_vs_fp64_gpu": float(np.abs(hh_m - hh_f).max()),
-                 "max_abs_d_rho_mf_mixed_vs_fp64_gpu": float(np.abs(rho_m - rho_f).max()),
-                 "rho_mf_range": [float(rho_f.min()), float(rho_f.max())]}
-    log("snr terms", snr_terms)
-    del terms_m, terms_f
+        wall_t = time.perf_counter() - t
+        terms_f = [h.loglik_terms(dk, H, precision="fp64") for h, dk in zip(hs, d)]
+        torch.cuda.synchronize()
+        dh_m = sum(x[1] for x in terms_m).cpu().numpy()
+        hh_m = sum(x[2] for x in terms_m).cpu().numpy()
+        dh_f = sum(x[1] for x in terms_f).cpu().numpy()
+        hh_f = sum(x[2] for x in terms_f).cpu().numpy()
+        rho_m, rho_f = dh_m / np.sqrt(hh_m), dh_f / np.sqrt(hh_f)
+        snr_terms = {"value": inst.B * tsteps / wall_t, "unit": "evals/s (logL + <d,h> + <h,h>, "
+                     "network sums)", "ms_per_step": wall_t / tsteps * 1e3, "steps": tsteps,
+                     "max_abs_d_dh_mixed_vs_fp64_gpu": float(np.abs(dh_m - dh_f).max()),
+                     "max_abs_d_hh_mixed_vs_fp64_gpu": float(np.abs(hh_m - hh_f).max()),
+                     "max_abs_d_rho_mf_mixed_vs_fp64_gpu": float(np.abs(rho_m - rho_f).max()),
+                     "rho_mf_range": [float(rho_f.min()), float(rho_f.max())]}
+        log("snr terms", snr_terms)
+        del terms_m, terms_f
 
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
