@@ -253,18 +253,30 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   const int64_t dst = ((tt * it.tks + ks) * 64 + lane) * 8;
   const int64_t b = 32 * tt + (lane & 31);
   const int64_t p0 = 16 * ks + 8 * (lane >> 5);
+  // the eight rows' values: e64 rows are contiguous (two 32-byte loads); template rows
+  // are gathered through idx (read as two 16-byte loads), all loads issued first
+  double v[8];
+  if (from_e) {
+    if (b < it.B) {
+      const double4 *src = reinterpret_cast<const double4 *>(it.e64 + b * it.n_pad + p0);
+      const double4 u0 = src[0], u1 = src[1];
+      v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
+      v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = 0.0;
+    }
+  } else {
+    const int4 *ip = reinterpret_cast<const int4 *>(it.idx + p0);
+    const int4 i0 = ip[0], i1 = ip[1];
+    const int32_t pr[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+    const double *row = b < it.B ? template_row(it, b) : nullptr;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (row && pr[e] >= 0) ? row[pr[e]] : 0.0;
+  }
   uint16_t hi[8], lo[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    double v = 0.0;
-    if (from_e) {
-      if (b < it.B) v = it.e64[b * it.n_pad + p0 + e];
-    } else {
-      const int32_t p = it.idx[p0 + e];
-      if (b < it.B && p >= 0) v = template_row(it, b)[p];
-    }
-    split2(v, hi[e], lo[e]);
-  }
+  for (int e = 0; e < 8; ++e) split2(v[e], hi[e], lo[e]);
   uint4 vh, vl;
   vh.x = hi[0] | ((uint32_t)hi[1] << 16); vh.y = hi[2] | ((uint32_t)hi[3] << 16);
   vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
