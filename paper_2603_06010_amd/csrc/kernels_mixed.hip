@@ -209,14 +209,15 @@ __global__ void k_lambda(const double *__restrict__ acf, int64_t length, int64_t
 }
 
 // Pass twiddles of the in-LDS h-point DFT (h = 2^LH): for pass p >= 1 with sub-transform
-// length Ns and radix R, entry [q-1][k] = w_{Ns R}^{q k} (q = 1 .. R-1, k < Ns).
+// length Ns and radix R, entry [k][q-1] = w_{Ns R}^{q k} (k < Ns, q = 1 .. R-1), so that
+// the R - 1 twiddles of one sub-transform are contiguous.
 __global__ void k_pass_twiddles(int LH, double *__restrict__ ptw) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= rl_tw_size(LH)) return;
   int p = 1;
   while (p + 1 < rl_npass(LH) && i >= rl_off(LH, p + 1)) ++p;
   const int ns = 1 << rl_lns(LH, p), r = 1 << rl_L(LH, p);
-  const int u = i - rl_off(LH, p), q = u / ns + 1, k = u % ns;
+  const int u = i - rl_off(LH, p), q = u % (r - 1) + 1, k = u / (r - 1);
   const int len = ns * r, e = (q * k) % len;
   double sn, cs;
   sincospi(2.0 * (double)e / (double)len, &sn, &cs);
@@ -229,11 +230,13 @@ hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *t
   const unsigned g = (unsigned)((m + 255) / 256);
   hipLaunchKernelGGL(k_twiddles, dim3(g), dim3(256), 0, s, m, tw);
   if (lam) hipLaunchKernelGGL(k_lambda, dim3(g), dim3(256), 0, s, acf, length, m, tw, lam);
-  if (ptw && m >= 16 && m <= RL_MAX_M) {
+  if (ptw && m >= 16 && m <= RL_MAX_M_SPLIT) {
     int lm = 0;
     while (((int64_t)1 << lm) < m) ++lm;
-    const int n = rl_tw_size(lm - 2);
-    if (n > 0) hipLaunchKernelGGL(k_pass_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, lm - 2, ptw);
+    // the m/4-point DFT, or its two halves beyond the LDS array
+    const int lh = m <= RL_MAX_M ? lm - 2 : lm - 3;
+    const int n = rl_tw_size(lh);
+    if (n > 0) hipLaunchKernelGGL(k_pass_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, lh, ptw);
   }
   return hipGetLastError();
 }
@@ -1043,10 +1046,10 @@ __device__ void refine_segment(const RefItem &it, const SegDev &sd, int64_t ba, 
 }
 
 // Work entry: (item, template a, template b or -1, 0).  Persistent grid; each workgroup
-// owns m complex doubles of scratch.
-// LMAX bounds log2 m of the segments the instantiation handles: register DFTs of up to
-// 16 points for LMAX = 16 (m <= 65536), 32 points for LMAX = 18; the host picks the
-// smallest instantiation that covers every segment of the launch.
+// owns m complex doubles of scratch.  Used for launches with a circulant longer than the
+// in-LDS refinement takes (m > 65536).
+// LMAX bounds log2 m of the segments the instantiation handles (register DFTs of up to
+// 2^(LMAX/2 - 4) points).
 template <int LMAX>
 __global__ __launch_bounds__(RF_THREADS) void k_refine(const RefItem *__restrict__ items,
                                                        const int4 *__restrict__ work,
@@ -1102,12 +1105,8 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const RefItem *__restrict
 hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work, double *scratch,
                          int64_t scratch_per_wg, int32_t n_wg, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  if (scratch_per_wg / 2 <= ((int64_t)1 << 16))
-    hipLaunchKernelGGL(k_refine<16>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
-                       n_work, (double2 *)scratch, scratch_per_wg / 2);
-  else
-    hipLaunchKernelGGL(k_refine<18>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
-                       n_work, (double2 *)scratch, scratch_per_wg / 2);
+  hipLaunchKernelGGL(k_refine<18>, dim3((unsigned)n_wg), dim3(RF_THREADS), 0, s, items, work,
+                     n_work, (double2 *)scratch, scratch_per_wg / 2);
   return hipGetLastError();
 }
 
@@ -1203,9 +1202,10 @@ __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ 
       }
       if constexpr (LNS > 0) {
         // a few twiddles at a time, so they do not all hold registers at once
+        const double2 *tk = ptw + OFF + k * (R - 1);
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          a[g][q] = cmul(a[g][q], ptw[OFF + (q - 1) * NS + k]);
+          a[g][q] = cmul(a[g][q], tk[q - 1]);
           if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -1247,6 +1247,40 @@ __device__ __forceinline__ void rl_fft(double2 *X, const double2 *ptw) {
 struct RlAcc {
   double hy, ydh, yc, bad;
 };
+
+// Pointwise stage of the circulant (even-frequency) part for the pair (k, h - k) of the
+// packed h-point spectrum: vk = Z_k, vr = Z_{h-k}, la = lambda_{2k}, lb = lambda_{2h-2k},
+// cc = w_m^{2k}.  The spectra of the even- and odd-indexed samples are
+// E = (vk + conj vr)/2 and O = -i (vk - conj vr)/2; gk, gr are the conjugated inputs of the
+// inverse DFT at k and h - k (for k = 0 or h/2 the pair is one index and gr is unused).
+__device__ __forceinline__ void rl_even_pair(double2 vk, double2 vr, double la, double lb,
+                                             double2 cc, double2 &gk, double2 &gr) {
+  const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+  const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+  const double2 cO = cmul(cc, O);
+  const double2 yk = scal(la, cadd(E, cO));
+  const double2 yr = scal(lb, conj2(csub(E, cO)));
+  const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
+  gk = conj2(cadd(ep, mul_i(cmul(conj2(cc), op))));
+  gr = conj2(cadd(conj2(ep), mul_i(cmul(cc, conj2(op)))));
+}
+
+// Pointwise stage of the skew-circulant (odd-frequency) part for the pair (k, h - 1 - k):
+// vk = Z_k, vr = Z_{h-1-k}, la = lambda_{2k+1}, lb = lambda_{2k+2h+1}, dd = w_m^{2k+1},
+// cc = w_m^{2k}, om = w_m; gk, gr as for the even part.
+__device__ __forceinline__ void rl_odd_pair(double2 vk, double2 vr, double la, double lb,
+                                            double2 dd, double2 cc, double2 om, double2 &gk,
+                                            double2 &gr) {
+  const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
+  const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
+  const double2 dB = cmul(dd, B);
+  const double2 yk = scal(la, cadd(A, dB));   // X_{2k+1}
+  const double2 ykh = scal(lb, csub(A, dB));  // X_{2k+2h+1}
+  const double2 P = cadd(yk, ykh);
+  const double2 Q = cmul(conj2(cc), csub(yk, ykh));
+  gk = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
+  gr = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+}
 
 // Element-wise phases: a thread handles positions p = t + RL_THREADS i (samples 2p and
 // 2p + 1) or frequency pairs k = t + RL_THREADS i.  Every global access of a chunk of
@@ -1339,16 +1373,10 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
       const int k = t + RL_THREADS * (i0 + c);
       if (!(i0 + c < NKE && k <= h / 2)) continue;
       const int kr = (h - k) & (h - 1);
-      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-      // spectra of the even- and odd-indexed samples: E = (vk + conj vr)/2, O = -i (vk - conj vr)/2
-      const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-      const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-      const double2 cO = cmul(cc[c], O);
-      const double2 yk = scal(la[c], cadd(E, cO));
-      const double2 yr = scal(lb[c], conj2(csub(E, cO)));
-      const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
-      X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(cc[c]), op))));
-      if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(cc[c], conj2(op)))));
+      double2 gk, gr;
+      rl_even_pair(X[lpad(k)], X[lpad(kr)], la[c], lb[c], cc[c], gk, gr);
+      X[lpad(k)] = gk;
+      if (k != 0 && k != h / 2) X[lpad(kr)] = gr;
     }
   }
   __syncthreads();
@@ -1413,16 +1441,10 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
       const int k = t + RL_THREADS * (i0 + c);
       if (!(i0 + c < NKO && k < h / 2)) continue;
       const int kr = h - 1 - k;
-      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-      const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-      const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-      const double2 dB = cmul(dd[c], B);
-      const double2 yk = scal(la[c], cadd(A, dB));   // X_{2k+1}
-      const double2 ykh = scal(lb[c], csub(A, dB));  // X_{2k+2h+1}
-      const double2 P = cadd(yk, ykh);
-      const double2 Q = cmul(conj2(cc[c]), csub(yk, ykh));
-      X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
-      X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+      double2 gk, gr;
+      rl_odd_pair(X[lpad(k)], X[lpad(kr)], la[c], lb[c], dd[c], cc[c], om, gk, gr);
+      X[lpad(k)] = gk;
+      X[lpad(kr)] = gr;
     }
   }
   __syncthreads();
@@ -1468,6 +1490,212 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   __syncthreads();
 }
 
+// Segments whose packed h-point DFTs (h = 2 hh, hh = 2^(LH-1) the largest in-LDS length)
+// exceed the LDS array.  Each h-point forward DFT is two hh-point DFTs, of the even- and
+// odd-indexed packed samples (Z_k = E_k + w_h^k O_k, Z_{k+hh} = E_k - w_h^k O_k); E waits
+// in registers while O is transformed in LDS.  The pointwise stage works on quadruples of
+// frequencies {k, k2, k + hh, k2 + hh}, k < hh/2, closed under both its pairing and the
+// split (k2 = hh - k for the even part, hh - 1 - k for the odd part), and returns the two
+// halves of the next DFT's input (decimation in frequency): A_k = G_k + G_{k+hh}, whose
+// hh-point DFT gives outputs 2n, and B_k = (G_k - G_{k+hh}) w_h^k, outputs 2n + 1.  A is
+// written over O in LDS and B waits in the registers E held.  Output 2n + s carries the
+// samples 4n + 2s and 4n + 2s + 1, so a thread owns the same samples in every phase.
+template <int LH>
+__device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &sd, int64_t b,
+                                              double2 *X, RlAcc &acc) {
+  constexpr int LHH = LH - 1;
+  constexpr int h = 1 << LH, hh = 1 << LHH;
+  static_assert(hh >= 2 * RL_THREADS && hh % (2 * RL_THREADS) == 0, "whole quadruples per thread");
+  constexpr int NI = hh / RL_THREADS;      // position iterations per half
+  constexpr int NQ = hh / 2 / RL_THREADS;  // quadruples per thread
+  static_assert(NI % RL_CH == 0, "whole chunks");
+  // the thread index is re-read (opaquely) at each phase, so that per-position addresses
+  // and masks are recomputed there instead of being held in registers across phases
+  int t = opaque_tid();
+  const float *__restrict__ y = it.y0 + b * it.n_pad;
+  const double *__restrict__ hrow = template_row(it, b) + sd.offset;
+  const double *__restrict__ ydp = it.yd_pos + sd.offset;
+  const int32_t *__restrict__ p2r = it.pos2row + sd.offset;
+  double *__restrict__ e = it.e64 + b * it.n_pad;
+  const double2 *__restrict__ tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
+  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;  // passes of the hh-point DFT
+  const double *__restrict__ lam = sd.lam;
+  const int len = (int)sd.length;
+  const bool dense = sd.nkeep == sd.length;
+  const int32_t row0 = (int32_t)sd.row0;
+  const double inv_m = 1.0 / (double)(4 * h);
+  auto wm = [&](int r) {  // w_m^r, 0 <= r < m
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  auto row_of = [&](int jj) -> int32_t {
+    if (jj >= len) return -1;
+    return dense ? row0 + jj : p2r[jj];
+  };
+  auto finite_or_flag = [&](float v) -> double {
+    if (!isfinite(v)) {
+      acc.bad = 1.0;
+      return 0.0;
+    }
+    return (double)v;
+  };
+  // rows and y0 values of the samples 4n + 2s, 4n + 2s + 1, n = t + RL_THREADS (i0 + c)
+  auto load_x = [&](int i0, int s, int32_t (&rr)[RL_CH][2], float (&xv)[RL_CH][2]) {
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c) {
+      const int n = t + RL_THREADS * (i0 + c);
+      rr[c][0] = row_of(4 * n + 2 * s);
+      rr[c][1] = row_of(4 * n + 2 * s + 1);
+    }
+#pragma unroll
+    for (int c = 0; c < RL_CH; ++c)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) xv[c][u] = rr[c][u] >= 0 ? y[rr[c][u]] : 0.f;
+  };
+  // X[n] = packed samples of half s (times w_m^{4n + 2s} for the skew-circulant part)
+  auto stage_half = [&](int s, bool skew) {
+    t = opaque_tid();
+    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+      int32_t rr[RL_CH][2];
+      float xv[RL_CH][2];
+      load_x(i0, s, rr, xv);
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int n = t + RL_THREADS * (i0 + c);
+        const double2 z = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
+        X[lpad(n)] = skew ? cmul(z, wm(4 * n + 2 * s)) : z;
+      }
+    }
+    __syncthreads();
+  };
+
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
+
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    const bool odd = part == 1;
+    // quadruple i of this thread: k = t + RL_THREADS i and its partner k2; the even part's
+    // k = hh/2 (its own partner) goes to thread 0 as an extra quadruple
+    auto k_of = [&](int i) { return i < NQ ? t + RL_THREADS * i : hh / 2; };
+    auto k2_of = [&](int k) { return odd ? hh - 1 - k : (hh - k) & (hh - 1); };
+    const bool extra = !odd && t == 0;
+    double2 ra[NQ + 1], rb[NQ + 1];  // E_k, E_k2, then B_k, B_k2
+    stage_half(0, odd);
+    rl_fft<LHH>(X, ptw);
+    t = opaque_tid();
+#pragma unroll
+    for (int i = 0; i <= NQ; ++i) {
+      if (i == NQ && !extra) continue;
+      const int k = k_of(i);
+      ra[i] = X[lpad(k)];
+      rb[i] = X[lpad(k2_of(k))];
+    }
+    __syncthreads();
+    stage_half(1, odd);
+    rl_fft<LHH>(X, ptw);
+    t = opaque_tid();
+#pragma unroll
+    for (int i = 0; i <= NQ; ++i) {
+      if (i == NQ && !extra) continue;
+      const int k = k_of(i), k2 = k2_of(k);
+      const double2 wk = wm(4 * k), wk2 = wm(4 * k2);  // w_h^k, w_h^k2
+      const double2 ok = cmul(wk, X[lpad(k)]), ok2 = cmul(wk2, X[lpad(k2)]);
+      const double2 zk = cadd(ra[i], ok), zkh = csub(ra[i], ok);     // Z_k, Z_{k+hh}
+      const double2 zk2 = cadd(rb[i], ok2), zk2h = csub(rb[i], ok2); // Z_k2, Z_{k2+hh}
+      double2 gk, gkh, gk2 = zk2, gk2h = zk2h, unused;
+      if (!odd) {
+        if (k == 0) {  // self-paired 0 and hh
+          rl_even_pair(zk, zk, lam[0], lam[2 * h], wm(0), gk, unused);
+          rl_even_pair(zkh, zkh, lam[h], lam[h], wm(h), gkh, unused);
+        } else {
+          // pairs (k, h - k = k2 + hh) and (k2, h - k2 = k + hh)
+          rl_even_pair(zk, zk2h, lam[2 * k], lam[2 * h - 2 * k], wm(2 * k), gk, gk2h);
+          rl_even_pair(zk2, zkh, lam[2 * k2], lam[2 * h - 2 * k2], wm(2 * k2), gk2, gkh);
+        }
+      } else {
+        // pairs (k, h - 1 - k = k2 + hh) and (k2, h - 1 - k2 = k + hh)
+        const double2 om = wm(1);
+        rl_odd_pair(zk, zk2h, lam[2 * k + 1], lam[2 * k + 2 * h + 1], wm(2 * k + 1), wm(2 * k),
+                    om, gk, gk2h);
+        rl_odd_pair(zk2, zkh, lam[2 * k2 + 1], lam[2 * k2 + 2 * h + 1], wm(2 * k2 + 1),
+                    wm(2 * k2), om, gk2, gkh);
+      }
+      X[lpad(k)] = cadd(gk, gkh);
+      ra[i] = cmul(csub(gk, gkh), wk);
+      if (k2 != k) {
+        X[lpad(k2)] = cadd(gk2, gk2h);
+        rb[i] = cmul(csub(gk2, gk2h), wk2);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      t = opaque_tid();
+      if (s == 1) {
+#pragma unroll
+        for (int i = 0; i <= NQ; ++i) {
+          if (i == NQ && !extra) continue;
+          const int k = k_of(i), k2 = k2_of(k);
+          X[lpad(k)] = ra[i];
+          if (k2 != k) X[lpad(k2)] = rb[i];
+        }
+        __syncthreads();
+      }
+      rl_fft<LHH>(X, ptw);
+      t = opaque_tid();
+      // output p = 2n + s: conj(X[n]) = t_{2p} + i t_{2p+1} (odd part: conj(w_m^{2p} X[n]))
+      for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+        int32_t rr[RL_CH][2];
+        float xv[RL_CH][2];
+        if (!odd) {
+#pragma unroll
+          for (int c = 0; c < RL_CH; ++c) {
+            const int n = t + RL_THREADS * (i0 + c);
+            rr[c][0] = row_of(4 * n + 2 * s);
+            rr[c][1] = row_of(4 * n + 2 * s + 1);
+          }
+#pragma unroll
+          for (int c = 0; c < RL_CH; ++c) {
+            const double2 v = X[lpad(t + RL_THREADS * (i0 + c))];
+            if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
+            if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
+          }
+          continue;
+        }
+        double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
+        load_x(i0, s, rr, xv);
+#pragma unroll
+        for (int c = 0; c < RL_CH; ++c) {
+          const int n = t + RL_THREADS * (i0 + c);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int jj = 4 * n + 2 * s + u;
+            ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
+            hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
+            yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < RL_CH; ++c) {
+          const int n = t + RL_THREADS * (i0 + c);
+          const double2 gz = conj2(cmul(wm(4 * n + 2 * s), X[lpad(n)]));
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (rr[c][u] < 0) continue;
+            const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
+            const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
+            e[rr[c][u]] = hv[c][u] - cz;
+            acc.hy += hv[c][u] * xd;
+            acc.ydh += hv[c][u] * yv[c][u];
+            acc.yc += xd * cz;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
 __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__restrict__ items,
                                                            const int2 *__restrict__ work,
@@ -1488,6 +1716,7 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
         TDA_RL(2) TDA_RL(3) TDA_RL(4) TDA_RL(5) TDA_RL(6) TDA_RL(7) TDA_RL(8) TDA_RL(9)
         TDA_RL(10) TDA_RL(11) TDA_RL(12) TDA_RL(13)
 #undef TDA_RL
+        case RL_LHMAX + 1: rl_segment_split<RL_LHMAX + 1>(it, sd, b, X, acc); break;
         default: acc.bad = 1.0;
       }
     }

@@ -128,13 +128,15 @@ struct SegDev {
 // h = 2^LH: ceil(LH / 4) passes of near-equal radix, larger radices first.
 constexpr int RL_LHMAX = 13;
 constexpr int64_t RL_MAX_M = (int64_t)4 << RL_LHMAX;
+// Twice that length still refines in LDS, with each m/4-point DFT split into two halves.
+constexpr int64_t RL_MAX_M_SPLIT = 2 * RL_MAX_M;
 __host__ __device__ constexpr int rl_npass(int LH) { return LH <= 4 ? 1 : (LH + 3) / 4; }
 __host__ __device__ constexpr int rl_L(int LH, int p) {
   return LH / rl_npass(LH) + (p < LH % rl_npass(LH) ? 1 : 0);
 }
 // log2 of the sub-transform length entering pass p
 __host__ __device__ constexpr int rl_lns(int LH, int p) { return p == 0 ? 0 : rl_lns(LH, p - 1) + rl_L(LH, p - 1); }
-// offset of pass p's twiddles w_{Ns R}^{q k} (q = 1 .. R-1, k < Ns, stored [q-1][k])
+// offset of pass p's twiddles w_{Ns R}^{q k} (k < Ns, q = 1 .. R-1, stored [k][q-1])
 __host__ __device__ constexpr int rl_off(int LH, int p) {
   return p <= 1 ? 0 : rl_off(LH, p - 1) + (((1 << rl_L(LH, p - 1)) - 1) << rl_lns(LH, p - 1));
 }
@@ -285,7 +287,7 @@ hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double
 hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
                      int64_t scratch_stride, int32_t n_wg, hipStream_t s);
 
-// In-LDS refinement for launches whose segments all have m <= RL_MAX_M; work entries
+// In-LDS refinement for launches whose segments all have m <= RL_MAX_M_SPLIT; work entries
 // (item, template).
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
                              hipStream_t s);

@@ -65,6 +65,64 @@ def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
     h.close()
 
 
+def _ar1_white_closed(X, keep, s, phi):
+    """Whitened rows of X under AR(1) restricted to the retained indices `keep` (a Markov
+    chain: one innovation per retained sample, over the gap since the previous), and the
+    log-determinant of the restricted covariance."""
+    acf0 = s * s / (1 - phi * phi)
+    g = np.diff(keep)
+    v = np.concatenate([[acf0], s * s * (1 - phi ** (2 * g)) / (1 - phi * phi)])
+    Xk = X[:, keep]
+    w = np.empty_like(Xk)
+    w[:, 0] = Xk[:, 0]
+    w[:, 1:] = Xk[:, 1:] - phi ** g * Xk[:, :-1]
+    return w / np.sqrt(v), np.log(v).sum()
+
+
+# Segments beyond the in-LDS DFT length (m = 4 x 8192): m = 65536 refines in LDS with each
+# DFT split in halves (lengths 16385 .. 32768, dense rows and rows with excluded samples),
+# longer ones in the global-scratch path (m = 131072).
+@pytest.mark.parametrize("N,n_gaps,B", [(16385, 1, 40), (20000, 0, 64), (32768, 3, 96),
+                                        (40000, 2, 48)])
+def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B):
+    from gpu_util import to_dev
+    from test_oracle_pins import ar1_acf, gapped_ar1_closed
+    import torch
+    print(f"case N={N} gaps={n_gaps} B={B}", flush=True)
+    s, phi = 0.8, 0.97
+    acf = ar1_acf(N, s, phi)
+    gaps = synth.draw_gaps(np.random.default_rng(N), N, n_gaps)
+    mask = synth.gap_mask_from(N, gaps)
+    rng = np.random.default_rng(N + 1)
+    d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
+    keep = np.flatnonzero(mask == 0)
+    wr, ld = _ar1_white_closed(d[None] - H, keep, s, phi)
+    want = -0.5 * (wr * wr).sum(1) - 0.5 * ld - 0.5 * len(keep) * np.log(2 * np.pi)
+    w5, ld5 = gapped_ar1_closed(d - H[5], keep, s, phi)  # the loop form, on one row
+    np.testing.assert_allclose(wr[5], w5, rtol=1e-12, atol=1e-12)
+    assert abs(ld - ld5) <= 1e-9 * abs(ld)
+    h = tda.Handle(acf, N, mask, precision="mixed").factor()
+    dd, Hd = to_dev(d), to_dev(H)
+    got = h.loglik(dd, Hd).cpu().numpy()
+    f64 = h.loglik(dd, Hd, precision="fp64").cpu().numpy()
+    tolf = 1e-6 * np.maximum(1.0, np.abs(want) / 1e4)
+    assert np.all(np.abs(f64 - want) <= tolf), np.max(np.abs(f64 - want))
+    err = got - want
+    assert np.max(np.abs(err)) <= TOL_MIXED, np.max(np.abs(err))
+    assert np.all(err >= -tolf), np.min(err)
+    # the inner products from the same refinement: <d,h> and the refined <h,h> (<= exact)
+    _, dh, hh = h.loglik_terms(dd, Hd)
+    wd, _ = _ar1_white_closed(d[None], keep, s, phi)
+    wh, _ = _ar1_white_closed(H, keep, s, phi)
+    dh_want, hh_want = wh @ wd[0], (wh * wh).sum(1)
+    dh, hh = dh.cpu().numpy(), hh.cpu().numpy()
+    assert np.max(np.abs(dh - dh_want)) <= TOL_MIXED, np.max(np.abs(dh - dh_want))
+    assert np.max(np.abs(hh - hh_want)) <= TOL_MIXED, np.max(np.abs(hh - hh_want))
+    assert np.all(hh <= hh_want + 1e-6 * np.maximum(1.0, hh_want / 1e4))
+    torch.cuda.synchronize()
+    h.close()
+
+
 @pytest.mark.parametrize("N,n_gaps,B,segments", [
     (3000, 2, 300, None),
     (2600, 1, 130, [(0, 1000), (1200, 1300), (2550, 50)]),
