@@ -217,6 +217,28 @@ tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int6
                             int32_t precision, void *hip_stream);
 
 /*
+ * tda_whitened_residual -- the whitened residual of every template, the vector
+ * whose squared norm is the quadratic form of logL (eq:td_like_whitened):
+ *   wres[b * ldw + j] = (L^-1 (d - h_b))_j,  j < n_eff,
+ * over the retained samples, segments concatenated in order and each in sample
+ * order (L the FP64 Cholesky factor of the segment's block of C[mask,mask]);
+ * residual diagnostics of the fit (Sec. II.B item 7) read them.  out[b] is logL
+ * exactly as tda_loglik_ex with TDA_PREC_FP64 computes it, from the same solve.
+ *   d, H, ldh, out  as tda_loglik (d is read directly, not from a cache).
+ *   wres  device float64, caller-owned, at least (B - 1) ldw + n_eff elements;
+ *         ldw >= n_eff (tda_info's n_eff).  Entries beyond n_eff are untouched.
+ * Runs the FP64 triangular solve, then copies its solution rows out (N_eff B
+ * doubles written).  B = 0 is a no-op.  NaN/Inf in a template stays in its row.
+ * Errors: ESTATE (not factored; handles without the FP64 factor: Gohberg-Semencul
+ * and compact mixed handles), EINVAL (B < 0, ldh < N, ldw < n_eff, NULL
+ * pointers), EHIP (more than 2^31 - 1 blocks of 32 templates x 64 rows).
+ * Asynchronous on hip_stream (NULL = default stream); not capturable in a graph.
+ */
+tda_status tda_whitened_residual(tda_handle h, const double *d, const double *H, int64_t B,
+                                 int64_t ldh, double *out, double *wres, int64_t ldw,
+                                 void *hip_stream);
+
+/*
  * tda_acf_estimate -- autocovariance of a stretch of strain, for building the
  * covariance (Sec. II.B item 6: correlate the data directly, or take a Welch
  * PSD and its inverse Fourier transform, then truncate to the lags needed).

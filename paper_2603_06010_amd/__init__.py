@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
 PREC_FP64, PREC_MIXED, PREC_GS, PREC_CDO = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-    "tda_loglik_terms", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_terms", "tda_whitened_residual", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_loglik.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
     L.tda_loglik_terms.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, i32, vp]
+    L.tda_whitened_residual.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
     L.tda_acf_estimate.argtypes = [vp, i64, i64, i32, i64, vp, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
     L.tda_info.argtypes = [vp, ctypes.POINTER(_Info)]
@@ -97,7 +98,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_timing_enable.argtypes = [i32]
     L.tda_timing_read.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-              "tda_loglik_terms", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
+              "tda_loglik_terms", "tda_whitened_residual", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
               "tda_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -215,6 +216,24 @@ class Handle:
                                      _ptr(dh) if dh is not None else None,
                                      _ptr(hh) if hh is not None else None, p, _stream(stream)))
         return out, dh, hh
+
+    def whitened_residual(self, d, H, stream=None):
+        """(logL, W): W[b] = L^-1 (d - h_b) over the retained samples (segments
+        concatenated), from the FP64 solve, through tda_whitened_residual."""
+        import torch
+        if H.dim() != 2:
+            raise ValueError("H must be 2-D")
+        if H.stride(1) != 1:
+            raise ValueError("H rows must be contiguous")
+        B = H.shape[0]
+        n_eff = self.info()["n_eff"]
+        out = torch.empty(B, dtype=torch.float64, device=H.device)
+        W = torch.empty((B, n_eff), dtype=torch.float64, device=H.device)
+        if B == 0:
+            return out, W
+        _check(_lib.tda_whitened_residual(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
+                                          _ptr(W), W.stride(0), _stream(stream)))
+        return out, W
 
     def snr(self, d, H, precision=None, stream=None):
         """Time-domain SNRs per template (Sec. II.B item 7): rho_mf = <d,h>/sqrt(<h,h>),

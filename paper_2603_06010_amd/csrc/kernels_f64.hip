@@ -439,6 +439,39 @@ hipError_t launch_trsm_f64(const TrsmItem *items, const TrsmTile *tiles, int64_t
   return hipGetLastError();
 }
 
+// One workgroup per (column tile, 64-row chunk), chunks fastest; 256 threads: 64 rows x
+// 4 column groups, 8 columns each.  Writes run along the rows of one template
+// (coalesced); the reads of a row's 32 templates share cache lines across the groups.
+__global__ __launch_bounds__(256) void k_whiten_export(const double *__restrict__ scratch,
+                                                       const int32_t *__restrict__ retpos,
+                                                       int64_t n_pad, int64_t n_chunks,
+                                                       int64_t B, double *__restrict__ wres,
+                                                       int64_t ldw) {
+  const int64_t t = blockIdx.x / n_chunks;
+  const int64_t r = (blockIdx.x % n_chunks) * 64 + (threadIdx.x & 63);
+  const int cg = threadIdx.x >> 6;
+  if (r >= n_pad) return;
+  const int32_t pos = retpos[r];
+  if (pos < 0) return;
+  const double *src = scratch + (t * n_pad + r) * BC;
+#pragma unroll
+  for (int i = 0; i < BC / 4; ++i) {
+    const int c = cg + 4 * i;
+    const int64_t b = t * BC + c;
+    if (b < B) wres[b * ldw + pos] = src[c];
+  }
+}
+
+hipError_t launch_whiten_export(const double *scratch, const int32_t *retpos, int64_t n_pad,
+                                int64_t B, double *wres, int64_t ldw, hipStream_t s) {
+  const int64_t nt = (B + BC - 1) / BC, nc = (n_pad + 63) / 64;
+  if (nt <= 0 || nc <= 0) return hipSuccess;
+  if (nt * nc > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_whiten_export, dim3((unsigned)(nt * nc)), dim3(256), 0, s, scratch, retpos,
+                     n_pad, nc, B, wres, ldw);
+  return hipGetLastError();
+}
+
 // One item passed by value; tile t covers columns [32t, 32t+32) over all block rows.
 __global__ __launch_bounds__(256, 1) void k_trsm_f64_single(const TrsmItem it, int32_t nblk) {
   const TrsmTile tl{0, (int32_t)(blockIdx.x * BC), 0, nblk,

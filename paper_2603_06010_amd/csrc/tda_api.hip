@@ -199,6 +199,7 @@ struct tda_ctx {
 
   // device state
   DevBuf acf_d, idx_d, pos2row_d, blk_first_d, blk_last_d;
+  DevBuf retpos_d;     // [n_pad] position of each padded row among the retained samples, -1 = padding
   DevBuf A_d;          // dense per-segment blocks (until factored)
   DevBuf dinv128_d, dinv256_d, logdiag_d, logdet_d, fail_d;
   DevBuf panels_d, panel_off_d;
@@ -273,7 +274,7 @@ struct tda_ctx {
                      &segdev_d, &dbar_d,  &yd_d,       &ydpos_d,     &qdd_d,      &ws_scratch,
                      &ws_tiles, &ws_items, &ws_hs_hi,  &ws_hs_lo,    &ws_w0_hi,   &ws_w0_lo,
                      &ws_y0,   &ws_fft,   &ws_work,    &ws_mix,      &ws_ref,     &gs_tab_d,
-                     &gs_seg_d, &gs_lev_d};
+                     &gs_seg_d, &gs_lev_d, &ws_zero,  &ws_terms,   &ws_cdo,      &retpos_d};
     for (DevBuf *b : all) release(*b);
   }
   double cterm() const { return -0.5 * logdet - 0.5 * (double)n_eff * kLog2Pi; }
@@ -375,7 +376,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   h->N = N;
   h->acf.assign(acf, acf + longest);
 
-  std::vector<int32_t> idx, pos2row((size_t)N, -1);
+  std::vector<int32_t> idx, pos2row((size_t)N, -1), retpos;
   int64_t row = 0;
   int32_t blk = 0;
   for (const tda_segment &s : segs) {
@@ -389,12 +390,16 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
       if (gap_mask && gap_mask[j]) continue;
       pos2row[j] = (int32_t)(row + keep);
       idx.push_back((int32_t)j);
+      retpos.push_back((int32_t)(h->n_eff + keep));
       ++keep;
     }
     if (keep == 0) continue;  // a fully excluded segment contributes nothing
     g.n_keep = keep;
     g.n_pad = (keep + TB - 1) / TB * TB;
-    for (int64_t j = keep; j < g.n_pad; ++j) idx.push_back(-1);
+    for (int64_t j = keep; j < g.n_pad; ++j) {
+      idx.push_back(-1);
+      retpos.push_back(-1);
+    }
     g.nblk = (int32_t)(g.n_pad / TB);
     int32_t l2 = 4;  // m >= 16: the in-LDS refinement needs m/4 >= 4
     while (((int64_t)1 << l2) < 2 * g.length) ++l2;
@@ -438,6 +443,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   if ((st = upload(h, h->acf_d, h->acf.data(), h->acf.size() * sizeof(double))) != TDA_OK ||
       (st = upload(h, h->idx_d, idx.data(), idx.size() * sizeof(int32_t))) != TDA_OK ||
       (st = upload(h, h->pos2row_d, pos2row.data(), pos2row.size() * sizeof(int32_t))) != TDA_OK ||
+      (st = upload(h, h->retpos_d, retpos.data(), retpos.size() * sizeof(int32_t))) != TDA_OK ||
       (st = upload(h, h->blk_first_d, h->blk_first_h.data(), h->nblk * sizeof(int32_t))) != TDA_OK ||
       (st = upload(h, h->blk_last_d, h->blk_last_h.data(), h->nblk * sizeof(int32_t))) != TDA_OK ||
       (st = upload(h, h->panel_off_d, h->panel_off_h.data(), h->nblk * sizeof(int64_t))) != TDA_OK)
@@ -757,6 +763,28 @@ extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const doub
     TDA_TRY(eval(zero, H, B, ldh, hh));
     if (out_dh) TDA_TRY(eval(d, zero, 1, h->N, dd));
     HIP_TRY(launch_terms_combine(out, hh, dd, h->cterm(), B, out_dh, s));
+  }
+  return mark_done(h, s);
+}
+
+extern "C" tda_status tda_whitened_residual(tda_handle h, const double *d, const double *H,
+                                            int64_t B, int64_t ldh, double *out, double *wres,
+                                            int64_t ldw, void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, TDA_PREC_FP64));
+  if (B == 0) return TDA_OK;
+  if (!wres) return fail_with(TDA_EINVAL, "NULL device pointer");
+  if (ldw < h->n_eff) return fail_with(TDA_EINVAL, "ldw < n_eff");
+  if (!h->panels_d.p) return fail_with(TDA_ESTATE, "whitened residuals need the FP64 factor");
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(refuse_capture(s));
+  TDA_TRY(order_after_previous(h, s));
+  // the triangular solve leaves every template's w = L^-1 (d - h) in its scratch rows
+  TDA_TRY(loglik_f64(h, d, H, B, ldh, out, s));
+  {
+    TimedScope ts("whiten_export", s);
+    HIP_TRY(launch_whiten_export((const double *)h->ws_scratch.p, (const int32_t *)h->retpos_d.p,
+                                 h->n_pad, B, wres, ldw, s));
   }
   return mark_done(h, s);
 }

@@ -202,6 +202,11 @@ hipError_t launch_combine(const double *parts, const int64_t *part_off, const in
 void register_kernel_attributes();
 hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hipStream_t s);
 // <h,h> = -2 (hh - cterm) in place and, if dh != NULL, <d,h> = out - dd[0] + <h,h>/2
+// Whitened residuals out of the single-item FP64 solve's scratch (column tile t holds
+// row r of its 32 templates at scratch[(t n_pad + r) 32 + c]): wres[b][retpos[r]] for the
+// retained rows (retpos >= 0), row stride ldw.
+hipError_t launch_whiten_export(const double *scratch, const int32_t *retpos, int64_t n_pad,
+                                int64_t B, double *wres, int64_t ldw, hipStream_t s);
 hipError_t launch_terms_combine(const double *out, double *hh, const double *dd, double cterm,
                                 int64_t B, double *dh, hipStream_t s);
 

@@ -135,6 +135,52 @@ def test_f64_invariants(tda):
     np.testing.assert_array_equal(h.loglik(d, Hp[:, :inst.N]).cpu().numpy(), base)
 
 
+@pytest.mark.parametrize("N,n_gaps,B,segments,precision", [
+    (3000, 2, 70, None, "fp64"),
+    (2600, 1, 40, [(0, 1000), (1200, 1300), (2550, 50)], "fp64"),
+    (1500, 1, 33, None, "mixed"),
+])
+def test_whitened_residual(tda, N, n_gaps, B, segments, precision):
+    """Exported L^-1 (d - h) against the oracle's whitening, element by element; logL from
+    the same solve equals the FP64 evaluation and -1/2 ||w||^2 + constant."""
+    from gpu_util import to_dev
+    import ctypes
+    import torch
+    print(f"case N={N} gaps={n_gaps} B={B} segments={segments} {precision}", flush=True)
+    inst = synth.random_rhs_case(300 + N, N, 1, n_gaps, B, segments=segments)
+    h = tda.Handle(inst.acf, N, inst.masks[0], segments, precision=precision).factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    out, W = h.whitened_residual(d, H)
+    f = oracle.factor(inst.acf, N, inst.masks[0], segments)
+    want = oracle.whiten(f, inst.d[0][None] - inst.H)
+    Wn = W.cpu().numpy()
+    assert Wn.shape == want.shape
+    # FP64 solve: error ~ n u cond(L) |w| with cond(L) ~ 1e3 at the test nugget
+    assert np.max(np.abs(Wn - want)) <= 1e-8 * np.max(np.abs(want)), np.max(np.abs(Wn - want))
+    np.testing.assert_array_equal(out.cpu().numpy(), h.loglik(d, H, precision="fp64").cpu().numpy())
+    info = h.info()
+    const = -0.5 * info["logdet"] - 0.5 * info["n_eff"] * np.log(2 * np.pi)
+    np.testing.assert_allclose(-0.5 * (Wn * Wn).sum(1) + const, out.cpu().numpy(), rtol=1e-12)
+    # row stride beyond n_eff: the extra entries stay untouched
+    n_eff = info["n_eff"]
+    W2 = torch.full((B, n_eff + 5), 7.0, dtype=torch.float64, device="cuda")
+    out2 = torch.empty(B, dtype=torch.float64, device="cuda")
+    lib = tda.load_library()
+    st = lib.tda_whitened_residual(h._h, d.data_ptr(), H.data_ptr(), B, H.stride(0),
+                                   out2.data_ptr(), W2.data_ptr(), n_eff + 5, None)
+    assert st == 0
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(W2[:, :n_eff].cpu().numpy(), Wn)
+    assert torch.all(W2[:, n_eff:] == 7.0)
+    # ldw < n_eff and a NULL output are rejected
+    assert lib.tda_whitened_residual(h._h, d.data_ptr(), H.data_ptr(), B, H.stride(0),
+                                     out2.data_ptr(), W2.data_ptr(), n_eff - 1, None) == 1
+    assert lib.tda_whitened_residual(h._h, d.data_ptr(), H.data_ptr(), B, H.stride(0),
+                                     out2.data_ptr(), None, n_eff, None) == 1
+    torch.cuda.synchronize()
+    h.close()
+
+
 def test_errors(tda):
     from gpu_util import to_dev
     # not positive definite: fail row reported
