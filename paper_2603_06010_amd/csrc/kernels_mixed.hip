@@ -1248,18 +1248,24 @@ struct RlAcc {
   double hy, ydh, yc, bad;
 };
 
+// Multiplier of the circulant product: real eigenvalues (the covariance) or complex
+// spectra (the Gohberg-Semencul correlations).
+__device__ __forceinline__ double2 mulm(double a, double2 v) { return scal(a, v); }
+__device__ __forceinline__ double2 mulm(double2 a, double2 v) { return cmul(a, v); }
+
 // Pointwise stage of the circulant (even-frequency) part for the pair (k, h - k) of the
 // packed h-point spectrum: vk = Z_k, vr = Z_{h-k}, la = lambda_{2k}, lb = lambda_{2h-2k},
 // cc = w_m^{2k}.  The spectra of the even- and odd-indexed samples are
 // E = (vk + conj vr)/2 and O = -i (vk - conj vr)/2; gk, gr are the conjugated inputs of the
 // inverse DFT at k and h - k (for k = 0 or h/2 the pair is one index and gr is unused).
-__device__ __forceinline__ void rl_even_pair(double2 vk, double2 vr, double la, double lb,
+template <class Mul>
+__device__ __forceinline__ void rl_even_pair(double2 vk, double2 vr, Mul la, Mul lb,
                                              double2 cc, double2 &gk, double2 &gr) {
   const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
   const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
   const double2 cO = cmul(cc, O);
-  const double2 yk = scal(la, cadd(E, cO));
-  const double2 yr = scal(lb, conj2(csub(E, cO)));
+  const double2 yk = mulm(la, cadd(E, cO));
+  const double2 yr = mulm(lb, conj2(csub(E, cO)));
   const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
   gk = conj2(cadd(ep, mul_i(cmul(conj2(cc), op))));
   gr = conj2(cadd(conj2(ep), mul_i(cmul(cc, conj2(op)))));
@@ -1268,14 +1274,14 @@ __device__ __forceinline__ void rl_even_pair(double2 vk, double2 vr, double la, 
 // Pointwise stage of the skew-circulant (odd-frequency) part for the pair (k, h - 1 - k):
 // vk = Z_k, vr = Z_{h-1-k}, la = lambda_{2k+1}, lb = lambda_{2k+2h+1}, dd = w_m^{2k+1},
 // cc = w_m^{2k}, om = w_m; gk, gr as for the even part.
-__device__ __forceinline__ void rl_odd_pair(double2 vk, double2 vr, double la, double lb,
-                                            double2 dd, double2 cc, double2 om, double2 &gk,
-                                            double2 &gr) {
+template <class Mul>
+__device__ __forceinline__ void rl_odd_pair(double2 vk, double2 vr, Mul la, Mul lb, double2 dd,
+                                            double2 cc, double2 om, double2 &gk, double2 &gr) {
   const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
   const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
   const double2 dB = cmul(dd, B);
-  const double2 yk = scal(la, cadd(A, dB));   // X_{2k+1}
-  const double2 ykh = scal(lb, csub(A, dB));  // X_{2k+2h+1}
+  const double2 yk = mulm(la, cadd(A, dB));   // X_{2k+1}
+  const double2 ykh = mulm(lb, csub(A, dB));  // X_{2k+2h+1}
   const double2 P = cadd(yk, ykh);
   const double2 Q = cmul(conj2(cc), csub(yk, ykh));
   gk = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
@@ -1500,17 +1506,113 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
 // hh-point DFT gives outputs 2n, and B_k = (G_k - G_{k+hh}) w_h^k, outputs 2n + 1.  A is
 // written over O in LDS and B waits in the registers E held.  Output 2n + s carries the
 // samples 4n + 2s and 4n + 2s + 1, so a thread owns the same samples in every phase.
-template <int LH>
-__device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &sd, int64_t b,
-                                              double2 *X, RlAcc &acc) {
+//
+// The caller supplies the data and takes the results:
+//   stage(s, odd)  writes X[n] = x_{4n+2s} + i x_{4n+2s+1} for n < hh (times w_m^{4n+2s}
+//                  in the odd part) and ends with a barrier;
+//   mult(r)        the multiplier of frequency r < m (real eigenvalue or complex spectrum);
+//   emit(s, odd)   reads X[n], n < hh, after the last DFT of half s: t_{2p} + i t_{2p+1} =
+//                  conj(X[n]) (even part) or conj(w_m^{2p} X[n]) (odd part), p = 2n + s,
+//                  with C x = (t_even + t_odd) / m.
+// The thread index is re-read (opaquely) at each phase, so that per-position addresses and
+// masks are recomputed there instead of being held in registers across phases.
+template <int LH, class Stage, class Mult, class Emit>
+__device__ __forceinline__ void rl_split_parts(double2 *X, const double2 *__restrict__ tw,
+                                               const double2 *__restrict__ ptw, Stage &&stage,
+                                               Mult &&mult, Emit &&emit) {
   constexpr int LHH = LH - 1;
   constexpr int h = 1 << LH, hh = 1 << LHH;
   static_assert(hh >= 2 * RL_THREADS && hh % (2 * RL_THREADS) == 0, "whole quadruples per thread");
-  constexpr int NI = hh / RL_THREADS;      // position iterations per half
   constexpr int NQ = hh / 2 / RL_THREADS;  // quadruples per thread
+  auto wm = [&](int r) {  // w_m^r, 0 <= r < m
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  int t = opaque_tid();
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    const bool odd = part == 1;
+    // quadruple i of this thread: k = t + RL_THREADS i and its partner k2; the even part's
+    // k = hh/2 (its own partner) goes to thread 0 as an extra quadruple
+    auto k_of = [&](int i) { return i < NQ ? t + RL_THREADS * i : hh / 2; };
+    auto k2_of = [&](int k) { return odd ? hh - 1 - k : (hh - k) & (hh - 1); };
+    const bool extra = !odd && t == 0;
+    double2 ra[NQ + 1], rb[NQ + 1];  // E_k, E_k2, then B_k, B_k2
+    stage(0, odd);
+    rl_fft<LHH>(X, ptw);
+    t = opaque_tid();
+#pragma unroll
+    for (int i = 0; i <= NQ; ++i) {
+      if (i == NQ && !extra) continue;
+      const int k = k_of(i);
+      ra[i] = X[lpad(k)];
+      rb[i] = X[lpad(k2_of(k))];
+    }
+    __syncthreads();
+    stage(1, odd);
+    rl_fft<LHH>(X, ptw);
+    t = opaque_tid();
+#pragma unroll
+    for (int i = 0; i <= NQ; ++i) {
+      if (i == NQ && !extra) continue;
+      const int k = k_of(i), k2 = k2_of(k);
+      const double2 wk = wm(4 * k), wk2 = wm(4 * k2);  // w_h^k, w_h^k2
+      const double2 ok = cmul(wk, X[lpad(k)]), ok2 = cmul(wk2, X[lpad(k2)]);
+      const double2 zk = cadd(ra[i], ok), zkh = csub(ra[i], ok);     // Z_k, Z_{k+hh}
+      const double2 zk2 = cadd(rb[i], ok2), zk2h = csub(rb[i], ok2); // Z_k2, Z_{k2+hh}
+      double2 gk, gkh, gk2 = zk2, gk2h = zk2h, unused;
+      if (!odd) {
+        if (k == 0) {  // self-paired 0 and hh
+          rl_even_pair(zk, zk, mult(0), mult(2 * h), wm(0), gk, unused);
+          rl_even_pair(zkh, zkh, mult(h), mult(h), wm(h), gkh, unused);
+        } else {
+          // pairs (k, h - k = k2 + hh) and (k2, h - k2 = k + hh)
+          rl_even_pair(zk, zk2h, mult(2 * k), mult(2 * h - 2 * k), wm(2 * k), gk, gk2h);
+          rl_even_pair(zk2, zkh, mult(2 * k2), mult(2 * h - 2 * k2), wm(2 * k2), gk2, gkh);
+        }
+      } else {
+        // pairs (k, h - 1 - k = k2 + hh) and (k2, h - 1 - k2 = k + hh)
+        const double2 om = wm(1);
+        rl_odd_pair(zk, zk2h, mult(2 * k + 1), mult(2 * k + 2 * h + 1), wm(2 * k + 1), wm(2 * k),
+                    om, gk, gk2h);
+        rl_odd_pair(zk2, zkh, mult(2 * k2 + 1), mult(2 * k2 + 2 * h + 1), wm(2 * k2 + 1),
+                    wm(2 * k2), om, gk2, gkh);
+      }
+      X[lpad(k)] = cadd(gk, gkh);
+      ra[i] = cmul(csub(gk, gkh), wk);
+      if (k2 != k) {
+        X[lpad(k2)] = cadd(gk2, gk2h);
+        rb[i] = cmul(csub(gk2, gk2h), wk2);
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      t = opaque_tid();
+      if (s == 1) {
+#pragma unroll
+        for (int i = 0; i <= NQ; ++i) {
+          if (i == NQ && !extra) continue;
+          const int k = k_of(i), k2 = k2_of(k);
+          X[lpad(k)] = ra[i];
+          if (k2 != k) X[lpad(k2)] = rb[i];
+        }
+        __syncthreads();
+      }
+      rl_fft<LHH>(X, ptw);
+      emit(s, odd);
+      __syncthreads();
+    }
+  }
+}
+
+// Refinement of one template over a segment with m = 8 hh (the split transforms above).
+template <int LH>
+__device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &sd, int64_t b,
+                                              double2 *X, RlAcc &acc) {
+  constexpr int h = 1 << LH, hh = h / 2;
+  constexpr int NI = hh / RL_THREADS;  // position iterations per half
   static_assert(NI % RL_CH == 0, "whole chunks");
-  // the thread index is re-read (opaquely) at each phase, so that per-position addresses
-  // and masks are recomputed there instead of being held in registers across phases
   int t = opaque_tid();
   const float *__restrict__ y = it.y0 + b * it.n_pad;
   const double *__restrict__ hrow = template_row(it, b) + sd.offset;
@@ -1552,8 +1654,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
 #pragma unroll
       for (int u = 0; u < 2; ++u) xv[c][u] = rr[c][u] >= 0 ? y[rr[c][u]] : 0.f;
   };
-  // X[n] = packed samples of half s (times w_m^{4n + 2s} for the skew-circulant part)
-  auto stage_half = [&](int s, bool skew) {
+  auto stage = [&](int s, bool odd) {
     t = opaque_tid();
     for (int i0 = 0; i0 < NI; i0 += RL_CH) {
       int32_t rr[RL_CH][2];
@@ -1563,137 +1664,67 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
       for (int c = 0; c < RL_CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 z = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
-        X[lpad(n)] = skew ? cmul(z, wm(4 * n + 2 * s)) : z;
+        X[lpad(n)] = odd ? cmul(z, wm(4 * n + 2 * s)) : z;
       }
     }
     __syncthreads();
   };
+  auto mult = [&](int r) { return lam[r]; };
+  // even part: t_E / m parked in e; odd part: C y0 = e + t_O / m, then the residual
+  // e = h - C y0 and the dot products
+  auto emit = [&](int s, bool odd) {
+    t = opaque_tid();
+    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+      int32_t rr[RL_CH][2];
+      float xv[RL_CH][2];
+      if (!odd) {
+#pragma unroll
+        for (int c = 0; c < RL_CH; ++c) {
+          const int n = t + RL_THREADS * (i0 + c);
+          rr[c][0] = row_of(4 * n + 2 * s);
+          rr[c][1] = row_of(4 * n + 2 * s + 1);
+        }
+#pragma unroll
+        for (int c = 0; c < RL_CH; ++c) {
+          const double2 v = X[lpad(t + RL_THREADS * (i0 + c))];
+          if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
+          if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
+        }
+        continue;
+      }
+      double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
+      load_x(i0, s, rr, xv);
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int n = t + RL_THREADS * (i0 + c);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int jj = 4 * n + 2 * s + u;
+          ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
+          hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
+          yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int n = t + RL_THREADS * (i0 + c);
+        const double2 gz = conj2(cmul(wm(4 * n + 2 * s), X[lpad(n)]));
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (rr[c][u] < 0) continue;
+          const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
+          const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
+          e[rr[c][u]] = hv[c][u] - cz;
+          acc.hy += hv[c][u] * xd;
+          acc.ydh += hv[c][u] * yv[c][u];
+          acc.yc += xd * cz;
+        }
+      }
+    }
+  };
 
   for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
-
-#pragma unroll 1
-  for (int part = 0; part < 2; ++part) {
-    const bool odd = part == 1;
-    // quadruple i of this thread: k = t + RL_THREADS i and its partner k2; the even part's
-    // k = hh/2 (its own partner) goes to thread 0 as an extra quadruple
-    auto k_of = [&](int i) { return i < NQ ? t + RL_THREADS * i : hh / 2; };
-    auto k2_of = [&](int k) { return odd ? hh - 1 - k : (hh - k) & (hh - 1); };
-    const bool extra = !odd && t == 0;
-    double2 ra[NQ + 1], rb[NQ + 1];  // E_k, E_k2, then B_k, B_k2
-    stage_half(0, odd);
-    rl_fft<LHH>(X, ptw);
-    t = opaque_tid();
-#pragma unroll
-    for (int i = 0; i <= NQ; ++i) {
-      if (i == NQ && !extra) continue;
-      const int k = k_of(i);
-      ra[i] = X[lpad(k)];
-      rb[i] = X[lpad(k2_of(k))];
-    }
-    __syncthreads();
-    stage_half(1, odd);
-    rl_fft<LHH>(X, ptw);
-    t = opaque_tid();
-#pragma unroll
-    for (int i = 0; i <= NQ; ++i) {
-      if (i == NQ && !extra) continue;
-      const int k = k_of(i), k2 = k2_of(k);
-      const double2 wk = wm(4 * k), wk2 = wm(4 * k2);  // w_h^k, w_h^k2
-      const double2 ok = cmul(wk, X[lpad(k)]), ok2 = cmul(wk2, X[lpad(k2)]);
-      const double2 zk = cadd(ra[i], ok), zkh = csub(ra[i], ok);     // Z_k, Z_{k+hh}
-      const double2 zk2 = cadd(rb[i], ok2), zk2h = csub(rb[i], ok2); // Z_k2, Z_{k2+hh}
-      double2 gk, gkh, gk2 = zk2, gk2h = zk2h, unused;
-      if (!odd) {
-        if (k == 0) {  // self-paired 0 and hh
-          rl_even_pair(zk, zk, lam[0], lam[2 * h], wm(0), gk, unused);
-          rl_even_pair(zkh, zkh, lam[h], lam[h], wm(h), gkh, unused);
-        } else {
-          // pairs (k, h - k = k2 + hh) and (k2, h - k2 = k + hh)
-          rl_even_pair(zk, zk2h, lam[2 * k], lam[2 * h - 2 * k], wm(2 * k), gk, gk2h);
-          rl_even_pair(zk2, zkh, lam[2 * k2], lam[2 * h - 2 * k2], wm(2 * k2), gk2, gkh);
-        }
-      } else {
-        // pairs (k, h - 1 - k = k2 + hh) and (k2, h - 1 - k2 = k + hh)
-        const double2 om = wm(1);
-        rl_odd_pair(zk, zk2h, lam[2 * k + 1], lam[2 * k + 2 * h + 1], wm(2 * k + 1), wm(2 * k),
-                    om, gk, gk2h);
-        rl_odd_pair(zk2, zkh, lam[2 * k2 + 1], lam[2 * k2 + 2 * h + 1], wm(2 * k2 + 1),
-                    wm(2 * k2), om, gk2, gkh);
-      }
-      X[lpad(k)] = cadd(gk, gkh);
-      ra[i] = cmul(csub(gk, gkh), wk);
-      if (k2 != k) {
-        X[lpad(k2)] = cadd(gk2, gk2h);
-        rb[i] = cmul(csub(gk2, gk2h), wk2);
-      }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int s = 0; s < 2; ++s) {
-      t = opaque_tid();
-      if (s == 1) {
-#pragma unroll
-        for (int i = 0; i <= NQ; ++i) {
-          if (i == NQ && !extra) continue;
-          const int k = k_of(i), k2 = k2_of(k);
-          X[lpad(k)] = ra[i];
-          if (k2 != k) X[lpad(k2)] = rb[i];
-        }
-        __syncthreads();
-      }
-      rl_fft<LHH>(X, ptw);
-      t = opaque_tid();
-      // output p = 2n + s: conj(X[n]) = t_{2p} + i t_{2p+1} (odd part: conj(w_m^{2p} X[n]))
-      for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-        int32_t rr[RL_CH][2];
-        float xv[RL_CH][2];
-        if (!odd) {
-#pragma unroll
-          for (int c = 0; c < RL_CH; ++c) {
-            const int n = t + RL_THREADS * (i0 + c);
-            rr[c][0] = row_of(4 * n + 2 * s);
-            rr[c][1] = row_of(4 * n + 2 * s + 1);
-          }
-#pragma unroll
-          for (int c = 0; c < RL_CH; ++c) {
-            const double2 v = X[lpad(t + RL_THREADS * (i0 + c))];
-            if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
-            if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
-          }
-          continue;
-        }
-        double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
-        load_x(i0, s, rr, xv);
-#pragma unroll
-        for (int c = 0; c < RL_CH; ++c) {
-          const int n = t + RL_THREADS * (i0 + c);
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int jj = 4 * n + 2 * s + u;
-            ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
-            hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
-            yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < RL_CH; ++c) {
-          const int n = t + RL_THREADS * (i0 + c);
-          const double2 gz = conj2(cmul(wm(4 * n + 2 * s), X[lpad(n)]));
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            if (rr[c][u] < 0) continue;
-            const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
-            const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
-            e[rr[c][u]] = hv[c][u] - cz;
-            acc.hy += hv[c][u] * xd;
-            acc.ydh += hv[c][u] * yv[c][u];
-            acc.yc += xd * cz;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
 }
 
 // Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
@@ -1754,11 +1785,15 @@ hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_w
 // Durbin's recursion: a = (1, a_1, .., a_k) the order-k prediction-error filter, E_k its
 // error energy; reflection kappa_k = -(sum_{j<k} a_j acf[k - j]) / E_{k-1}, a_j += kappa_k
 // a_{k-j} (pairwise, in place), E_k = E_{k-1} (1 - kappa_k^2); x = a / E_{n-1}.
+// The coefficients live in LDS, or (kGlobal, for n beyond the LDS) in x itself; either
+// way only this workgroup touches them, and its barriers order the accesses.
+template <bool kGlobal>
 __global__ __launch_bounds__(1024) void k_levinson(const double *__restrict__ acf, int n,
                                                    double *__restrict__ x,
                                                    double *__restrict__ logdet_out,
                                                    int32_t *__restrict__ fail) {
-  extern __shared__ double lev_a[];  // [n]
+  extern __shared__ double lev_lds[];  // [n] unless kGlobal
+  double *lev_a = kGlobal ? x : lev_lds;
   __shared__ double wsum[16];
   __shared__ double shE, shL;
   __shared__ int shFail;
@@ -1810,9 +1845,12 @@ __global__ __launch_bounds__(1024) void k_levinson(const double *__restrict__ ac
 
 hipError_t launch_levinson(const double *acf, int64_t n, double *x, double *logdet,
                            int32_t *fail, hipStream_t s) {
-  if (n < 1 || n > RL_MAX_LEV) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_levinson, dim3(1), dim3(1024), (size_t)n * sizeof(double), s, acf, (int)n,
-                     x, logdet, fail);
+  if (n < 1 || n > GS_MAX_LEN) return hipErrorInvalidValue;
+  if (n <= RL_MAX_LEV)
+    hipLaunchKernelGGL(k_levinson<false>, dim3(1), dim3(1024), (size_t)n * sizeof(double), s, acf,
+                       (int)n, x, logdet, fail);
+  else
+    hipLaunchKernelGGL(k_levinson<true>, dim3(1), dim3(1024), 0, s, acf, (int)n, x, logdet, fail);
   return hipGetLastError();
 }
 
@@ -1907,15 +1945,10 @@ __device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64
         const int k = t + RL_THREADS * (i0 + c);
         if (!(i0 + c < NKE && k <= h / 2)) continue;
         const int kr = (h - k) & (h - 1);
-        const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-        const double2 E = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-        const double2 O = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-        const double2 cO = cmul(cc[c], O);
-        const double2 yk = cmul(ma[c], cadd(E, cO));
-        const double2 yr = cmul(mb[c], conj2(csub(E, cO)));
-        const double2 ep = cadd(yk, conj2(yr)), op = csub(yk, conj2(yr));
-        X[lpad(k)] = conj2(cadd(ep, mul_i(cmul(conj2(cc[c]), op))));
-        if (k != 0 && k != h / 2) X[lpad(kr)] = conj2(cadd(conj2(ep), mul_i(cmul(cc[c], conj2(op)))));
+        double2 gk, gr;
+        rl_even_pair(X[lpad(k)], X[lpad(kr)], ma[c], mb[c], cc[c], gk, gr);
+        X[lpad(k)] = gk;
+        if (k != 0 && k != h / 2) X[lpad(kr)] = gr;
       }
     }
     __syncthreads();
@@ -1965,16 +1998,10 @@ __device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64
         const int k = t + RL_THREADS * (i0 + c);
         if (!(i0 + c < NKO && k < h / 2)) continue;
         const int kr = h - 1 - k;
-        const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
-        const double2 A = make_double2(0.5 * (vk.x + vr.x), 0.5 * (vk.y - vr.y));
-        const double2 B = make_double2(0.5 * (vk.y + vr.y), -0.5 * (vk.x - vr.x));
-        const double2 dB = cmul(dv[c], B);
-        const double2 yk = cmul(ma[c], cadd(A, dB));
-        const double2 ykh = cmul(mb[c], csub(A, dB));
-        const double2 P = cadd(yk, ykh);
-        const double2 Q = cmul(conj2(cc[c]), csub(yk, ykh));
-        X[lpad(k)] = conj2(cadd(P, mul_i(cmul(conj2(om), Q))));
-        X[lpad(kr)] = conj2(cadd(conj2(P), mul_i(cmul(om, conj2(Q)))));
+        double2 gk, gr;
+        rl_odd_pair(X[lpad(k)], X[lpad(kr)], ma[c], mb[c], dv[c], cc[c], om, gk, gr);
+        X[lpad(k)] = gk;
+        X[lpad(kr)] = gr;
       }
     }
     __syncthreads();
@@ -1992,6 +2019,72 @@ __device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64
     }
     __syncthreads();
   }
+  return ss;
+}
+
+// gs_sumsq for m = 8 hh, through the split transforms of the refinement.
+template <int LH>
+__device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd, int64_t b,
+                                              const double2 *__restrict__ M, double2 *X,
+                                              double *__restrict__ tes) {
+  constexpr int h = 1 << LH, hh = h / 2;
+  constexpr int NI = hh / RL_THREADS;
+  static_assert(NI % RL_CH == 0, "whole chunks");
+  int t = opaque_tid();
+  const double *__restrict__ hrow = gs_template_row(it, b) + sd.offset;
+  const double *__restrict__ dd = it.d + sd.offset;
+  const double2 *__restrict__ tw = (const double2 *)sd.tw;
+  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
+  const int len = (int)sd.length;
+  const double inv_m = 1.0 / (double)(4 * h);
+  auto wm = [&](int r) {
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  auto stage = [&](int s, bool odd) {
+    t = opaque_tid();
+    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
+      double rv[RL_CH][2];
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int jj = 4 * (t + RL_THREADS * (i0 + c)) + 2 * s + u;
+          rv[c][u] = jj < len ? dd[jj] - hrow[jj] : 0.0;
+        }
+#pragma unroll
+      for (int c = 0; c < RL_CH; ++c) {
+        const int n = t + RL_THREADS * (i0 + c);
+        const double2 z = make_double2(rv[c][0], rv[c][1]);
+        X[lpad(n)] = odd ? cmul(z, wm(4 * n + 2 * s)) : z;
+      }
+    }
+    __syncthreads();
+  };
+  auto mult = [&](int r) { return M[r]; };
+  double ss = 0.0;
+  // even part parked in this workgroup's scratch (the same thread reads it back)
+  auto emit = [&](int s, bool odd) {
+    t = opaque_tid();
+    for (int i = 0; i < NI; ++i) {
+      const int n = t + RL_THREADS * i, j0 = 4 * n + 2 * s;
+      if (j0 >= len) continue;
+      if (!odd) {
+        const double2 g = X[lpad(n)];
+        tes[j0] = g.x;
+        if (j0 + 1 < len) tes[j0 + 1] = -g.y;
+        continue;
+      }
+      const double2 gz = conj2(cmul(wm(j0), X[lpad(n)]));
+      const double c0 = (tes[j0] + gz.x) * inv_m;
+      ss += c0 * c0;
+      if (j0 + 1 < len) {
+        const double c1 = (tes[j0 + 1] + gz.y) * inv_m;
+        ss += c1 * c1;
+      }
+    }
+  };
+  rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
   return ss;
 }
 
@@ -2024,6 +2117,12 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
         TDA_GS(2) TDA_GS(3) TDA_GS(4) TDA_GS(5) TDA_GS(6) TDA_GS(7) TDA_GS(8) TDA_GS(9)
         TDA_GS(10) TDA_GS(11) TDA_GS(12) TDA_GS(13)
 #undef TDA_GS
+        case RL_LHMAX + 1: {
+          const double s1 = gs_sumsq_split<RL_LHMAX + 1>(it, sd, b, (const double2 *)sd.M1, X, tes);
+          const double s2 = gs_sumsq_split<RL_LHMAX + 1>(it, sd, b, (const double2 *)sd.M2, X, tes);
+          qp += (s1 - s2) * sd.inv_x0;
+          break;
+        }
         default: bad = true;
       }
     }
@@ -2052,7 +2151,7 @@ void register_mixed_attributes() {
                       (int)RL_LDS_BYTES);
   hipFuncSetAttribute((const void *)k_gs, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)RL_LDS_BYTES);
-  hipFuncSetAttribute((const void *)k_levinson, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipFuncSetAttribute((const void *)k_levinson<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)(RL_MAX_LEV * sizeof(double)));
 }
 

@@ -454,9 +454,9 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
       const Seg &g = h->segs[si];
       if (g.n_keep != g.length)
         return cleanup(fail_with(TDA_EINVAL, "GS precision: segment %zu has excluded samples", si));
-      if (g.length > RL_MAX_LEV)
+      if (g.length > GS_MAX_LEN)
         return cleanup(fail_with(TDA_EINVAL, "GS precision: segment %zu is longer than %d samples",
-                                 si, RL_MAX_LEV));
+                                 si, GS_MAX_LEN));
     }
   } else {
     // dense blocks (lower triangle used), assembled now

@@ -281,8 +281,11 @@ __device__ __forceinline__ const double *gs_template_row(const GsItem &it, int64
 
 // Levinson-Durbin for the first column of the inverse of the symmetric Toeplitz matrix
 // with first column acf[0..n): x = C^-1 e_1, log det C = sum log E_k; *fail = first k with
-// E_k <= 0 or not finite (else -1).  One workgroup; n <= RL_MAX_LEV.
+// E_k <= 0 or not finite (else -1).  One workgroup; n <= GS_MAX_LEN, with the
+// coefficients in LDS up to RL_MAX_LEV and in x (global memory) beyond.
 constexpr int RL_MAX_LEV = 16384;
+// Longest Gohberg-Semencul segment: its circulant (m >= 2 n) refines in LDS with split DFTs.
+constexpr int GS_MAX_LEN = (int)(RL_MAX_M_SPLIT / 2);
 hipError_t launch_levinson(const double *acf, int64_t n, double *x, double *logdet,
                            int32_t *fail, hipStream_t s);
 // conj(DFT_m) of x zero-padded and of (0, x_{n-1}, ..., x_1) zero-padded

@@ -52,6 +52,49 @@ def test_gs_parity(tda, N, B, segments, eps):
     h.close()
 
 
+# Segments of 16385 .. 32768 samples: Levinson with its coefficients in global memory and
+# the correlations through split DFTs (m = 65536); one case mixes them with a short segment.
+@pytest.mark.parametrize("N,B,segments", [(20000, 40, None), (32768, 48, None),
+                                          (20000, 33, [(0, 17000), (17000, 3000)])])
+def test_gs_long_segments_ar1_closed_form(tda, N, B, segments):
+    from gpu_util import to_dev
+    from test_oracle_pins import ar1_acf, ar1_whiten_closed
+    print(f"case N={N} B={B} segments={segments}", flush=True)
+    s, phi = 0.8, 0.97
+    acf = ar1_acf(N, s, phi)
+    rng = np.random.default_rng(N + B)
+    d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
+    want = np.zeros(B)
+    n_eff = 0
+    for off, L in (segments or [(0, N)]):
+        w = ar1_whiten_closed(d[None, off:off + L] - H[:, off:off + L], s, phi)
+        ld = np.log(s * s / (1 - phi * phi)) + (L - 1) * np.log(s * s)
+        want += -0.5 * (w * w).sum(1) - 0.5 * ld
+        n_eff += L
+    want -= 0.5 * n_eff * np.log(2 * np.pi)
+    h = tda.Handle(acf, N, None, segments, precision="gs").factor()
+    got = h.loglik(to_dev(d), to_dev(H)).cpu().numpy()
+    assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+    h.close()
+
+
+def test_gs_long_segment_vs_fp64_and_limit(tda):
+    """N = 20000 with the benchmark's ACF recipe: GS against the FP64 (Cholesky) path; a
+    segment one sample beyond the limit is refused."""
+    from gpu_util import to_dev
+    inst = synth.random_rhs_case(77, 20000, 1, 0, 64, eps=1e-6)
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    hg = tda.Handle(inst.acf, inst.N, None, precision="gs").factor()
+    hf = tda.Handle(inst.acf, inst.N, None, precision="fp64").factor()
+    got, ref = hg.loglik(d, H).cpu().numpy(), hf.loglik(d, H).cpu().numpy()
+    assert abs(hg.info()["logdet"] - hf.info()["logdet"]) <= 1e-9 * abs(hf.info()["logdet"])
+    assert np.all(np.abs(got - ref) <= TOLGS(ref)), np.max(np.abs(got - ref))
+    hg.close(); hf.close()
+    with pytest.raises(tda.TdaError) as e:
+        tda.Handle(synth.make_acf(32769), 32769, None, precision="gs")
+    assert e.value.name == "TDA_EINVAL"
+
+
 def test_gs_full_size_and_vs_fp64(tda):
     """Two detectors x N = 16384 (the benchmark shape), 256 templates: GS vs the FP64
     Cholesky path on the GPU, and vs the oracle on a sample."""
