@@ -249,7 +249,7 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   const int64_t nks = it.n_pad / 16;
   const int64_t chunks = (int64_t)(it.Bp / 32) * nks * 64;
   const int64_t chunk = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (chunk >= chunks || it.B == 0) return;
+  if (chunk >= chunks || it.B == 0 || (!from_e && it.hs_shared)) return;
   const int lane = (int)(chunk & 63);
   const int64_t ks = (chunk >> 6) % nks;
   const int64_t tt = (chunk >> 6) / nks;
@@ -285,8 +285,8 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
   vl.x = lo[0] | ((uint32_t)lo[1] << 16); vl.y = lo[2] | ((uint32_t)lo[3] << 16);
   vl.z = lo[4] | ((uint32_t)lo[5] << 16); vl.w = lo[6] | ((uint32_t)lo[7] << 16);
-  *reinterpret_cast<uint4 *>(it.hs_hi + dst) = vh;
-  *reinterpret_cast<uint4 *>(it.hs_lo + dst) = vl;
+  *reinterpret_cast<uint4 *>((from_e ? it.es_hi : it.hs_hi) + dst) = vh;
+  *reinterpret_cast<uint4 *>((from_e ? it.es_lo : it.hs_lo) + dst) = vl;
 }
 
 hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
@@ -694,8 +694,8 @@ __device__ __forceinline__ void corr_block(const MixItem *items, const int4 *wor
   constexpr int64_t dir = ph ? -1 : 1;
   const FragSrc A{it.wa_hi + it.wa_off[i] + k1 * 8 * FRAG, it.wa_lo + it.wa_off[i] + k1 * 8 * FRAG,
                   FRAG, dir * 8 * FRAG};
-  const FragSrc B{it.hs_hi + (T0 * it.tks + ks0 + k1) * FRAG,
-                  it.hs_lo + (T0 * it.tks + ks0 + k1) * FRAG, it.tks * FRAG, dir * FRAG};
+  const FragSrc B{it.es_hi + (T0 * it.tks + ks0 + k1) * FRAG,
+                  it.es_lo + (T0 * it.tks + ks0 + k1) * FRAG, it.tks * FRAG, dir * FRAG};
   f16v acc[4][L::WB];
   gemm3_v<CORR_PROD, V>(A, B, nks, tid, acc);
   // per column: sum of squares over the wave's 128 rows; the two row halves of the

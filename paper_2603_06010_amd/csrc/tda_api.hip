@@ -200,6 +200,8 @@ struct tda_ctx {
   // device state
   DevBuf acf_d, idx_d, pos2row_d, blk_first_d, blk_last_d;
   DevBuf retpos_d;     // [n_pad] position of each padded row among the retained samples, -1 = padding
+  std::vector<int32_t> idx_h;  // host copy of idx (sample of each padded row, -1 = padding)
+  uint64_t idx_hash = 0;       // FNV-1a of idx_h
   DevBuf A_d;          // dense per-segment blocks (until factored)
   DevBuf dinv128_d, dinv256_d, logdiag_d, logdet_d, fail_d;
   DevBuf panels_d, panel_off_d;
@@ -420,6 +422,9 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   }
   h->n_pad = row;
   h->nblk = blk;
+  h->idx_h = idx;
+  h->idx_hash = 1469598103934665603ull;
+  for (int32_t v : idx) h->idx_hash = (h->idx_hash ^ (uint32_t)v) * 1099511628211ull;
   if (h->n_pad > ((int64_t)1 << 31) / TB) {
     delete h;
     return fail_with(TDA_EINVAL, "too many rows");
@@ -1045,6 +1050,8 @@ static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int
   mi.ldh = ldh;
   mi.hs_hi = ws.hs_hi;
   mi.hs_lo = ws.hs_lo;
+  mi.es_hi = ws.hs_hi;  // the residual's split reuses the buffer once the products are done
+  mi.es_lo = ws.hs_lo;
   mi.w0_hi = ws.w0_hi;
   mi.w0_lo = ws.w0_lo;
   mi.y0 = ws.y0;
@@ -1516,6 +1523,21 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
       ris[k] = make_ref_item(w.h, mis[k]);
       hs[k] = w.h;
     }
+    // detectors that evaluate the same templates over the same padded rows share one
+    // template split: the split pass runs once and the forward products read one copy
+    for (int64_t k = 1; k < n_items; ++k)
+      for (int64_t j = 0; j < k; ++j) {
+        const MixItem &a = mis[j];
+        MixItem &b = mis[k];
+        if (a.hs_shared || a.H != b.H || a.ldh != b.ldh || a.Hrows != b.Hrows || a.B != b.B ||
+            a.Bp != b.Bp || a.tks != b.tks || hs[j]->idx_hash != hs[k]->idx_hash ||
+            hs[j]->idx_h != hs[k]->idx_h)
+          continue;
+        b.hs_hi = a.hs_hi;
+        b.hs_lo = a.hs_lo;
+        b.hs_shared = 1;
+        break;
+      }
     TDA_TRY(enqueue_mixed(mc->ring, mis, ris, hs, (double *)P.ws_fft.p, max_m, s));
     HIP_TRY(mc->ring.reserve(4096 + n_items * 16 + group_out.size() * 16));
   }

@@ -90,6 +90,8 @@ struct MixItem {
   int64_t ldh;
   const double *const *Hrows;      // optional per-template row pointers
   uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][tks][64][8]
+                                   // (another item's, when hs_shared)
+  uint16_t *es_hi, *es_lo;         // split residual e, same layout (this item's own buffer)
   uint16_t *w0_hi, *w0_lo;         // split W h, same layout as hs
   int64_t tks;                     // k-steps per template tile in those layouts (n_pad/16 + TKS_PAD)
   float *y0;                       // [Bp][n_pad]
@@ -102,6 +104,8 @@ struct MixItem {
   int32_t B, Bp;                   // templates, padded to a multiple of MT
   int32_t nblk;
   int32_t n_pad;
+  int32_t hs_shared;               // hs is split by an earlier item (same templates and rows)
+  int32_t pad0;
 };
 
 // Template tiles of the split layouts are n_pad/16 + TKS_PAD fragments apart: without the

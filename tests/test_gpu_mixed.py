@@ -215,6 +215,33 @@ def test_multi_matches_single(tda):
         np.testing.assert_allclose(out.cpu().numpy(), single.cpu().numpy(), rtol=0, atol=1e-9)
 
 
+def test_multi_shared_template_split(tda):
+    """Detectors with the same templates and the same retained rows share one template
+    split in a batched call; a third item with other rows (and a fourth with other
+    templates) does not.  Every item's logL equals its single-handle evaluation."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(91, 3000, 2, 2, 80)
+    other = synth.random_rhs_case(92, 3000, 1, 1, 80)
+    mask = inst.masks[0]
+    hs = [tda.Handle(inst.acf, inst.N, mask, precision="mixed").factor() for _ in range(2)]
+    hs.append(tda.Handle(inst.acf, inst.N, other.masks[0], precision="mixed").factor())
+    hs.append(tda.Handle(inst.acf, inst.N, mask, precision="mixed").factor())
+    ds = [to_dev(inst.d[0]), to_dev(inst.d[1]), to_dev(inst.d[0]), to_dev(other.d[0])]
+    H, H2 = to_dev(inst.H), to_dev(other.H)
+    Hs = [H, H, H, H2]
+    outs = [torch.empty(80, dtype=torch.float64, device="cuda") for _ in range(4)]
+    tda.loglik_multi([(h, d, Hk, o) for h, d, Hk, o in zip(hs, ds, Hs, outs)], precision="mixed")
+    torch.cuda.synchronize()
+    for h, d, Hk, o in zip(hs, ds, Hs, outs):
+        single = h.loglik(d, Hk).cpu().numpy()
+        np.testing.assert_allclose(o.cpu().numpy(), single, rtol=0, atol=1e-9)
+    f = oracle.factor(inst.acf, inst.N, mask)
+    _check_mixed(outs[1].cpu().numpy(), oracle.loglik(f, inst.d[1], inst.H))
+    for h in hs:
+        h.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_plan_graph_replay(tda, precision):
     """A captured plan replayed several times, with eager work in between, matches the
