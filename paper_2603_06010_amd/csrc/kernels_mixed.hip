@@ -230,11 +230,11 @@ hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *t
   const unsigned g = (unsigned)((m + 255) / 256);
   hipLaunchKernelGGL(k_twiddles, dim3(g), dim3(256), 0, s, m, tw);
   if (lam) hipLaunchKernelGGL(k_lambda, dim3(g), dim3(256), 0, s, acf, length, m, tw, lam);
-  if (ptw && m >= 16 && m <= RL_MAX_M_SPLIT) {
+  if (ptw && m >= 16 && m <= RL_MAX_M_QUAD) {
     int lm = 0;
     while (((int64_t)1 << lm) < m) ++lm;
-    // the m/4-point DFT, or its two halves beyond the LDS array
-    const int lh = m <= RL_MAX_M ? lm - 2 : lm - 3;
+    // the m/4-point DFT, or its halves or quarters beyond the LDS array
+    const int lh = lm - 2 <= RL_LHMAX ? lm - 2 : RL_LHMAX;
     const int n = rl_tw_size(lh);
     if (n > 0) hipLaunchKernelGGL(k_pass_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, lh, ptw);
   }
@@ -1606,12 +1606,141 @@ __device__ __forceinline__ void rl_split_parts(double2 *X, const double2 *__rest
   }
 }
 
-// Refinement of one template over a segment with m = 8 hh (the split transforms above).
-template <int LH>
+// Segments with m = 16 hq (h = 4 hq, hq = 2^(LH-2) the largest in-LDS length): each
+// h-point DFT is four hq-point DFTs of the packed samples p = 4q + s (radix-4 decimation
+// in time): Z_{k0 + hq j} = sum_s (-i)^{sj} U_s with U_s = w_h^{s k0} F_s[k0].  F_0..F_2
+// wait in the workgroup's global scratch S (3 hq complex) while F_3 is in LDS.  The
+// pointwise stage takes the frequencies in groups {k0, k1} x {j = 0..3}, k1 = hq - k0
+// (even part) or hq - 1 - k0 (odd part), closed under its pairing (partner of k0 + hq j
+// is k1 + hq (3 - j)); a group yields the four quarters of the next DFT's input (radix-4
+// decimation in frequency), A_s[p0] = w_h^{s p0} sum_j (-i)^{sj} G[p0 + hq j], whose
+// hq-point DFTs give the outputs 4n + s.  A_3 goes to LDS, A_0..A_2 over F_0..F_2 in S.
+// Callbacks as for rl_split_parts, with quarters s = 0..3 (samples 8n + 2s, 8n + 2s + 1).
+
+// V_j = sum_s (-i)^{sj} U_s (4-point forward DFT)
+__device__ __forceinline__ void dft4(const double2 (&u)[4], double2 (&v)[4]) {
+  const double2 a = cadd(u[0], u[2]), b = csub(u[0], u[2]);
+  const double2 c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
+  const double2 md = make_double2(d.y, -d.x);  // -i d
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, md);
+  v[3] = csub(b, md);
+}
+
+template <int LH, class Stage, class Mult, class Emit>
+__device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ S,
+                                              const double2 *__restrict__ tw,
+                                              const double2 *__restrict__ ptw, Stage &&stage,
+                                              Mult &&mult, Emit &&emit) {
+  constexpr int LHQ = LH - 2;
+  constexpr int h = 1 << LH, hq = 1 << LHQ;
+  static_assert(hq >= 2 * RL_THREADS && hq % (2 * RL_THREADS) == 0, "whole groups per thread");
+  constexpr int NI = hq / RL_THREADS;      // positions per thread and quarter
+  constexpr int NG = hq / 2 / RL_THREADS;  // groups per thread
+  auto wm = [&](int r) {  // w_m^r, 0 <= r < m
+    const double2 v = tw[r];
+    return make_double2(v.x, -v.y);
+  };
+  int t = opaque_tid();
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    const bool odd = part == 1;
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+      stage(s, odd);
+      rl_fft<LHQ>(X, ptw);
+      if (s < 3) {
+        t = opaque_tid();
+        for (int i = 0; i < NI; ++i) {
+          const int n = t + RL_THREADS * i;
+          S[s * hq + n] = X[lpad(n)];
+        }
+        __syncthreads();
+      }
+    }
+    t = opaque_tid();
+    // the even part's k0 = hq/2 (its own partner) goes to thread 0 as an extra group
+#pragma unroll 1
+    for (int i = 0; i <= NG; ++i) {
+      if (i == NG && (odd || t != 0)) continue;
+      const int k0 = i < NG ? t + RL_THREADS * i : hq / 2;
+      const int k1 = odd ? hq - 1 - k0 : (hq - k0) & (hq - 1);
+      double2 za[4], zb[4], ga[4], gb[4];
+      {
+        double2 u[4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] = S[q * hq + k0];
+        u[3] = X[lpad(k0)];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) u[q] = cmul(wm(4 * q * k0), u[q]);
+        dft4(u, za);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] = S[q * hq + k1];
+        u[3] = X[lpad(k1)];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) u[q] = cmul(wm(4 * q * k1), u[q]);
+        dft4(u, zb);
+      }
+      if (!odd && k0 == 0) {
+        // 0 and h/2 pair with themselves, hq with 3 hq
+        double2 unused;
+        rl_even_pair(za[0], za[0], mult(0), mult(2 * h), wm(0), ga[0], unused);
+        rl_even_pair(za[1], za[3], mult(2 * hq), mult(2 * h - 2 * hq), wm(2 * hq), ga[1], ga[3]);
+        rl_even_pair(za[2], za[2], mult(h), mult(h), wm(h), ga[2], unused);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + hq * j;  // partner h - k (even) or h - 1 - k (odd) = k1 + hq (3 - j)
+          if (!odd)
+            rl_even_pair(za[j], zb[3 - j], mult(2 * k), mult(2 * h - 2 * k), wm(2 * k), ga[j],
+                         gb[3 - j]);
+          else
+            rl_odd_pair(za[j], zb[3 - j], mult(2 * k + 1), mult(2 * k + 2 * h + 1), wm(2 * k + 1),
+                        wm(2 * k), wm(1), ga[j], gb[3 - j]);
+        }
+      }
+      // quarters of the inverse DFT's input at p0 = k0 and p0 = k1
+      double2 v[4];
+      dft4(ga, v);
+      X[lpad(k0)] = cmul(wm(12 * k0), v[3]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) S[q * hq + k0] = q ? cmul(wm(4 * q * k0), v[q]) : v[q];
+      if (k1 != k0) {
+        dft4(gb, v);
+        X[lpad(k1)] = cmul(wm(12 * k1), v[3]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) S[q * hq + k1] = q ? cmul(wm(4 * q * k1), v[q]) : v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 3; s >= 0; --s) {
+      if (s < 3) {
+        t = opaque_tid();
+        for (int i = 0; i < NI; ++i) {
+          const int n = t + RL_THREADS * i;
+          X[lpad(n)] = S[s * hq + n];
+        }
+        __syncthreads();
+      }
+      rl_fft<LHQ>(X, ptw);
+      emit(s, odd);
+      __syncthreads();
+    }
+  }
+}
+
+// Refinement of one template over a segment whose transforms split into P = 2 halves
+// (m = 8 hh, rl_split_parts) or P = 4 quarters (m = 16 hq, rl_quad_parts, with the
+// workgroup's scratch S): part s of a transform carries the samples 2 P n + 2 s and
+// 2 P n + 2 s + 1.
+template <int LH, int P>
 __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &sd, int64_t b,
-                                              double2 *X, RlAcc &acc) {
-  constexpr int h = 1 << LH, hh = h / 2;
-  constexpr int NI = hh / RL_THREADS;  // position iterations per half
+                                              double2 *X, double2 *S, RlAcc &acc) {
+  static_assert(P == 2 || P == 4, "halves or quarters");
+  constexpr int h = 1 << LH;
+  constexpr int NI = h / P / RL_THREADS;  // position iterations per part
   static_assert(NI % RL_CH == 0, "whole chunks");
   int t = opaque_tid();
   const float *__restrict__ y = it.y0 + b * it.n_pad;
@@ -1620,7 +1749,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   const int32_t *__restrict__ p2r = it.pos2row + sd.offset;
   double *__restrict__ e = it.e64 + b * it.n_pad;
   const double2 *__restrict__ tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
-  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;  // passes of the hh-point DFT
+  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;  // passes of the part DFTs
   const double *__restrict__ lam = sd.lam;
   const int len = (int)sd.length;
   const bool dense = sd.nkeep == sd.length;
@@ -1641,13 +1770,13 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
     }
     return (double)v;
   };
-  // rows and y0 values of the samples 4n + 2s, 4n + 2s + 1, n = t + RL_THREADS (i0 + c)
+  // rows and y0 values of the samples 2Pn + 2s, 2Pn + 2s + 1, n = t + RL_THREADS (i0 + c)
   auto load_x = [&](int i0, int s, int32_t (&rr)[RL_CH][2], float (&xv)[RL_CH][2]) {
 #pragma unroll
     for (int c = 0; c < RL_CH; ++c) {
       const int n = t + RL_THREADS * (i0 + c);
-      rr[c][0] = row_of(4 * n + 2 * s);
-      rr[c][1] = row_of(4 * n + 2 * s + 1);
+      rr[c][0] = row_of(2 * P * n + 2 * s);
+      rr[c][1] = row_of(2 * P * n + 2 * s + 1);
     }
 #pragma unroll
     for (int c = 0; c < RL_CH; ++c)
@@ -1664,7 +1793,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
       for (int c = 0; c < RL_CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 z = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
-        X[lpad(n)] = odd ? cmul(z, wm(4 * n + 2 * s)) : z;
+        X[lpad(n)] = odd ? cmul(z, wm(2 * P * n + 2 * s)) : z;
       }
     }
     __syncthreads();
@@ -1681,8 +1810,8 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
 #pragma unroll
         for (int c = 0; c < RL_CH; ++c) {
           const int n = t + RL_THREADS * (i0 + c);
-          rr[c][0] = row_of(4 * n + 2 * s);
-          rr[c][1] = row_of(4 * n + 2 * s + 1);
+          rr[c][0] = row_of(2 * P * n + 2 * s);
+          rr[c][1] = row_of(2 * P * n + 2 * s + 1);
         }
 #pragma unroll
         for (int c = 0; c < RL_CH; ++c) {
@@ -1699,7 +1828,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
         const int n = t + RL_THREADS * (i0 + c);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int jj = 4 * n + 2 * s + u;
+          const int jj = 2 * P * n + 2 * s + u;
           ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
           hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
           yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
@@ -1708,7 +1837,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
 #pragma unroll
       for (int c = 0; c < RL_CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
-        const double2 gz = conj2(cmul(wm(4 * n + 2 * s), X[lpad(n)]));
+        const double2 gz = conj2(cmul(wm(2 * P * n + 2 * s), X[lpad(n)]));
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           if (rr[c][u] < 0) continue;
@@ -1724,16 +1853,23 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   };
 
   for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
-  rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
+  if constexpr (P == 2)
+    rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
+  else
+    rl_quad_parts<LH>(X, S, tw, ptw, stage, mult, emit);
 }
 
 // Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
+// Segments of the largest circulant length also need scratch: 3 x 8192 complex doubles per
+// workgroup at qscratch (NULL when the launch has none).
 __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__restrict__ items,
                                                            const int2 *__restrict__ work,
-                                                           int64_t n_work) {
+                                                           int64_t n_work,
+                                                           double2 *__restrict__ qscratch) {
   extern __shared__ double2 rl_smem[];
   double2 *X = rl_smem;
   double *red = (double *)(rl_smem + RL_XN);
+  double2 *S = qscratch ? qscratch + (int64_t)blockIdx.x * RL_QUAD_SCRATCH : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
     const RefItem &it = items[wk.x];
@@ -1747,7 +1883,11 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
         TDA_RL(2) TDA_RL(3) TDA_RL(4) TDA_RL(5) TDA_RL(6) TDA_RL(7) TDA_RL(8) TDA_RL(9)
         TDA_RL(10) TDA_RL(11) TDA_RL(12) TDA_RL(13)
 #undef TDA_RL
-        case RL_LHMAX + 1: rl_segment_split<RL_LHMAX + 1>(it, sd, b, X, acc); break;
+        case RL_LHMAX + 1: rl_segment_split<RL_LHMAX + 1, 2>(it, sd, b, X, nullptr, acc); break;
+        case RL_LHMAX + 2:
+          if (S) rl_segment_split<RL_LHMAX + 2, 4>(it, sd, b, X, S, acc);
+          else acc.bad = 1.0;
+          break;
         default: acc.bad = 1.0;
       }
     }
@@ -1764,11 +1904,11 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
 
 
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
-                             hipStream_t s) {
+                             double *qscratch, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  const int64_t g = std::min<int64_t>(n_work, 2048);
+  const int64_t g = std::min<int64_t>(n_work, qscratch ? RL_QUAD_WG : 2048);
   hipLaunchKernelGGL(k_refine_lds, dim3((unsigned)g), dim3(RL_THREADS), RL_LDS_BYTES, s, items,
-                     work, n_work);
+                     work, n_work, (double2 *)qscratch);
   return hipGetLastError();
 }
 

@@ -867,6 +867,14 @@ std::vector<int4> xcd_order(std::vector<BlockJob> jobs) {
 
 constexpr int kRefineWG = 768;  // persistent refinement workgroups (3 per CU)
 
+// FFT scratch of a launch whose largest circulant is max_m: the global-scratch refinement
+// (m beyond the quarter split) or the quarters of the in-LDS one; none below that.
+static size_t fft_ws_bytes(int64_t max_m) {
+  if (max_m > RL_MAX_M_QUAD) return (size_t)kRefineWG * max_m * 16;
+  if (max_m > RL_MAX_M_SPLIT) return (size_t)RL_QUAD_WG * RL_QUAD_SCRATCH * 16;
+  return 0;
+}
+
 }  // namespace
 
 static tda_status build_mixed(tda_ctx *h) {
@@ -1141,7 +1149,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     if (mis[k].B == 0) continue;
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp / 256, 1, jf);
     add_block_jobs(hs[k], (int32_t)k, mis[k].Bp / 256, 2, jh);
-    const bool in_lds = hs[k]->max_m <= RL_MAX_M_SPLIT;
+    const bool in_lds = hs[k]->max_m <= RL_MAX_M_QUAD;
     if (!in_lds) add_refine_pairs((int32_t)k, mis[k].B, wr);
     for (int32_t b = 0; b < mis[k].B; ++b) {
       wfin.push_back(int2{(int32_t)k, b});
@@ -1150,7 +1158,11 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   }
   int64_t max_m_scratch = 0;
   for (int64_t k = 0; k < n; ++k)
-    if (mis[k].B > 0 && hs[k]->max_m > RL_MAX_M_SPLIT) max_m_scratch = std::max(max_m_scratch, hs[k]->max_m);
+    if (mis[k].B > 0 && hs[k]->max_m > RL_MAX_M_QUAD) max_m_scratch = std::max(max_m_scratch, hs[k]->max_m);
+  // quarter-split segments keep three quarters of their transforms in the same scratch
+  bool quad = false;
+  for (int64_t k = 0; k < n; ++k)
+    quad |= mis[k].B > 0 && hs[k]->max_m > RL_MAX_M_SPLIT && hs[k]->max_m <= RL_MAX_M_QUAD;
   // the forward, backward and correction products share the work lists (block pairs):
   // whole template groups, and half groups for the half-group variant
   const std::vector<int4> wf = xcd_order(jf), wh = xcd_order(jh);
@@ -1211,7 +1223,8 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   {
     TimedScope ts("refine_fft", s);
     if (!wrl.empty())
-      HIP_TRY(launch_refine_lds((const RefItem *)d_ri, (const int2 *)d_rl, (int64_t)wrl.size(), s));
+      HIP_TRY(launch_refine_lds((const RefItem *)d_ri, (const int2 *)d_rl, (int64_t)wrl.size(),
+                                quad ? fft_scratch : nullptr, s));
     if (!wr.empty())
       HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
                             fft_scratch, 2 * max_m_scratch, kRefineWG, s));
@@ -1288,7 +1301,7 @@ static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int
   if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
   const int64_t Bp = (B + MT - 1) / MT * MT;
   TDA_TRY(h->alloc(h->ws_mix, mix_ws_bytes(h, Bp)));
-  if (h->max_m > RL_MAX_M_SPLIT) TDA_TRY(h->alloc(h->ws_fft, (size_t)kRefineWG * h->max_m * 16));
+  if (fft_ws_bytes(h->max_m)) TDA_TRY(h->alloc(h->ws_fft, fft_ws_bytes(h->max_m)));
   const MixWs ws = carve_mix_ws(h, Bp, (char *)h->ws_mix.p);
   std::vector<MixItem> mis{make_mix_item(h, H, ldh, B, Bp, ws, out)};
   mis[0].hh_out = out_hh;
@@ -1513,7 +1526,7 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
       max_m = std::max(max_m, items[k].h->max_m);
     }
     TDA_TRY(P.alloc(P.ws_mix, total));
-    if (max_m > RL_MAX_M_SPLIT) TDA_TRY(P.alloc(P.ws_fft, (size_t)kRefineWG * max_m * 16));
+    if (fft_ws_bytes(max_m)) TDA_TRY(P.alloc(P.ws_fft, fft_ws_bytes(max_m)));
     for (int64_t k = 0; k < n_items; ++k) {
       const tda_work &w = items[k];
       const int64_t Bp = (w.B + MT - 1) / MT * MT;

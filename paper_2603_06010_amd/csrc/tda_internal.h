@@ -132,8 +132,13 @@ struct SegDev {
 // h = 2^LH: ceil(LH / 4) passes of near-equal radix, larger radices first.
 constexpr int RL_LHMAX = 13;
 constexpr int64_t RL_MAX_M = (int64_t)4 << RL_LHMAX;
-// Twice that length still refines in LDS, with each m/4-point DFT split into two halves.
+// Twice that length still refines in LDS, with each m/4-point DFT split into two halves;
+// four times, into quarters, three of which wait in per-workgroup global scratch of
+// RL_QUAD_SCRATCH complex doubles (launches with such segments run RL_QUAD_WG workgroups).
 constexpr int64_t RL_MAX_M_SPLIT = 2 * RL_MAX_M;
+constexpr int64_t RL_MAX_M_QUAD = 4 * RL_MAX_M;
+constexpr int64_t RL_QUAD_SCRATCH = (int64_t)3 << RL_LHMAX;
+constexpr int RL_QUAD_WG = 512;
 __host__ __device__ constexpr int rl_npass(int LH) { return LH <= 4 ? 1 : (LH + 3) / 4; }
 __host__ __device__ constexpr int rl_L(int LH, int p) {
   return LH / rl_npass(LH) + (p < LH % rl_npass(LH) ? 1 : 0);
@@ -299,10 +304,11 @@ hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double
 hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
                      int64_t scratch_stride, int32_t n_wg, hipStream_t s);
 
-// In-LDS refinement for launches whose segments all have m <= RL_MAX_M_SPLIT; work entries
-// (item, template).
+// In-LDS refinement for launches whose segments all have m <= RL_MAX_M_QUAD; work entries
+// (item, template).  qscratch: RL_QUAD_WG x RL_QUAD_SCRATCH complex doubles when a segment
+// has m > RL_MAX_M_SPLIT, else NULL.
 hipError_t launch_refine_lds(const RefItem *items, const int2 *work, int64_t n_work,
-                             hipStream_t s);
+                             double *qscratch, hipStream_t s);
 
 // ---------------------------------------------------------------- internal entry points (tda_api.hip)
 struct MultiCtx;

@@ -80,15 +80,17 @@ def _ar1_white_closed(X, keep, s, phi):
 
 
 # Segments beyond the in-LDS DFT length (m = 4 x 8192): m = 65536 refines in LDS with each
-# DFT split in halves (lengths 16385 .. 32768, dense rows and rows with excluded samples),
-# longer ones in the global-scratch path (m = 131072).
-@pytest.mark.parametrize("N,n_gaps,B", [(16385, 1, 40), (20000, 0, 64), (32768, 3, 96),
-                                        (40000, 2, 48)])
-def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B):
+# DFT split in halves (lengths 16385 .. 32768), m = 131072 with quarters, three of them in
+# per-workgroup scratch (lengths 32769 .. 65536); dense rows and rows with excluded samples,
+# one handle with segments of both kinds.
+@pytest.mark.parametrize("N,n_gaps,B,segments", [
+    (16385, 1, 40, None), (20000, 0, 64, None), (32768, 3, 96, None), (40000, 2, 48, None),
+    (65536, 0, 24, None), (60000, 1, 20, [(0, 40000), (40000, 20000)])])
+def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B, segments):
     from gpu_util import to_dev
     from test_oracle_pins import ar1_acf, gapped_ar1_closed
     import torch
-    print(f"case N={N} gaps={n_gaps} B={B}", flush=True)
+    print(f"case N={N} gaps={n_gaps} B={B} segments={segments}", flush=True)
     s, phi = 0.8, 0.97
     acf = ar1_acf(N, s, phi)
     gaps = synth.draw_gaps(np.random.default_rng(N), N, n_gaps)
@@ -96,12 +98,22 @@ def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B):
     rng = np.random.default_rng(N + 1)
     d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
     keep = np.flatnonzero(mask == 0)
-    wr, ld = _ar1_white_closed(d[None] - H, keep, s, phi)
-    want = -0.5 * (wr * wr).sum(1) - 0.5 * ld - 0.5 * len(keep) * np.log(2 * np.pi)
-    w5, ld5 = gapped_ar1_closed(d - H[5], keep, s, phi)  # the loop form, on one row
-    np.testing.assert_allclose(wr[5], w5, rtol=1e-12, atol=1e-12)
-    assert abs(ld - ld5) <= 1e-9 * abs(ld)
-    h = tda.Handle(acf, N, mask, precision="mixed").factor()
+    # segments are independent blocks: closed forms add over them
+    q = np.zeros(B); ld = 0.0; dh_want = np.zeros(B); hh_want = np.zeros(B)
+    for off, L in (segments or [(0, N)]):
+        ks = keep[(keep >= off) & (keep < off + L)]
+        wr, lds = _ar1_white_closed(d[None] - H, ks, s, phi)
+        wd, _ = _ar1_white_closed(d[None], ks, s, phi)
+        wh, _ = _ar1_white_closed(H, ks, s, phi)
+        q += (wr * wr).sum(1); ld += lds
+        dh_want += wh @ wd[0]; hh_want += (wh * wh).sum(1)
+    want = -0.5 * q - 0.5 * ld - 0.5 * len(keep) * np.log(2 * np.pi)
+    if segments is None:
+        wr, _ = _ar1_white_closed(d[None] - H, keep, s, phi)
+        w5, ld5 = gapped_ar1_closed(d - H[5], keep, s, phi)  # the loop form, on one row
+        np.testing.assert_allclose(wr[5], w5, rtol=1e-12, atol=1e-12)
+        assert abs(ld - ld5) <= 1e-9 * abs(ld)
+    h = tda.Handle(acf, N, mask, segments, precision="mixed").factor()
     dd, Hd = to_dev(d), to_dev(H)
     got = h.loglik(dd, Hd).cpu().numpy()
     f64 = h.loglik(dd, Hd, precision="fp64").cpu().numpy()
@@ -112,9 +124,6 @@ def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B):
     assert np.all(err >= -tolf), np.min(err)
     # the inner products from the same refinement: <d,h> and the refined <h,h> (<= exact)
     _, dh, hh = h.loglik_terms(dd, Hd)
-    wd, _ = _ar1_white_closed(d[None], keep, s, phi)
-    wh, _ = _ar1_white_closed(H, keep, s, phi)
-    dh_want, hh_want = wh @ wd[0], (wh * wh).sum(1)
     dh, hh = dh.cpu().numpy(), hh.cpu().numpy()
     assert np.max(np.abs(dh - dh_want)) <= TOL_MIXED, np.max(np.abs(dh - dh_want))
     assert np.max(np.abs(hh - hh_want)) <= TOL_MIXED, np.max(np.abs(hh - hh_want))
