@@ -132,6 +132,27 @@ def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B, segments):
     h.close()
 
 
+@pytest.mark.parametrize("variant", ["1", "2", "4", "5"])
+def test_small_batch_after_full_batch(tda, monkeypatch, variant):
+    """A batch with one live half group of templates, evaluated after a full group on the
+    same handle (same padded workspace, now holding the first batch's intermediates):
+    only template halves may be skipped, never the sample halves of the backward
+    product, so the result must match the oracle whatever the first batch left behind."""
+    from gpu_util import to_dev
+    import torch
+    monkeypatch.setenv("TDA_PRODUCT_VARIANT", variant)
+    inst = synth.random_rhs_case(61, 3000, 1, 1, 256)
+    h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision="mixed").factor()
+    d = to_dev(inst.d[0])
+    h.loglik(d, to_dev(inst.H * 50.0))
+    f = oracle.factor(inst.acf, inst.N, inst.masks[0])
+    for B in (96, 1, 129):
+        got = h.loglik(d, to_dev(inst.H[:B])).cpu().numpy()
+        _check_mixed(got, oracle.loglik(f, inst.d[0], inst.H[:B]))
+    torch.cuda.synchronize()
+    h.close()
+
+
 @pytest.mark.parametrize("N,n_gaps,B,segments", [
     (3000, 2, 300, None),
     (2600, 1, 130, [(0, 1000), (1200, 1300), (2550, 50)]),
