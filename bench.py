@@ -134,9 +134,8 @@ def main():
                          "kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; run with --gpus 1 "
-              "(templates and datasets shard across GPUs with no exchange in the hot loop, "
-              "see the design notes)", file=sys.stderr)
+        print("bench.py: measures one GPU only; run with --gpus 1 (templates and datasets "
+              "shard across GPUs with no exchange in the hot loop)", file=sys.stderr)
         sys.exit(2)
 
     import torch
