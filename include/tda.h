@@ -40,7 +40,7 @@
  *                     z = (0, x_{n-1}, .., x_1) and L(v) the lower-triangular
  *                     Toeplitz matrix of v, both products by FFT (O(n log n) per
  *                     template, no factorisation).  Only for segments without
- *                     excluded samples and of at most 32768 samples; a GS handle
+ *                     excluded samples and of at most 65536 samples; a GS handle
  *                     evaluates only in TDA_PREC_GS.
  *   TDA_PREC_CDO   -- an evaluation precision of mixed handles (not a handle
  *                     precision): FP64 through the explicit inverse, the
@@ -140,7 +140,7 @@ typedef struct {
  *            them on return.
  * Errors: EINVAL (N < 1, acf_len too short, acf[0] <= 0 or non-finite,
  *   bad segments, no retained sample; for TDA_PREC_GS also an excluded sample
- *   inside a segment or a segment longer than 32768), ENOMEM, ENODEV, EHIP.
+ *   inside a segment or a segment longer than 65536), ENOMEM, ENODEV, EHIP.
  * Synchronous: returns after assembly finished (GS handles assemble nothing).
  */
 tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t N, const uint8_t *gap_mask,

@@ -2162,13 +2162,15 @@ __device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64
   return ss;
 }
 
-// gs_sumsq for m = 8 hh, through the split transforms of the refinement.
-template <int LH>
+// gs_sumsq for transforms split in P = 2 halves (m = 8 hh) or P = 4 quarters (m = 16 hq,
+// with the workgroup's scratch S), through the drivers of the refinement.
+template <int LH, int P>
 __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd, int64_t b,
                                               const double2 *__restrict__ M, double2 *X,
-                                              double *__restrict__ tes) {
-  constexpr int h = 1 << LH, hh = h / 2;
-  constexpr int NI = hh / RL_THREADS;
+                                              double2 *S, double *__restrict__ tes) {
+  static_assert(P == 2 || P == 4, "halves or quarters");
+  constexpr int h = 1 << LH;
+  constexpr int NI = h / P / RL_THREADS;
   static_assert(NI % RL_CH == 0, "whole chunks");
   int t = opaque_tid();
   const double *__restrict__ hrow = gs_template_row(it, b) + sd.offset;
@@ -2189,14 +2191,14 @@ __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd,
       for (int c = 0; c < RL_CH; ++c)
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int jj = 4 * (t + RL_THREADS * (i0 + c)) + 2 * s + u;
+          const int jj = 2 * P * (t + RL_THREADS * (i0 + c)) + 2 * s + u;
           rv[c][u] = jj < len ? dd[jj] - hrow[jj] : 0.0;
         }
 #pragma unroll
       for (int c = 0; c < RL_CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 z = make_double2(rv[c][0], rv[c][1]);
-        X[lpad(n)] = odd ? cmul(z, wm(4 * n + 2 * s)) : z;
+        X[lpad(n)] = odd ? cmul(z, wm(2 * P * n + 2 * s)) : z;
       }
     }
     __syncthreads();
@@ -2207,7 +2209,7 @@ __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd,
   auto emit = [&](int s, bool odd) {
     t = opaque_tid();
     for (int i = 0; i < NI; ++i) {
-      const int n = t + RL_THREADS * i, j0 = 4 * n + 2 * s;
+      const int n = t + RL_THREADS * i, j0 = 2 * P * n + 2 * s;
       if (j0 >= len) continue;
       if (!odd) {
         const double2 g = X[lpad(n)];
@@ -2224,7 +2226,10 @@ __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd,
       }
     }
   };
-  rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
+  if constexpr (P == 2)
+    rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
+  else
+    rl_quad_parts<LH>(X, S, tw, ptw, stage, mult, emit);
   return ss;
 }
 
@@ -2236,13 +2241,17 @@ __device__ __forceinline__ void gs_segment(const GsItem &it, const GsSeg &sd, in
   qacc += (s1 - s2) * sd.inv_x0;
 }
 
+// Per-workgroup scratch of `stride` doubles: the parked even part, then (qoff >= 0) the
+// quarters of transforms split in four.
 __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ items,
                                                    const int2 *__restrict__ work, int64_t n_work,
-                                                   double *__restrict__ scratch, int64_t stride) {
+                                                   double *__restrict__ scratch, int64_t stride,
+                                                   int64_t qoff) {
   extern __shared__ double2 rl_smem[];
   double2 *X = rl_smem;
   double *red = (double *)(rl_smem + RL_XN);
   double *tes = scratch + (int64_t)blockIdx.x * stride;
+  double2 *S = qoff >= 0 ? (double2 *)(tes + qoff) : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
     const GsItem &it = items[wk.x];
@@ -2258,8 +2267,22 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
         TDA_GS(10) TDA_GS(11) TDA_GS(12) TDA_GS(13)
 #undef TDA_GS
         case RL_LHMAX + 1: {
-          const double s1 = gs_sumsq_split<RL_LHMAX + 1>(it, sd, b, (const double2 *)sd.M1, X, tes);
-          const double s2 = gs_sumsq_split<RL_LHMAX + 1>(it, sd, b, (const double2 *)sd.M2, X, tes);
+          const double s1 =
+              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, (const double2 *)sd.M1, X, nullptr, tes);
+          const double s2 =
+              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, (const double2 *)sd.M2, X, nullptr, tes);
+          qp += (s1 - s2) * sd.inv_x0;
+          break;
+        }
+        case RL_LHMAX + 2: {
+          if (!S) {
+            bad = true;
+            break;
+          }
+          const double s1 =
+              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, (const double2 *)sd.M1, X, S, tes);
+          const double s2 =
+              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, (const double2 *)sd.M2, X, S, tes);
           qp += (s1 - s2) * sd.inv_x0;
           break;
         }
@@ -2272,11 +2295,11 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
 }
 
 hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
-                     int64_t scratch_stride, int32_t n_wg, hipStream_t s) {
+                     int64_t scratch_stride, int64_t qoff, int32_t n_wg, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   const int64_t g = std::min<int64_t>(n_work, n_wg);
   hipLaunchKernelGGL(k_gs, dim3((unsigned)g), dim3(RL_THREADS), RL_LDS_BYTES, s, items, work, n_work,
-                     scratch, scratch_stride);
+                     scratch, scratch_stride, qoff);
   return hipGetLastError();
 }
 

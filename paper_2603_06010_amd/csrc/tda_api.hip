@@ -615,6 +615,25 @@ static tda_status build_gs(tda_ctx *h) {
 
 constexpr int32_t kGsWG = 1024;  // persistent Gohberg-Semencul workgroups (one per CU runs at once)
 
+// Per-workgroup Gohberg-Semencul scratch: the parked even part (max_len doubles, rounded
+// to an even count) and, when a segment's transforms split in quarters, their quarters;
+// fewer workgroups then.
+struct GsScratch {
+  int32_t n_wg;
+  int64_t stride, qoff;
+  size_t bytes;
+};
+static GsScratch gs_scratch_plan(int64_t n_work, int64_t max_len, int64_t max_m) {
+  const bool quad = max_m > RL_MAX_M_SPLIT;
+  GsScratch g;
+  g.n_wg = (int32_t)std::min<int64_t>(n_work, quad ? RL_QUAD_WG : kGsWG);
+  const int64_t tes = (max_len + 1) & ~(int64_t)1;
+  g.qoff = quad ? tes : -1;
+  g.stride = tes + (quad ? 2 * RL_QUAD_SCRATCH : 0);
+  g.bytes = (size_t)g.n_wg * g.stride * sizeof(double);
+  return g;
+}
+
 static GsItem make_gs_item(const tda_ctx *h, const double *d, const double *H, int64_t ldh,
                            int64_t B, double *out) {
   GsItem it{};
@@ -631,8 +650,8 @@ static GsItem make_gs_item(const tda_ctx *h, const double *d, const double *H, i
 
 static tda_status loglik_gs(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
                             double *out, hipStream_t s) {
-  const int32_t n_wg = (int32_t)std::min<int64_t>(B, kGsWG);
-  TDA_TRY(h->alloc(h->ws_fft, (size_t)n_wg * h->gs_max_len * sizeof(double)));
+  const GsScratch gsc = gs_scratch_plan(B, h->gs_max_len, h->max_m);
+  TDA_TRY(h->alloc(h->ws_fft, gsc.bytes));
   const GsItem it = make_gs_item(h, d, H, ldh, B, out);
   std::vector<int2> work((size_t)B);
   for (int64_t b = 0; b < B; ++b) work[b] = int2{0, (int32_t)b};
@@ -643,7 +662,7 @@ static tda_status loglik_gs(tda_ctx *h, const double *d, const double *H, int64_
   {
     TimedScope ts("gs_fft", s);
     HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, B, (double *)h->ws_fft.p,
-                      h->gs_max_len, n_wg, s));
+                      gsc.stride, gsc.qoff, gsc.n_wg, s));
   }
   HIP_TRY(h->ring.seal(s));
   return TDA_OK;
@@ -1453,16 +1472,17 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
   if (precision == TDA_PREC_GS) {
     std::vector<GsItem> gis(n_items);
     std::vector<int2> work;
-    int64_t max_len = 0;
+    int64_t max_len = 0, max_m = 0;
     for (int64_t k = 0; k < n_items; ++k) {
       const tda_work &w = items[k];
       gis[k] = make_gs_item(w.h, w.d, w.H, w.ldh, w.B, partbuf + part_off[k]);
       gis[k].Hrows = hrows ? hrows[k] : nullptr;
       max_len = std::max(max_len, w.h->gs_max_len);
+      max_m = std::max(max_m, w.h->max_m);
       for (int64_t b = 0; b < w.B; ++b) work.push_back(int2{(int32_t)k, (int32_t)b});
     }
-    const int32_t n_wg = (int32_t)std::min<int64_t>((int64_t)work.size(), kGsWG);
-    TDA_TRY(P.alloc(P.ws_fft, (size_t)n_wg * max_len * sizeof(double)));
+    const GsScratch gsc = gs_scratch_plan((int64_t)work.size(), max_len, max_m);
+    TDA_TRY(P.alloc(P.ws_fft, gsc.bytes));
     HIP_TRY(mc->ring.reserve(4096 + gis.size() * sizeof(GsItem) + work.size() * sizeof(int2) +
                              n_items * 16 + group_out.size() * 16));
     void *d_it, *d_w;
@@ -1470,7 +1490,7 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
     HIP_TRY(mc->ring.push(work.data(), work.size() * sizeof(int2), s, &d_w));
     TimedScope ts("gs_fft", s);
     HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, (int64_t)work.size(),
-                      (double *)P.ws_fft.p, max_len, n_wg, s));
+                      (double *)P.ws_fft.p, gsc.stride, gsc.qoff, gsc.n_wg, s));
   } else if (precision == TDA_PREC_FP64) {
     std::vector<TrsmItem> its(n_items);
     std::vector<TrsmTile> tiles;

@@ -293,16 +293,19 @@ __device__ __forceinline__ const double *gs_template_row(const GsItem &it, int64
 // E_k <= 0 or not finite (else -1).  One workgroup; n <= GS_MAX_LEN, with the
 // coefficients in LDS up to RL_MAX_LEV and in x (global memory) beyond.
 constexpr int RL_MAX_LEV = 16384;
-// Longest Gohberg-Semencul segment: its circulant (m >= 2 n) refines in LDS with split DFTs.
-constexpr int GS_MAX_LEN = (int)(RL_MAX_M_SPLIT / 2);
+// Longest Gohberg-Semencul segment: its circulant (m >= 2 n) runs through the in-LDS
+// transforms split in quarters.
+constexpr int GS_MAX_LEN = (int)(RL_MAX_M_QUAD / 2);
 hipError_t launch_levinson(const double *acf, int64_t n, double *x, double *logdet,
                            int32_t *fail, hipStream_t s);
 // conj(DFT_m) of x zero-padded and of (0, x_{n-1}, ..., x_1) zero-padded
 hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double *tw,
                              double *M1, double *M2, hipStream_t s);
-// q_b over the segments of each item, out[b] = -q_b/2 + cterm; work entries (item, b)
+// q_b over the segments of each item, out[b] = -q_b/2 + cterm; work entries (item, b).
+// Workgroup g uses scratch + g scratch_stride doubles: the parked even part, and from qoff
+// (even; -1 = none) RL_QUAD_SCRATCH complex doubles for segments with m > RL_MAX_M_SPLIT.
 hipError_t launch_gs(const GsItem *items, const int2 *work, int64_t n_work, double *scratch,
-                     int64_t scratch_stride, int32_t n_wg, hipStream_t s);
+                     int64_t scratch_stride, int64_t qoff, int32_t n_wg, hipStream_t s);
 
 // In-LDS refinement for launches whose segments all have m <= RL_MAX_M_QUAD; work entries
 // (item, template).  qscratch: RL_QUAD_WG x RL_QUAD_SCRATCH complex doubles when a segment

@@ -52,10 +52,13 @@ def test_gs_parity(tda, N, B, segments, eps):
     h.close()
 
 
-# Segments of 16385 .. 32768 samples: Levinson with its coefficients in global memory and
-# the correlations through split DFTs (m = 65536); one case mixes them with a short segment.
+# Segments of 16385 .. 65536 samples: Levinson with its coefficients in global memory and
+# the correlations through DFTs split in halves (m = 65536) or quarters (m = 131072); one
+# case mixes halves with a short segment, one quarters with halves.
 @pytest.mark.parametrize("N,B,segments", [(20000, 40, None), (32768, 48, None),
-                                          (20000, 33, [(0, 17000), (17000, 3000)])])
+                                          (20000, 33, [(0, 17000), (17000, 3000)]),
+                                          (65536, 24, None),
+                                          (60000, 20, [(0, 40000), (40000, 20000)])])
 def test_gs_long_segments_ar1_closed_form(tda, N, B, segments):
     from gpu_util import to_dev
     from test_oracle_pins import ar1_acf, ar1_whiten_closed
@@ -80,7 +83,7 @@ def test_gs_long_segments_ar1_closed_form(tda, N, B, segments):
 
 def test_gs_long_segment_vs_fp64_and_limit(tda):
     """N = 20000 with the benchmark's ACF recipe: GS against the FP64 (Cholesky) path; a
-    segment one sample beyond the limit is refused."""
+    segment one sample beyond the limit (65536) is refused."""
     from gpu_util import to_dev
     inst = synth.random_rhs_case(77, 20000, 1, 0, 64, eps=1e-6)
     d, H = to_dev(inst.d[0]), to_dev(inst.H)
@@ -91,7 +94,7 @@ def test_gs_long_segment_vs_fp64_and_limit(tda):
     assert np.all(np.abs(got - ref) <= TOLGS(ref)), np.max(np.abs(got - ref))
     hg.close(); hf.close()
     with pytest.raises(tda.TdaError) as e:
-        tda.Handle(synth.make_acf(32769), 32769, None, precision="gs")
+        tda.Handle(synth.make_acf(65537), 65537, None, precision="gs")
     assert e.value.name == "TDA_EINVAL"
 
 
