@@ -121,8 +121,9 @@ def main():
     ap.add_argument("--core-only", action="store_true",
                     help="c2: only the batched mixed and FP64 evaluations (for profiling runs); "
                          "the Gohberg-Semencul, explicit-inverse, inner-product and ACF lines are null")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default): two detectors x N=16384, 4096 templates per launch; "
+                         "c3: one detector x N=32768 with 3 gaps, 8192 templates; "
                          "c4: 64 ragged instances in one batched evaluation; "
                          "c5: request server over 32 resident datasets")
     ap.add_argument("--duration", type=float, default=4.0, help="c5: seconds of request trace")
@@ -148,6 +149,8 @@ def main():
     tda.load_library()
     dev = torch.device("cuda", 0)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.workload == "c3":
+        return bench_c3(args, tda, torch, synth, dev, log)
     if args.workload == "c4":
         return bench_c4(args, tda, torch, synth, dev, log)
     if args.workload == "c5":
@@ -387,6 +390,54 @@ def _base_line(args, value, unit, wall, steps, config, dtype):
             "warmup": args.warmup, "ms_per_step": wall / max(steps, 1) * 1e3,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
             "data": "synthetic", "config": config}
+
+
+def bench_c3(args, tda, torch, synth, dev, log):
+    """One detector, N = 32768 with 3 gaps (the masked covariance C[mask, mask], one
+    segment whose circulant refines with split transforms), 8192 templates per launch:
+    mixed and FP64 evaluations through the same handle."""
+    t0 = time.perf_counter()
+    w = synth.c3_workload()
+    inst = w.instances[0]
+    log(f"c3 inputs in {time.perf_counter() - t0:.1f} s")
+    d = torch.from_numpy(inst.d[0]).to(dev)
+    H = torch.from_numpy(inst.H).to(dev)
+    t0 = time.perf_counter()
+    h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision="mixed").factor()
+    h.set_data(d)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log(f"c3 setup {setup:.1f} s, n_eff {h.info()['n_eff']}")
+    res = {}
+    for p in ("mixed", "fp64"):
+        out = torch.empty(inst.B, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            h.loglik(d, H, out=out, precision=p)
+        torch.cuda.synchronize()
+        tda.timing_read(reset=True)
+        tda.timing_enable(True)
+        steps = args.steps if p == "mixed" else max(2, args.steps // 4)
+        t = time.perf_counter()
+        for _ in range(steps):
+            h.loglik(d, H, out=out, precision=p)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        tda.timing_enable(False)
+        res[p] = (wall, steps, tda.timing_read(reset=True), out.cpu().numpy())
+        log(f"c3 {p}: {wall / steps * 1e3:.2f} ms/step")
+    h.close()
+    wall, steps, kt, rm = res["mixed"]
+    line = _base_line(args, inst.B * steps / wall, "evals/s", wall, steps,
+                      {"workload": f"one detector x N={inst.N} with 3 gaps (64-512 samples), "
+                                   f"{inst.B} chirp templates per launch"},
+                      "bf16x3+f64")
+    fw, fs, _, rf = res["fp64"]
+    line["fp64"] = {"value": inst.B * fs / fw, "unit": "evals/s", "ms_per_step": fw / fs * 1e3}
+    line["speedup_mixed_vs_fp64"] = line["value"] / line["fp64"]["value"]
+    line["accuracy"] = {"max_abs_dlogL_mixed_vs_fp64_gpu": float(np.abs(rm - rf).max())}
+    line["kernels_ms"] = {k: v[1] / v[0] for k, v in kt.items()}
+    line["setup_s"] = setup
+    print(json.dumps(line), flush=True)
 
 
 def bench_c4(args, tda, torch, synth, dev, log):
