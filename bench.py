@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "logL evals/s @N=16384, mixed vs FP64 at |ΔlogL|≤1e-3; p50/p99 latency"
 PEAK_BF16 = 2.5e15       # dense BF16 matrix-core peak, FLOP/s
 PEAK_FP64 = 78.6e12      # FP64 matrix-core peak, FLOP/s
+PEAK_HBM = 8.0e12        # HBM3E bandwidth, bytes/s
 
 
 # HBM traffic of a kernel comes from rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE,
@@ -236,7 +237,7 @@ def main():
         for h in hg:
             h.close()
 
-    acf_line = cdo = snr_terms = None
+    acf_line = cdo = snr_terms = wres = None
     if not args.core_only:
         # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
         # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
@@ -312,6 +313,31 @@ def main():
         log("snr terms", snr_terms)
         del terms_m, terms_f
 
+        # whitened residuals (tda_whitened_residual) of one detector: the FP64 solve plus the
+        # export of L^-1 (d - h) for every template; the export kernel against the HBM peak
+        wsteps = 3
+        out_w, W = hs[0].whitened_residual(d[0], H)
+        torch.cuda.synchronize()
+        tda.timing_read(reset=True)
+        tda.timing_enable(True)
+        t = time.perf_counter()
+        for _ in range(wsteps):
+            out_w, W = hs[0].whitened_residual(d[0], H)
+        torch.cuda.synchronize()
+        wall_w = time.perf_counter() - t
+        tda.timing_enable(False)
+        kt_w = tda.timing_read(reset=True)
+        ref_w = hs[0].loglik(d[0], H, precision="fp64")
+        exp_ms = kt_w["whiten_export"][1] / kt_w["whiten_export"][0]
+        exp_bytes = 16.0 * W.shape[0] * W.shape[1]  # 8 B read and 8 B written per entry
+        wres = {"ms_per_call": wall_w / wsteps * 1e3, "templates": int(W.shape[0]),
+                "n_eff": int(W.shape[1]), "export_ms": exp_ms,
+                "export_GB_per_s": exp_bytes / exp_ms / 1e6,
+                "export_frac_of_hbm_peak": exp_bytes / exp_ms / 1e-3 / PEAK_HBM,
+                "logL_identical_to_fp64": bool(torch.equal(out_w, ref_w))}
+        log("whitened residuals", wres)
+        del W, out_w, ref_w
+
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
 
@@ -358,6 +384,7 @@ def main():
         "cdo_fp64": cdo,
         "acf_estimate": acf_line,
         "snr_terms": snr_terms,
+        "whitened_residual": wres,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
                      "templates_compared": int(inst.B)},
