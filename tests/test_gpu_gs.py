@@ -81,6 +81,34 @@ def test_gs_long_segments_ar1_closed_form(tda, N, B, segments):
     h.close()
 
 
+def test_gs_multi_mixed_lengths(tda):
+    """One batched call over items whose transforms stay whole, split in halves and split
+    in quarters (the workgroup scratch is planned for the longest), each item against the
+    AR(1) closed form."""
+    from gpu_util import to_dev
+    from test_oracle_pins import ar1_acf, ar1_whiten_closed
+    import torch
+    s, phi = 0.8, 0.97
+    items, wants, outs, keep = [], [], [], []
+    for k, (N, B) in enumerate([(3000, 20), (40000, 12), (20000, 16), (5000, 9)]):
+        rng = np.random.default_rng(300 + k)
+        d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
+        w = ar1_whiten_closed(d[None] - H, s, phi)
+        ld = np.log(s * s / (1 - phi * phi)) + (N - 1) * np.log(s * s)
+        wants.append(-0.5 * (w * w).sum(1) - 0.5 * ld - 0.5 * N * np.log(2 * np.pi))
+        h = tda.Handle(ar1_acf(N, s, phi), N, None, precision="gs").factor()
+        out = torch.empty(B, dtype=torch.float64, device="cuda")
+        dd, Hd = to_dev(d), to_dev(H)
+        items.append((h, dd, Hd, out)); outs.append(out); keep.append((h, dd, Hd))
+    tda.loglik_multi(items, precision="gs")
+    torch.cuda.synchronize()
+    for out, want in zip(outs, wants):
+        got = out.cpu().numpy()
+        assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+    for h, _, _ in keep:
+        h.close()
+
+
 def test_gs_long_segment_vs_fp64_and_limit(tda):
     """N = 20000 with the benchmark's ACF recipe: GS against the FP64 (Cholesky) path; a
     segment one sample beyond the limit (65536) is refused."""

@@ -231,6 +231,35 @@ def test_multi_ragged_instances(tda, precision):
             _check_mixed(got, want)
 
 
+def test_multi_long_segments(tda):
+    """One batched mixed call over items whose refinement transforms stay whole, split in
+    halves and split in quarters (scratch planned for the longest), each item against the
+    gapped AR(1) closed form."""
+    from gpu_util import to_dev
+    from test_oracle_pins import ar1_acf
+    import torch
+    s, phi = 0.8, 0.97
+    items, wants, outs, keep = [], [], [], []
+    for k, (N, n_gaps, B) in enumerate([(3000, 1, 20), (40000, 2, 12), (20000, 0, 16)]):
+        mask = synth.gap_mask_from(N, synth.draw_gaps(np.random.default_rng(400 + k), N, n_gaps))
+        kept = np.flatnonzero(mask == 0)
+        rng = np.random.default_rng(410 + k)
+        d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
+        wr, ld = _ar1_white_closed(d[None] - H, kept, s, phi)
+        wants.append(-0.5 * (wr * wr).sum(1) - 0.5 * ld - 0.5 * len(kept) * np.log(2 * np.pi))
+        h = tda.Handle(ar1_acf(N, s, phi), N, mask, precision="mixed").factor()
+        out = torch.empty(B, dtype=torch.float64, device="cuda")
+        dd, Hd = to_dev(d), to_dev(H)
+        items.append((h, dd, Hd, out)); outs.append(out); keep.append((h, dd, Hd))
+    tda.loglik_multi(items, precision="mixed")
+    torch.cuda.synchronize()
+    for out, want in zip(outs, wants):
+        err = out.cpu().numpy() - want
+        assert np.max(np.abs(err)) <= TOL_MIXED, np.max(np.abs(err))
+    for h, _, _ in keep:
+        h.close()
+
+
 def test_multi_matches_single(tda):
     from gpu_util import to_dev
     import torch
