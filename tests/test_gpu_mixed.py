@@ -332,6 +332,42 @@ def test_plan_graph_replay(tda, precision):
     plan.close()
 
 
+def test_plan_graph_replay_long_segments(tda):
+    """A captured mixed plan over items whose refinement splits its transforms in quarters
+    (workgroup scratch inside the graph) and in halves, replayed with eager work in
+    between: every replay matches the eager evaluation."""
+    from gpu_util import to_dev
+    import torch
+    specs = [(40000, 1, 24), (20000, 0, 16)]
+    hs, ds, Hs = [], [], []
+    for k, (N, n_gaps, B) in enumerate(specs):
+        inst = synth.random_rhs_case(700 + k, N, 1, n_gaps, B)
+        hs.append(tda.Handle(inst.acf, N, inst.masks[0], precision="mixed").factor())
+        ds.append(to_dev(inst.d[0])); Hs.append(to_dev(inst.H))
+    refs = [torch.empty(B, dtype=torch.float64, device="cuda") for _, _, B in specs]
+    tda.loglik_multi(list(zip(hs, ds, Hs, refs)), precision="mixed")
+    torch.cuda.synchronize()
+    wants = [r.cpu().numpy() for r in refs]
+    outs = [torch.empty(B, dtype=torch.float64, device="cuda") for _, _, B in specs]
+    plan = tda.Plan(list(zip(hs, ds, Hs, outs)), precision="mixed")
+    stream = torch.cuda.Stream()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.execute(stream=stream, graph=True)
+        stream.synchronize()
+        for o, want in zip(outs, wants):
+            np.testing.assert_allclose(o.cpu().numpy(), want, rtol=0, atol=1e-8)
+        other = torch.empty(specs[0][2], dtype=torch.float64, device="cuda")
+        tda.loglik_multi([(hs[0], ds[0], Hs[0], other)], precision="mixed")
+        torch.cuda.synchronize()
+    plan.close()
+    for h in hs:
+        h.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_scale_invariance(tda, precision):
     """acf -> s acf with d, H -> sqrt(s) (d, H) leaves the quadratic form unchanged and
