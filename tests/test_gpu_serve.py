@@ -128,3 +128,37 @@ def test_server_fp64(env):
         want = ds[k]["want"][:50]
         assert np.all(np.abs(outs[k].cpu().numpy() - want) <= 1e-6 + 2e-9 * np.abs(want))
     srv.close()
+
+
+def test_server_long_datasets(env):
+    """Served requests against datasets whose refinement splits its transforms in halves
+    (N = 20000) and in quarters (N = 40000), mixed with a short one, against the gapped
+    AR(1) closed form."""
+    from gpu_util import to_dev
+    from test_oracle_pins import ar1_acf
+    from test_gpu_mixed import _ar1_white_closed
+    tda, short = env
+    s, phi = 0.8, 0.97
+    ds = [short[0]]
+    for k, (N, n_gaps) in enumerate([(20000, 1), (40000, 2)]):
+        mask = synth.gap_mask_from(N, synth.draw_gaps(np.random.default_rng(800 + k), N, n_gaps))
+        kept = np.flatnonzero(mask == 0)
+        rng = np.random.default_rng(810 + k)
+        d = rng.standard_normal(N); H = rng.standard_normal((96, N)) * 0.3
+        wr, ld = _ar1_white_closed(d[None] - H, kept, s, phi)
+        want = -0.5 * (wr * wr).sum(1) - 0.5 * ld - 0.5 * len(kept) * np.log(2 * np.pi)
+        h = tda.Handle(ar1_acf(N, s, phi), N, mask, precision="mixed").factor()
+        ds.append(dict(h=h, d=to_dev(d), H=to_dev(H), want=want))
+    rng = np.random.default_rng(9)
+    reqs = []
+    for _ in range(40):
+        k = int(rng.integers(0, len(ds)))
+        c = int(rng.integers(1, 65))
+        reqs.append((k, int(rng.integers(0, 96 - c + 1)), c))
+    res, st = _serve(tda, ds, reqs, n_slots=2, threads=4)
+    assert st["completed"] == len(reqs)
+    for (k, r0, c), got in zip(reqs, res):
+        err = got - ds[k]["want"][r0:r0 + c]
+        assert np.max(np.abs(err)) <= 1e-3, (k, np.max(np.abs(err)))
+    for x in ds[1:]:
+        x["h"].close()
