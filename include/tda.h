@@ -32,7 +32,11 @@
  *                     uses an FP64 FFT Toeplitz product (eq:toeplitz_fft).
  *                     The refined quadratic form is never larger than the
  *                     exact one (variational bound) and its error is
- *                     quadratic in the BF16 product error.
+ *                     quadratic in the BF16 product error.  Its FP64 FFT
+ *                     product rounds at about u lambda_max ||C^-1 h||^2, which
+ *                     keeps |dlogL| <= 1e-3 up to kappa(C) of about 3e7 on the
+ *                     benchmark inputs and exceeds it from about 1e8; beyond
+ *                     that use TDA_PREC_FP64.
  *   TDA_PREC_GS    -- FP64 evaluation through the Gohberg-Semencul form of the
  *                     Toeplitz inverse (Sec. III.A.3): x = C^-1 e_1 and log det C
  *                     by Levinson-Durbin once per segment, then per template
@@ -91,8 +95,11 @@ typedef enum { TDA_PREC_FP64 = 0, TDA_PREC_MIXED = 1, TDA_PREC_GS = 2, TDA_PREC_
 /* TDA_FLAG_COMPACT (mixed handles): once tda_set_data has cached the whitened
  * data, release the FP64 solve panels and the FP64 whitening operator, keeping
  * only the BF16 hi/lo operator copies (2 N_eff^2 bytes each for W and W^T) and
- * the cached data.  Afterwards FP64 evaluation and tda_set_data with other data
- * return TDA_ESTATE.  For large resident datasets (serving). */
+ * the cached data.  Afterwards FP64 and explicit-inverse evaluation, tda_set_data,
+ * and evaluations that pass another data pointer return TDA_ESTATE; if the cached
+ * data vector's retained samples change in place, the handle cannot whiten them
+ * again and every result (logL and <d,h>) comes back NaN until the original
+ * values are restored.  For large resident datasets (serving). */
 enum { TDA_FLAG_COMPACT = 1 };
 
 /* Half-open sample range [offset, offset + length) of the N-sample series. */
@@ -101,12 +108,30 @@ typedef struct {
   int64_t length;
 } tda_segment;
 
+/* Device-memory provider for a handle's buffers (covariance blocks, factor, operator
+ * copies, cached data, workspaces), so that the caller's allocator owns that memory
+ * (e.g. PyTorch's caching allocator).
+ *   alloc(bytes, ctx) returns device memory of the handle's device, at least 256-byte
+ *     aligned, or NULL (the call then fails with TDA_ENOMEM);
+ *   free(ptr, ctx) releases a pointer returned by alloc.  The library calls it only
+ *     after the work that used the buffer has finished (it synchronises first).
+ * Both are called on the thread that makes the library call.  The struct is copied by
+ * tda_cov_build; the functions and ctx must stay valid until tda_destroy returns.
+ * Per-call descriptor rings and pinned staging (a few hundred KB) still come from
+ * hipMalloc / hipHostMalloc. */
 typedef struct {
-  uint32_t struct_size;   /* sizeof(tda_options) */
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} tda_allocator;
+
+typedef struct {
+  uint32_t struct_size;   /* sizeof(tda_options); the size without `allocator` is accepted */
   int32_t precision;      /* tda_precision */
   int32_t device;         /* HIP device ordinal; -1 = current device */
   int32_t flags;          /* TDA_FLAG_* bits; 0 = default */
   size_t hbm_budget_bytes;/* cap on this handle's device memory; 0 = none */
+  const tda_allocator *allocator; /* NULL: hipMalloc / hipFree */
 } tda_options;
 
 typedef struct {
@@ -166,17 +191,22 @@ tda_status tda_factor(tda_handle h);
  * (Sec. III.A: cache L and the whitened data once).  d is device
  * float64[N]; only retained samples are read.  FP64 handles accept and
  * ignore the call.  Enqueued on hip_stream (NULL = default stream).
- * Errors: ESTATE (not factored), EINVAL.
+ * The cache is keyed by a fingerprint of d's retained samples (a 64-bit sum of
+ * mixed sample bits and positions, computed on the device): every mixed
+ * evaluation recomputes it (O(N)) and re-whitens only when it differs, so
+ * calling this first is optional; it forces the whitening now (and, with
+ * TDA_FLAG_COMPACT, releases the FP64 operator afterwards, synchronously).
+ * Errors: ESTATE (not factored; compact handle already compacted), EINVAL.
  */
 tda_status tda_set_data(tda_handle h, const double *d, void *hip_stream);
 
 /*
  * tda_loglik -- logL for B templates against one detector, constants
  * included (eq:td_like_whitened plus -1/2 log det C - N_eff/2 log 2 pi).
- *   d    device float64[N]: data.  Mixed handles use the whitened data
- *        cached by the last tda_set_data; if d differs from the pointer
- *        given there (or none was given), tda_set_data(h, d) runs first.
- *        After changing d's contents in place, call tda_set_data again.
+ *   d    device float64[N]: data.  Mixed handles use their cached whitened
+ *        data when the fingerprint of d's retained samples matches the cached
+ *        one (new contents, in place or at another address, are re-whitened
+ *        within the call, at O(N_eff^2) cost; see tda_set_data).
  *   H    device float64, B rows of length >= N, row stride ldh (>= N).
  *   out  device float64[B], written (not accumulated).
  *   B = 0 is a no-op.  NaN/Inf in a template affects only its own out[b].
@@ -215,6 +245,23 @@ tda_status tda_loglik_ex(tda_handle h, const double *d, const double *H, int64_t
 tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int64_t B,
                             int64_t ldh, double *out, double *out_dh, double *out_hh,
                             int32_t precision, void *hip_stream);
+
+/*
+ * tda_snr -- logL and the paper's time-domain SNRs per template (Sec. II.B item 7),
+ * finished on the device from the two inner products of tda_loglik_terms:
+ *   out[b]      = logL, exactly as tda_loglik_terms computes it,
+ *   rho_mf[b]   = <d,h_b> / sqrt(<h_b,h_b>)    (matched-filter SNR),
+ *   rho_opt[b]  = sqrt(<h_b,h_b>)               (optimal SNR),
+ *   rho_eff2[b] = <d,d> - <r_b,r_b> = 2 <d,h_b> - <h_b,h_b>, r_b = d - h_b
+ *                 (squared effective SNR),
+ * each device float64[B], distinct; any of the three may be NULL (not written).
+ * A zero template gives rho_mf = NaN (0/0), rho_opt = 0 and rho_eff2 = 0.  Cost as
+ * tda_loglik_terms with both inner products requested, plus one O(B) kernel.
+ * Errors and asynchrony as tda_loglik_ex.
+ */
+tda_status tda_snr(tda_handle h, const double *d, const double *H, int64_t B, int64_t ldh,
+                   double *out, double *rho_mf, double *rho_opt, double *rho_eff2,
+                   int32_t precision, void *hip_stream);
 
 /*
  * tda_whitened_residual -- the whitened residual of every template, the vector
@@ -297,9 +344,10 @@ tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, int32_t prec
  * into a HIP graph on that stream and every call launches the graph (one
  * submission per step, no allocation, no descriptor upload).  Once captured, a
  * plan always replays its graph.  Results overwrite the items' outputs as in
- * tda_loglik_multi.  Calls on one plan must be serialised by the caller.  The
- * graph also captures each handle's cached whitened data: after tda_set_data
- * with another vector on a handle of the plan, destroy and re-create the plan.
+ * tda_loglik_multi.  Calls on one plan must be serialised by the caller.  Each
+ * replay re-checks the fingerprint of every mixed item's data, so changed data
+ * (in place, or after tda_set_data with another vector on a handle of the plan)
+ * is re-whitened inside the replay.
  * tda_loglik, tda_loglik_ex and tda_loglik_multi refuse a capturing stream
  * (TDA_ESTATE); plans are the way to put an evaluation into a graph.
  */

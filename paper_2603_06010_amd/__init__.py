@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtda.so")
 PREC_FP64, PREC_MIXED, PREC_GS, PREC_CDO = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-    "tda_loglik_terms", "tda_whitened_residual", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
+    "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
@@ -43,10 +44,45 @@ class _Segment(ctypes.Structure):
     _fields_ = [("offset", ctypes.c_int64), ("length", ctypes.c_int64)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("hbm_budget_bytes", ctypes.c_size_t),
+                ("allocator", ctypes.POINTER(_Allocator))]
+
+
+class _TorchAllocator:
+    """tda_allocator backed by PyTorch's caching allocator on one device, so the handle's
+    device memory is owned (and counted) by torch."""
+
+    def __init__(self, device: int):
+        import torch
+        self.device = int(device)
+
+        def _alloc(nbytes, _ctx):
+            # the library calls this with the handle's device current
+            try:
+                dev = self.device if self.device >= 0 else torch.cuda.current_device()
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev)
+            except Exception:  # out of memory: the library reports TDA_ENOMEM
+                return None
+
+        def _free(ptr, _ctx):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self._fns = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+        self.struct = _Allocator(self._fns[0], self._fns[1], None)
 
 
 class _Info(ctypes.Structure):
@@ -86,6 +122,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_loglik.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
     L.tda_loglik_terms.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, i32, vp]
+    L.tda_snr.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, i32, vp]
     L.tda_whitened_residual.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
     L.tda_acf_estimate.argtypes = [vp, i64, i64, i32, i64, vp, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
@@ -98,7 +135,8 @@ def load_library(path: str = LIB_PATH):
     L.tda_timing_enable.argtypes = [i32]
     L.tda_timing_read.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
-              "tda_loglik_terms", "tda_whitened_residual", "tda_acf_estimate", "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
+              "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
+              "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
               "tda_timing_read"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -140,12 +178,21 @@ class Handle:
 
     acf: float64[>= longest segment]; N: samples; gap_mask: uint8[N] (1 = excluded) or None;
     segments: [(offset, length), ...] or None for one segment [0, N).
+    allocator: "torch" (default) passes PyTorch's caching allocator as the handle's
+    tda_allocator, so torch owns and counts its device memory; "hip" lets the library
+    call hipMalloc itself.
     """
 
     def __init__(self, acf, N: int, gap_mask=None, segments: Optional[Sequence] = None,
                  precision="fp64", device: int = -1, hbm_budget: int = 0,
-                 compact: bool = False):
+                 compact: bool = False, allocator: str = "torch"):
         L = load_library()
+        self._h = ctypes.c_void_p()
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = _TorchAllocator(device)
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
         acf = np.ascontiguousarray(acf, dtype=np.float64)
         self._acf = acf
         mask_ptr = None
@@ -160,7 +207,8 @@ class Handle:
             nseg = len(segments)
             seg_arr = (_Segment * max(nseg, 1))(*[_Segment(int(o), int(l)) for o, l in segments])
         opt = _Options(ctypes.sizeof(_Options), _precision(precision), int(device),
-                       1 if compact else 0, int(hbm_budget))
+                       1 if compact else 0, int(hbm_budget),
+                       ctypes.pointer(self._alloc.struct) if self._alloc else None)
         h = ctypes.c_void_p()
         _check(L.tda_cov_build(acf.ctypes.data, len(acf), int(N), mask_ptr,
                                ctypes.cast(seg_arr, ctypes.c_void_p) if seg_arr is not None else None,
@@ -236,12 +284,22 @@ class Handle:
         return out, W
 
     def snr(self, d, H, precision=None, stream=None):
-        """Time-domain SNRs per template (Sec. II.B item 7): rho_mf = <d,h>/sqrt(<h,h>),
-        rho_opt = sqrt(<h,h>) and rho_eff^2 = <d,d> - <r,r> = 2 <d,h> - <h,h>."""
+        """Time-domain SNRs per template (Sec. II.B item 7) through tda_snr, computed in
+        the library: {"loglik", "rho_mf" = <d,h>/sqrt(<h,h>), "rho_opt" = sqrt(<h,h>),
+        "rho_eff2" = <d,d> - <r,r>}."""
         import torch
-        _, dh, hh = self.loglik_terms(d, H, precision=precision, stream=stream)
-        return {"rho_mf": dh / torch.sqrt(hh), "rho_opt": torch.sqrt(hh),
-                "rho_eff2": 2.0 * dh - hh, "dh": dh, "hh": hh}
+        if H.dim() != 2:
+            raise ValueError("H must be 2-D")
+        if H.stride(1) != 1:
+            raise ValueError("H rows must be contiguous")
+        B = H.shape[0]
+        mk = lambda: torch.empty(B, dtype=torch.float64, device=H.device)
+        out, mf, opt, eff2 = mk(), mk(), mk(), mk()
+        if B:
+            p = self.precision if precision is None else _precision(precision)
+            _check(_lib.tda_snr(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), _ptr(mf),
+                                _ptr(opt), _ptr(eff2), p, _stream(stream)))
+        return {"loglik": out, "rho_mf": mf, "rho_opt": opt, "rho_eff2": eff2}
 
     def info(self) -> dict:
         i = _Info()

@@ -698,4 +698,27 @@ hipError_t launch_terms_combine(const double *out, double *hh, const double *dd,
   return hipGetLastError();
 }
 
+// Time-domain SNRs from the two inner products (Sec. II.B item 7): the matched-filter
+// rho_mf = <d,h> / sqrt(<h,h>), the optimal rho_opt = sqrt(<h,h>) and the effective
+// rho_eff^2 = <d,d> - <d-h,d-h>, which expands to 2 <d,h> - <h,h>.
+__global__ void k_snr(const double *__restrict__ dh, const double *__restrict__ hh, int64_t B,
+                      double *__restrict__ rho_mf, double *__restrict__ rho_opt,
+                      double *__restrict__ rho_eff2) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const double a = dh[b], c = hh[b];
+  const double r = sqrt(c);
+  if (rho_mf) rho_mf[b] = a / r;
+  if (rho_opt) rho_opt[b] = r;
+  if (rho_eff2) rho_eff2[b] = 2.0 * a - c;
+}
+
+hipError_t launch_snr(const double *dh, const double *hh, int64_t B, double *rho_mf,
+                      double *rho_opt, double *rho_eff2, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_snr, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, dh, hh, B, rho_mf,
+                     rho_opt, rho_eff2);
+  return hipGetLastError();
+}
+
 }  // namespace tda

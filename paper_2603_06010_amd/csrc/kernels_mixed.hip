@@ -111,11 +111,63 @@ hipError_t launch_split_w(const double *w64, const int64_t *w64_off, const int32
 
 // ---------------------------------------------------------------- whitened data (FP64)
 // dbar = W d on retained rows, y_d = W^T dbar = C^-1 d, q_dd = dbar^T dbar (Sec. III.A:
-// the whitened data vector is computed once and cached).
+// the whitened data vector is computed once and cached).  The cache is keyed by a
+// fingerprint of the retained samples of d, taken on the device by every evaluation
+// (k_data_check): the three whitening kernels run only when it differs from the cached
+// one (chk->stale), so an in-place update of d, or new data at the cached address, is
+// picked up without a host round trip.
+
+// splitmix64 finaliser (Steele, Lea and Flood, OOPSLA 2014): a bijective 64-bit mixer.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// One workgroup.  fp = sum over retained rows r of mix64(bits(d[idx[r]]) + mix64(r)) mod
+// 2^64 (order-free, so reproducible).  Then: equal to the cached fingerprint -> not stale,
+// chk->qdd = the cached q_dd; else, if the handle can whiten (its FP64 operator is held)
+// -> stale (the whitening kernels recompute and k_qdd_and_scatter stores the fingerprint);
+// else (compact handle) -> not stale and chk->qdd = NaN, so every result of the call is NaN.
+__global__ __launch_bounds__(1024) void k_data_check(const double *__restrict__ d,
+                                                     const int32_t *__restrict__ idx,
+                                                     int32_t n_pad, DataCache *__restrict__ cache,
+                                                     DataCheck *__restrict__ chk,
+                                                     int32_t can_whiten, int32_t force) {
+  __shared__ uint64_t part[1024];
+  uint64_t acc = 0;
+  for (int32_t r = threadIdx.x; r < n_pad; r += 1024) {
+    const int32_t p = idx[r];
+    if (p < 0) continue;
+    acc += mix64((uint64_t)__double_as_longlong(d[p]) + mix64((uint64_t)r));
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t fp = part[0];
+    chk->fp = fp;
+    const bool match = !force && cache->valid == 1 && cache->fp == fp;
+    if (match) {
+      chk->stale = 0;
+      chk->qdd = cache->qdd;
+    } else if (can_whiten) {
+      chk->stale = 1;
+    } else {
+      chk->stale = 0;
+      chk->qdd = __builtin_nan("");
+    }
+  }
+}
+
 __global__ void k_dbar(const double *__restrict__ w64, const int64_t *__restrict__ off,
                        const int32_t *__restrict__ rb, const int32_t *__restrict__ blk_first,
                        const int32_t *__restrict__ idx, const double *__restrict__ d,
-                       double *__restrict__ dbar) {
+                       double *__restrict__ dbar, const DataCheck *__restrict__ chk) {
+  if (!chk->stale) return;
   const int i = blockIdx.x;
   const int64_t r = (int64_t)i * TB + threadIdx.x;
   const int64_t c_beg = (int64_t)blk_first[i] * TB;
@@ -130,7 +182,9 @@ __global__ void k_dbar(const double *__restrict__ w64, const int64_t *__restrict
 
 __global__ void k_yd(const double *__restrict__ w64, const int64_t *__restrict__ off,
                      const int32_t *__restrict__ rb, const int32_t *__restrict__ blk_last,
-                     const double *__restrict__ dbar, double *__restrict__ yd) {
+                     const double *__restrict__ dbar, double *__restrict__ yd,
+                     const DataCheck *__restrict__ chk) {
+  if (!chk->stale) return;
   __shared__ double part[8][32];
   const int ct = blockIdx.x;
   const int cc = threadIdx.x & 31, g = threadIdx.x >> 5;
@@ -147,37 +201,54 @@ __global__ void k_yd(const double *__restrict__ w64, const int64_t *__restrict__
   }
 }
 
+// q_dd, and y_d scattered to sample positions (0 at excluded samples).  Every position is
+// written once with its final value, so a concurrent evaluation on another stream that
+// reads the cache never sees a transient value; the fingerprint is published last, after
+// a device-scope fence, so a reader that sees it also sees the values it keys.
 __global__ void k_qdd_and_scatter(const double *__restrict__ dbar, const double *__restrict__ yd,
-                                  const int32_t *__restrict__ idx, int32_t n_pad, int64_t N,
-                                  double *__restrict__ yd_pos, double *__restrict__ qdd) {
+                                  const int32_t *__restrict__ pos2row, int32_t n_pad, int64_t N,
+                                  double *__restrict__ yd_pos, DataCache *__restrict__ cache,
+                                  DataCheck *__restrict__ chk) {
+  if (!chk->stale) return;
   __shared__ double part[256];
-  for (int64_t j = threadIdx.x; j < N; j += 256) yd_pos[j] = 0.0;
-  __syncthreads();
-  double s = 0.0;
-  for (int64_t r = threadIdx.x; r < n_pad; r += 256) {
-    s += dbar[r] * dbar[r];
-    const int32_t p = idx[r];
-    if (p >= 0) yd_pos[p] = yd[r];
+  for (int64_t j = threadIdx.x; j < N; j += 256) {
+    const int32_t r = pos2row[j];
+    yd_pos[j] = r >= 0 ? yd[r] : 0.0;
   }
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < n_pad; r += 256) s += dbar[r] * dbar[r];
   part[threadIdx.x] = s;
+  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int k = 0; k < 256; ++k) t += part[k];
-    qdd[0] = t;
+    chk->qdd = t;
+    cache->qdd = t;
+    __threadfence();
+    cache->fp = chk->fp;
+    cache->valid = 1;
   }
+}
+
+hipError_t launch_data_check(const double *d, const int32_t *idx, int32_t n_pad, DataCache *cache,
+                             DataCheck *chk, int32_t can_whiten, int32_t force, hipStream_t s) {
+  hipLaunchKernelGGL(k_data_check, dim3(1), dim3(1024), 0, s, d, idx, n_pad, cache, chk,
+                     can_whiten, force);
+  return hipGetLastError();
 }
 
 hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const int32_t *w64_rb,
                               const int32_t *blk_first, const int32_t *blk_last, const int32_t *idx,
-                              int32_t n_pad, int64_t N, const double *d, double *dbar, double *yd,
-                              double *yd_pos, double *qdd, hipStream_t s) {
+                              const int32_t *pos2row, int32_t n_pad, int64_t N, const double *d,
+                              double *dbar, double *yd, double *yd_pos, DataCache *cache,
+                              DataCheck *chk, hipStream_t s) {
   hipLaunchKernelGGL(k_dbar, dim3((unsigned)(n_pad / TB)), dim3(TB), 0, s, w64, w64_off, w64_rb,
-                     blk_first, idx, d, dbar);
+                     blk_first, idx, d, dbar, (const DataCheck *)chk);
   hipLaunchKernelGGL(k_yd, dim3((unsigned)(n_pad / 32)), dim3(256), 0, s, w64, w64_off, w64_rb,
-                     blk_last, dbar, yd);
-  hipLaunchKernelGGL(k_qdd_and_scatter, dim3(1), dim3(256), 0, s, dbar, yd, idx, n_pad, N, yd_pos,
-                     qdd);
+                     blk_last, dbar, yd, (const DataCheck *)chk);
+  hipLaunchKernelGGL(k_qdd_and_scatter, dim3(1), dim3(256), 0, s, dbar, yd, pos2row, n_pad, N,
+                     yd_pos, cache, chk);
   return hipGetLastError();
 }
 
@@ -1091,8 +1162,10 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(const RefItem *__restrict
       it.qpart[ba] = s_bada > 0 ? nan : it.qdd[0] - 2.0 * s_ydha + 2.0 * s_hya - s_yca;
       if (two) it.qpart[bb] = s_badb > 0 ? nan : it.qdd[0] - 2.0 * s_ydhb + 2.0 * s_hyb - s_ycb;
       if (it.dh_out) {
-        it.dh_out[ba] = s_bada > 0 ? nan : s_ydha;
-        if (two) it.dh_out[bb] = s_badb > 0 ? nan : s_ydhb;
+        // a NaN q_dd marks data that the handle can no longer whiten: <d,h> is NaN too
+        const bool dbad = isnan(it.qdd[0]);
+        it.dh_out[ba] = s_bada > 0 || dbad ? nan : s_ydha;
+        if (two) it.dh_out[bb] = s_badb > 0 || dbad ? nan : s_ydhb;
       }
       if (it.hh_out) {
         it.hh_out[ba] = s_bada > 0 ? nan : 2.0 * s_hya - s_yca;
@@ -1896,7 +1969,7 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
     if (threadIdx.x == 0) {
       const double nan = __builtin_nan("");
       it.qpart[b] = s_bad > 0 ? nan : it.qdd[0] - 2.0 * s_ydh + 2.0 * s_hy - s_yc;
-      if (it.dh_out) it.dh_out[b] = s_bad > 0 ? nan : s_ydh;
+      if (it.dh_out) it.dh_out[b] = s_bad > 0 || isnan(it.qdd[0]) ? nan : s_ydh;
       if (it.hh_out) it.hh_out[b] = s_bad > 0 ? nan : 2.0 * s_hy - s_yc;
     }
   }

@@ -7,6 +7,11 @@
 // (own stream and workspace).  A completion thread retires slots in launch order,
 // stamps latencies and frees the slot for the next batch.  Up to n_slots batches are
 // in flight, so new requests are admitted while earlier ones run.
+//
+// Bounded bookkeeping: request states live in a ring indexed by ticket (sized at creation
+// to hold every request that can be outstanding), latencies in a fixed log-spaced
+// histogram, and each slot's device and pinned tables are sized at creation for the
+// largest batch its staging share admits, so nothing grows while the server runs.
 #include <math.h>
 #include <string.h>
 
@@ -49,41 +54,59 @@ struct Slot {
   hipEvent_t ev = nullptr;
   MultiCtx *mc = nullptr;
   // device tables: row pointers, result staging, scatter descriptors
+  // (sized at creation: rows_cap template rows, desc_cap requests)
   void *rows_dev = nullptr;
   size_t rows_cap = 0;
   double *out_dev = nullptr;
-  size_t out_cap = 0;
   int64_t *desc_dev = nullptr;
   size_t desc_cap = 0;
   // pinned host staging for the tables
   void *rows_host = nullptr;
-  size_t rows_host_cap = 0;
   int64_t *desc_host = nullptr;
-  size_t desc_host_cap = 0;
   std::vector<Request> reqs;
   bool busy = false;
   double t_launch = 0;
 };
 
-hipError_t grow_host(void **p, size_t *cap, size_t need) {
-  if (need <= *cap) return hipSuccess;
-  if (*p) (void)hipHostFree(*p);
-  *p = nullptr;
-  size_t c = std::max(need * 2, (size_t)4096);
-  hipError_t e = hipHostMalloc(p, c, 0);
-  if (e == hipSuccess) *cap = c;
-  return e;
-}
+// Latency histogram: bucket k covers [kLatMin * kLatStep^k, kLatMin * kLatStep^(k+1)) ms,
+// 1 us to about 1e5 s at 1 % resolution; the first and last buckets take what falls outside.
+constexpr int kLatBuckets = 2560;
+constexpr double kLatMin = 1e-3;
+constexpr double kLatStep = 1.01;
 
-hipError_t grow_dev(void **p, size_t *cap, size_t need) {
-  if (need <= *cap) return hipSuccess;
-  if (*p) (void)hipFree(*p);
-  *p = nullptr;
-  size_t c = std::max(need * 2, (size_t)4096);
-  hipError_t e = hipMalloc(p, c);
-  if (e == hipSuccess) *cap = c;
-  return e;
-}
+struct LatencyHist {
+  std::vector<int64_t> n = std::vector<int64_t>(kLatBuckets, 0);
+  int64_t count = 0;
+  double sum = 0.0, max = 0.0;
+  void add(double ms) {
+    int k = ms <= kLatMin ? 0 : (int)(log(ms / kLatMin) / log(kLatStep));
+    k = std::min(std::max(k, 0), kLatBuckets - 1);
+    n[k] += 1;
+    count += 1;
+    sum += ms;
+    max = std::max(max, ms);
+  }
+  // p-th percentile, interpolated inside its bucket (geometrically)
+  double pct(double p) const {
+    if (count == 0) return 0.0;
+    const double target = p / 100.0 * (double)count;
+    int64_t below = 0;
+    for (int k = 0; k < kLatBuckets; ++k) {
+      if (n[k] == 0) continue;
+      if ((double)(below + n[k]) >= target) {
+        const double f = std::min(std::max((target - (double)below) / (double)n[k], 0.0), 1.0);
+        return std::min(kLatMin * pow(kLatStep, (double)k + f), max);
+      }
+      below += n[k];
+    }
+    return max;
+  }
+  void clear() {
+    std::fill(n.begin(), n.end(), 0);
+    count = 0;
+    sum = max = 0.0;
+  }
+};
 
 }  // namespace
 
@@ -97,12 +120,20 @@ struct tda_server {
   std::deque<Request> pending;
   std::vector<Slot> slots;
   std::deque<int> inflight;
-  std::vector<uint8_t> done;  // by ticket
+  // request state by ticket: ring[t & ring_mask] = 0 pending, 1 done, 2 failed.  The ring
+  // holds at least twice as many entries as requests can be outstanding (pending or in
+  // flight), so a ticket older than one ring length has completed; failures of such old
+  // tickets are kept in a short list.
+  std::vector<uint8_t> ring;
+  uint64_t ring_mask = 0;
+  std::deque<uint64_t> old_failed;
+  int64_t outstanding = 0;
+  int64_t max_outstanding = 0;
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread sched, retire;
   // statistics
-  std::vector<double> lat_ms;
+  LatencyHist lat;
   int64_t submitted = 0, completed = 0, rejected = 0, launches = 0, templates = 0, max_depth = 0;
   double busy_s = 0, busy_since = -1;
   tda_status error = TDA_OK;
@@ -110,6 +141,20 @@ struct tda_server {
 
   void scheduler();
   void retirer();
+  uint8_t &state(uint64_t t) { return ring[t & ring_mask]; }
+  // 0 pending, 1 done, 2 failed; ticket known to have been issued
+  uint8_t status(uint64_t t) const {
+    if (t + ring_mask + 1 > next_ticket) return ring[t & ring_mask];
+    return std::find(old_failed.begin(), old_failed.end(), t) != old_failed.end() ? 2 : 1;
+  }
+  void finish(uint64_t t, uint8_t st) {
+    ring[t & ring_mask] = st;
+    if (st == 2) {
+      old_failed.push_back(t);
+      if (old_failed.size() > 4096) old_failed.pop_front();
+    }
+    outstanding -= 1;
+  }
   tda_status launch(Slot &sl, std::vector<Request> &reqs, const std::vector<Dataset> &dsv);
 };
 
@@ -138,17 +183,10 @@ tda_status tda_server::launch(Slot &sl, std::vector<Request> &reqs,
     out_off.push_back(rows);
     rows += B;
   }
-  if (grow_dev(&sl.rows_dev, &sl.rows_cap, rows * sizeof(void *)) != hipSuccess ||
-      grow_dev((void **)&sl.out_dev, &sl.out_cap, rows * sizeof(double)) != hipSuccess ||
-      grow_dev((void **)&sl.desc_dev, &sl.desc_cap, reqs.size() * 3 * sizeof(int64_t)) !=
-          hipSuccess)
-    return set_error(TDA_ENOMEM, "server: staging allocation failed");
+  // tables sized at creation for slot_rows templates (the coalescing never takes more);
   // the slot's previous launch has retired, so its pinned tables are free to reuse
-  if (grow_host(&sl.rows_host, &sl.rows_host_cap, std::max<size_t>(rows, 1) * sizeof(void *)) !=
-          hipSuccess ||
-      grow_host((void **)&sl.desc_host, &sl.desc_host_cap,
-                std::max<size_t>(reqs.size(), 1) * 3 * sizeof(int64_t)) != hipSuccess)
-    return set_error(TDA_ENOMEM, "server: pinned staging allocation failed");
+  if ((size_t)rows > sl.rows_cap || reqs.size() > sl.desc_cap)
+    return set_error(TDA_EINTERNAL, "server: batch beyond the slot tables");
   const double **rt = (const double **)sl.rows_host;
   std::vector<int64_t> fill(order.size(), 0);
   size_t nd = 0;
@@ -232,7 +270,7 @@ void tda_server::scheduler() {
     lk.lock();
     if (st != TDA_OK) {
       error = st;
-      for (const Request &r : take) done[r.ticket] = 2;  // failed
+      for (const Request &r : take) finish(r.ticket, 2);
       sl.busy = false;
       cv.notify_all();
       continue;
@@ -266,8 +304,8 @@ void tda_server::retirer() {
     lk.lock();
     inflight.pop_front();
     for (const Request &r : sl.reqs) {
-      done[r.ticket] = e == hipSuccess ? 1 : 2;
-      lat_ms.push_back((t - r.t_submit) * 1e3);
+      finish(r.ticket, e == hipSuccess ? 1 : 2);
+      lat.add((t - r.t_submit) * 1e3);
       completed += 1;
     }
     sl.reqs.clear();
@@ -295,6 +333,19 @@ extern "C" tda_status tda_server_create(const tda_server_options *opt, tda_serve
   if (s->device < 0) (void)hipGetDevice(&s->device);
   (void)hipSetDevice(s->device);
   s->slot_stage_bytes = std::max<size_t>(opt->staging_bytes / opt->n_slots, 1 << 16);
+  // a launch gathers at most slot_rows templates (a single request may fill the share)
+  const size_t slot_rows = s->slot_stage_bytes / (sizeof(void *) + sizeof(double));
+  // outstanding requests: at most max_queue pending plus what n_slots launches took
+  const uint64_t most = (uint64_t)opt->max_queue * (uint64_t)(opt->n_slots + 1);
+  uint64_t rs = 1024;
+  while (rs < 2 * most) rs <<= 1;
+  if (rs > ((uint64_t)1 << 30)) {
+    delete s;
+    return set_error(TDA_EINVAL, "max_queue x (n_slots + 1) too large for the request ring");
+  }
+  s->ring.assign(rs, 0);
+  s->ring_mask = rs - 1;
+  s->max_outstanding = (int64_t)most;
   s->slots.resize(opt->n_slots);
   for (Slot &sl : s->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -303,8 +354,17 @@ extern "C" tda_status tda_server_create(const tda_server_options *opt, tda_serve
       return set_error(TDA_EHIP, "server: stream/event creation failed");
     }
     sl.mc = multi_ctx_create();
+    sl.rows_cap = slot_rows;
+    sl.desc_cap = slot_rows;
+    if (hipMalloc(&sl.rows_dev, slot_rows * sizeof(void *)) != hipSuccess ||
+        hipMalloc((void **)&sl.out_dev, slot_rows * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&sl.desc_dev, slot_rows * 3 * sizeof(int64_t)) != hipSuccess ||
+        hipHostMalloc(&sl.rows_host, slot_rows * sizeof(void *), 0) != hipSuccess ||
+        hipHostMalloc((void **)&sl.desc_host, slot_rows * 3 * sizeof(int64_t), 0) != hipSuccess) {
+      tda_server_destroy(s);
+      return set_error(TDA_ENOMEM, "server: slot table allocation failed");
+    }
   }
-  s->done.resize(1, 0);
   s->sched = std::thread([s] { s->scheduler(); });
   s->retire = std::thread([s] { s->retirer(); });
   *out = s;
@@ -318,6 +378,15 @@ extern "C" tda_status tda_server_add_dataset(tda_server_t s, tda_handle h, const
   if (!handle_ready(h, s->opt.precision))
     return set_error(TDA_ESTATE, "dataset handle not factored for the server precision");
   std::lock_guard<std::mutex> lk(s->mu);
+  // one handle caches one data vector: a second registration with other data would
+  // rewrite the cache under requests of the first
+  for (size_t k = 0; k < s->ds.size(); ++k)
+    if (s->ds[k].h == h) {
+      if (s->ds[k].d != d)
+        return set_error(TDA_EINVAL, "handle already registered with other data");
+      *dataset = (int32_t)k;
+      return TDA_OK;
+    }
   const size_t bytes = handle_bytes(h);
   if (s->opt.dataset_budget_bytes && s->ds_bytes + bytes > s->opt.dataset_budget_bytes)
     return set_error(TDA_ENOMEM, "dataset budget exceeded");
@@ -341,13 +410,14 @@ extern "C" tda_status tda_server_submit(tda_server_t s, int32_t dataset, const d
   if (dataset < 0 || dataset >= (int32_t)s->ds.size()) return set_error(TDA_EINVAL, "bad dataset");
   if (B < 1 || !H || !out || ldh < s->ds[dataset].N) return set_error(TDA_EINVAL, "bad request");
   if (s->stop) return set_error(TDA_ESTATE, "server stopping");
-  if ((int64_t)s->pending.size() >= s->opt.max_queue ||
+  if ((int64_t)s->pending.size() >= s->opt.max_queue || s->outstanding >= s->max_outstanding ||
       (size_t)B * (sizeof(void *) + sizeof(double)) > s->slot_stage_bytes) {
     s->rejected += 1;
     return TDA_EAGAIN;
   }
   const uint64_t tk = s->next_ticket++;
-  if (s->done.size() <= tk) s->done.resize(tk + 1, 0);
+  s->state(tk) = 0;
+  s->outstanding += 1;
   s->pending.push_back(Request{tk, dataset, H, B, ldh, out, t});
   s->submitted += 1;
   s->max_depth = std::max<int64_t>(s->max_depth, (int64_t)s->pending.size());
@@ -360,8 +430,9 @@ extern "C" tda_status tda_server_poll(tda_server_t s, uint64_t ticket, int32_t *
   if (!s || !done) return set_error(TDA_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
   if (ticket == 0 || ticket >= s->next_ticket) return set_error(TDA_EINVAL, "unknown ticket");
-  if (s->done[ticket] == 2) return set_error(TDA_EHIP, "request failed");
-  *done = s->done[ticket] == 1;
+  const uint8_t st = s->status(ticket);
+  if (st == 2) return set_error(TDA_EHIP, "request failed");
+  *done = st == 1;
   return TDA_OK;
 }
 
@@ -370,9 +441,9 @@ extern "C" tda_status tda_server_wait(tda_server_t s, uint64_t ticket, double ti
   std::unique_lock<std::mutex> lk(s->mu);
   if (ticket == 0 || ticket >= s->next_ticket) return set_error(TDA_EINVAL, "unknown ticket");
   const bool ok = s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
-                                 [&] { return s->done[ticket] != 0; });
+                                 [&] { return s->status(ticket) != 0; });
   if (!ok) return TDA_EAGAIN;
-  return s->done[ticket] == 1 ? TDA_OK : set_error(TDA_EHIP, "request failed");
+  return s->status(ticket) == 1 ? TDA_OK : set_error(TDA_EHIP, "request failed");
 }
 
 extern "C" tda_status tda_server_stats(tda_server_t s, tda_server_stats_t *st, int32_t reset) {
@@ -386,25 +457,15 @@ extern "C" tda_status tda_server_stats(tda_server_t s, tda_server_stats_t *st, i
   st->templates = s->templates;
   st->max_queue_depth = s->max_depth;
   st->busy_s = s->busy_s + (s->busy_since >= 0 ? now_s() - s->busy_since : 0.0);
-  if (!s->lat_ms.empty()) {
-    std::vector<double> v = s->lat_ms;
-    std::sort(v.begin(), v.end());
-    auto pct = [&](double p) {
-      const double x = p / 100.0 * (double)(v.size() - 1);
-      const size_t i = (size_t)x;
-      const double f = x - (double)i;
-      return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
-    };
-    st->p50_ms = pct(50);
-    st->p99_ms = pct(99);
-    double sum = 0;
-    for (double x : v) sum += x;
-    st->mean_ms = sum / (double)v.size();
-    st->max_ms = v.back();
+  if (s->lat.count) {
+    st->p50_ms = s->lat.pct(50);
+    st->p99_ms = s->lat.pct(99);
+    st->mean_ms = s->lat.sum / (double)s->lat.count;
+    st->max_ms = s->lat.max;
   }
   st->mean_templates_per_launch = s->launches ? (double)s->templates / (double)s->launches : 0;
   if (reset) {
-    s->lat_ms.clear();
+    s->lat.clear();
     s->submitted = s->completed = s->rejected = s->launches = s->templates = s->max_depth = 0;
     s->busy_s = 0;
     if (s->busy_since >= 0) s->busy_since = now_s();

@@ -14,6 +14,7 @@
 
 using namespace tda;
 
+
 namespace {
 
 thread_local std::string g_err;
@@ -184,6 +185,8 @@ struct DescRing {
 
 struct tda_ctx {
   int device = 0;
+  tda_allocator user_alloc{};  // caller's device-memory provider (has_user_alloc)
+  bool has_user_alloc = false;
   int precision = TDA_PREC_FP64;
   int flags = 0;
   bool compacted = false;  // FP64 panels and operator released (TDA_FLAG_COMPACT)
@@ -214,8 +217,10 @@ struct tda_ctx {
   DevBuf w64_d, w64_off_d, w64_rb_d;
   DevBuf wa_hi, wa_lo, wb_hi, wb_lo, wa_off_d, wb_off_d;
   DevBuf lam_d, tw_d, segdev_d;
-  DevBuf dbar_d, yd_d, ydpos_d, qdd_d;
-  const double *data_ptr = nullptr;
+  DevBuf dbar_d, yd_d, ydpos_d;
+  DevBuf cache_d;   // DataCache: fingerprint and q_dd of the whitened data
+  DevBuf chk_d;     // DataCheck of the single-handle calls (serialised per handle)
+  const double *data_ptr = nullptr;  // data of the last call (compact handles: the cached data)
 
   // Gohberg-Semencul state: per segment twiddles, pass twiddles, the two spectra and
   // x = C^-1 e_1; descriptors; Levinson outputs
@@ -228,6 +233,7 @@ struct tda_ctx {
   DevBuf ws_hs_hi, ws_hs_lo, ws_w0_hi, ws_w0_lo, ws_y0, ws_fft, ws_work, ws_mix, ws_ref;
   DevBuf ws_zero, ws_terms;  // inner-product entry point: zero vector [N], <h,h> and <d,d>
   DevBuf ws_cdo;             // explicit-inverse evaluation: residual rows and block sums
+  DevBuf ws_snr;             // tda_snr: <d,h> and <h,h>
   hipEvent_t done = nullptr;  // last enqueued work of this handle
   DescRing ring;
   std::vector<SegDev> segdev_h;
@@ -242,27 +248,46 @@ struct tda_ctx {
     if (b.p) {
       if (b.bytes >= bytes) return TDA_OK;
       hipDeviceSynchronize();
-      hipFree(b.p);
+      free_dev(b.p);
       held -= b.bytes;
       b.p = nullptr;
       b.bytes = 0;
     }
-    if (bytes == 0) bytes = 256;
+    // whole 512-byte units (the granule of PyTorch's caching allocator, so that the bytes a
+    // caller's allocator accounts equal device_bytes)
+    if (bytes == 0) bytes = 512;
+    bytes = (bytes + 511) & ~(size_t)511;
     if (budget && held + bytes > budget)
       return fail_with(TDA_ENOMEM, "HBM budget exceeded: need %zu more bytes, hold %zu of %zu",
                        bytes, held, budget);
-    hipError_t e = hipMalloc(&b.p, bytes);
-    if (e != hipSuccess) {
-      b.p = nullptr;
-      return fail_with(TDA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (has_user_alloc) {
+      b.p = user_alloc.alloc(bytes, user_alloc.ctx);
+      if (!b.p) return fail_with(TDA_ENOMEM, "allocator returned NULL for %zu bytes", bytes);
+      if ((uintptr_t)b.p & 255) {
+        user_alloc.free(b.p, user_alloc.ctx);
+        b.p = nullptr;
+        return fail_with(TDA_ENOMEM, "allocator returned memory not aligned to 256 bytes");
+      }
+    } else {
+      hipError_t e = hipMalloc(&b.p, bytes);
+      if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail_with(TDA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      }
     }
     b.bytes = bytes;
     held += bytes;
     return TDA_OK;
   }
+  void free_dev(void *p) {
+    if (has_user_alloc)
+      user_alloc.free(p, user_alloc.ctx);
+    else
+      hipFree(p);
+  }
   void release(DevBuf &b) {
     if (b.p) {
-      hipFree(b.p);
+      free_dev(b.p);
       held -= b.bytes;
     }
     b.p = nullptr;
@@ -273,10 +298,11 @@ struct tda_ctx {
                      &dinv128_d, &dinv256_d, &logdiag_d, &logdet_d,  &fail_d,     &panels_d,
                      &panel_off_d, &w64_d, &w64_off_d, &w64_rb_d,    &wa_hi,      &wa_lo,
                      &wb_hi,   &wb_lo,    &wa_off_d,   &wb_off_d,    &lam_d,      &tw_d,
-                     &segdev_d, &dbar_d,  &yd_d,       &ydpos_d,     &qdd_d,      &ws_scratch,
+                     &segdev_d, &dbar_d,  &yd_d,       &ydpos_d,     &cache_d,    &ws_scratch,
                      &ws_tiles, &ws_items, &ws_hs_hi,  &ws_hs_lo,    &ws_w0_hi,   &ws_w0_lo,
                      &ws_y0,   &ws_fft,   &ws_work,    &ws_mix,      &ws_ref,     &gs_tab_d,
-                     &gs_seg_d, &gs_lev_d, &ws_zero,  &ws_terms,   &ws_cdo,      &retpos_d};
+                     &gs_seg_d, &gs_lev_d, &ws_zero,  &ws_terms,   &ws_cdo,      &retpos_d,
+                     &chk_d,   &ws_snr};
     for (DevBuf *b : all) release(*b);
   }
   double cterm() const { return -0.5 * logdet - 0.5 * (double)n_eff * kLog2Pi; }
@@ -333,11 +359,17 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     return fail_with(TDA_EINVAL, "acf[0] must be positive and finite");
   if (n_segments < 0 || (n_segments > 0 && !segments))
     return fail_with(TDA_EINVAL, "bad segment list");
-  tda_options o{sizeof(tda_options), TDA_PREC_FP64, -1, 0, 0};  // struct_size, precision, device, flags, budget
+  // struct_size, precision, device, flags, budget, allocator
+  tda_options o{sizeof(tda_options), TDA_PREC_FP64, -1, 0, 0, nullptr};
   if (opt) {
-    if (opt->struct_size < sizeof(tda_options)) return fail_with(TDA_EINVAL, "options struct_size");
-    o = *opt;
+    // the options of callers built before the allocator field end at its offset
+    const size_t v1 = offsetof(tda_options, allocator);
+    if (opt->struct_size < v1) return fail_with(TDA_EINVAL, "options struct_size");
+    memcpy(&o, opt, std::min<size_t>(opt->struct_size, sizeof(tda_options)));
+    o.struct_size = sizeof(tda_options);
   }
+  if (o.allocator && (!o.allocator->alloc || !o.allocator->free))
+    return fail_with(TDA_EINVAL, "allocator needs both alloc and free");
   if (o.precision != TDA_PREC_FP64 && o.precision != TDA_PREC_MIXED && o.precision != TDA_PREC_GS)
     return fail_with(TDA_EINVAL, "unknown precision %d", o.precision);
   if (o.flags & ~TDA_FLAG_COMPACT) return fail_with(TDA_EINVAL, "unknown flags");
@@ -375,6 +407,10 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   h->precision = o.precision;
   h->flags = o.flags;
   h->budget = o.hbm_budget_bytes;
+  if (o.allocator) {
+    h->user_alloc = *o.allocator;
+    h->has_user_alloc = true;
+  }
   h->N = N;
   h->acf.assign(acf, acf + longest);
 
@@ -423,9 +459,14 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   h->n_pad = row;
   h->nblk = blk;
   h->idx_h = idx;
+  if (hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess) {
+    delete h;
+    return fail_with(TDA_EHIP, "event creation failed");
+  }
   h->idx_hash = 1469598103934665603ull;
   for (int32_t v : idx) h->idx_hash = (h->idx_hash ^ (uint32_t)v) * 1099511628211ull;
   if (h->n_pad > ((int64_t)1 << 31) / TB) {
+    hipEventDestroy(h->done);
     delete h;
     return fail_with(TDA_EINVAL, "too many rows");
   }
@@ -442,6 +483,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
   tda_status st = TDA_OK;
   auto cleanup = [&](tda_status s) {
     h->release_all();
+    hipEventDestroy(h->done);
     delete h;
     return s;
   };
@@ -470,6 +512,7 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     if ((st = h->alloc(h->A_d, dense * sizeof(double))) != TDA_OK) return cleanup(st);
     size_t a_off = 0;
     for (const Seg &g : h->segs) {
+      TimedScope ts("assemble", 0);
       hipError_t e = launch_assemble((const double *)h->acf_d.p,
                                      (const int32_t *)h->idx_d.p + g.row0, g.n_keep, g.n_pad,
                                      (double *)h->A_d.p + a_off, 0);
@@ -516,8 +559,11 @@ extern "C" tda_status tda_factor(tda_handle h) {
     HIP_TRY(hipMemcpy(h->fail_d.p, &minus1, sizeof minus1, hipMemcpyHostToDevice));
     double *A = (double *)h->A_d.p + a_off;
     double *dinv = (double *)h->dinv128_d.p + cp_off * CP * CP;
-    HIP_TRY(launch_cholesky(A, g.n_pad, dinv, (double *)h->logdiag_d.p + cp_off,
-                            (int32_t *)h->fail_d.p, 0));
+    {
+      TimedScope ts("cholesky", 0);
+      HIP_TRY(launch_cholesky(A, g.n_pad, dinv, (double *)h->logdiag_d.p + cp_off,
+                              (int32_t *)h->fail_d.p, 0));
+    }
     int32_t failrow = -1;
     HIP_TRY(hipMemcpy(&failrow, h->fail_d.p, sizeof failrow, hipMemcpyDeviceToHost));
     if (failrow >= 0) {
@@ -752,20 +798,15 @@ extern "C" tda_status tda_loglik_ex(tda_handle h, const double *d, const double 
   return mark_done(h, s);
 }
 
-extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int64_t B,
-                                       int64_t ldh, double *out, double *out_dh, double *out_hh,
-                                       int32_t precision, void *hip_stream) {
-  TDA_TRY(check_eval(h, d, H, B, ldh, out, precision));
-  if (B == 0) return TDA_OK;
-  DeviceGuard guard(h->device);
-  hipStream_t s = (hipStream_t)hip_stream;
-  TDA_TRY(refuse_capture(s));
-  TDA_TRY(order_after_previous(h, s));
+// logL, <d,h> and <h,h> (either may be NULL) on stream s, ordered after the handle's
+// earlier work by the caller.
+static tda_status terms_impl(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
+                             double *out, double *out_dh, double *out_hh, int32_t precision,
+                             hipStream_t s) {
   if (precision == TDA_PREC_MIXED) {
     // <d,h> = y_d^T h is an FP64 term of the split form and <h,h> its refined part plus
     // the correction: both come out of the same launches
-    TDA_TRY(loglik_mixed(h, d, H, B, ldh, out, s, out_dh, out_hh));
-    return mark_done(h, s);
+    return loglik_mixed(h, d, H, B, ldh, out, s, out_dh, out_hh);
   }
   auto eval = [&](const double *dd, const double *HH, int64_t BB, int64_t ld, double *o) {
     return precision == TDA_PREC_FP64  ? loglik_f64(h, dd, HH, BB, ld, o, s)
@@ -788,6 +829,36 @@ extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const doub
     if (out_dh) TDA_TRY(eval(d, zero, 1, h->N, dd));
     HIP_TRY(launch_terms_combine(out, hh, dd, h->cterm(), B, out_dh, s));
   }
+  return TDA_OK;
+}
+
+extern "C" tda_status tda_loglik_terms(tda_handle h, const double *d, const double *H, int64_t B,
+                                       int64_t ldh, double *out, double *out_dh, double *out_hh,
+                                       int32_t precision, void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, precision));
+  if (B == 0) return TDA_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(refuse_capture(s));
+  TDA_TRY(order_after_previous(h, s));
+  TDA_TRY(terms_impl(h, d, H, B, ldh, out, out_dh, out_hh, precision, s));
+  return mark_done(h, s);
+}
+
+extern "C" tda_status tda_snr(tda_handle h, const double *d, const double *H, int64_t B,
+                              int64_t ldh, double *out, double *rho_mf, double *rho_opt,
+                              double *rho_eff2, int32_t precision, void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, precision));
+  if (B == 0) return TDA_OK;
+  DeviceGuard guard(h->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  TDA_TRY(refuse_capture(s));
+  TDA_TRY(order_after_previous(h, s));
+  // <d,h> and <h,h> into the handle's SNR buffer, then the three ratios
+  TDA_TRY(h->alloc(h->ws_snr, (size_t)2 * B * sizeof(double)));
+  double *dh = (double *)h->ws_snr.p, *hh = dh + B;
+  TDA_TRY(terms_impl(h, d, H, B, ldh, out, dh, hh, precision, s));
+  HIP_TRY(launch_snr(dh, hh, B, rho_mf, rho_opt, rho_eff2, s));
   return mark_done(h, s);
 }
 
@@ -818,6 +889,7 @@ extern "C" tda_status tda_loglik(tda_handle h, const double *d, const double *H,
   if (!h) return fail_with(TDA_EINVAL, "NULL handle");
   return tda_loglik_ex(h, d, H, B, ldh, out, h->precision, hip_stream);
 }
+
 
 // ---------------------------------------------------------------- mixed precision
 
@@ -983,22 +1055,50 @@ static tda_status build_mixed(tda_ctx *h) {
     mo += g.m;
   }
   TDA_TRY(upload(h, h->segdev_d, h->segdev_h.data(), h->segdev_h.size() * sizeof(SegDev)));
+  // whitened-data cache (invalid until the first data check) and the per-call check
+  TDA_TRY(h->alloc(h->cache_d, sizeof(DataCache)));
+  TDA_TRY(h->alloc(h->chk_d, sizeof(DataCheck)));
+  HIP_TRY(hipMemset(h->cache_d.p, 0, sizeof(DataCache)));
+  HIP_TRY(hipMemset(h->chk_d.p, 0, sizeof(DataCheck)));
   HIP_TRY(hipDeviceSynchronize());
   return TDA_OK;
 }
 
+// Enqueue the data check of a mixed handle for data d into chk (device): the fingerprint
+// of d's retained samples against the cached one and, while the handle holds its FP64
+// operator, the whitening kernels, which run only on a mismatch (or with force).  A
+// compact handle cannot whiten new data: the check then sets chk->qdd to NaN.
+static tda_status enqueue_data_check(tda_ctx *h, const double *d, DataCheck *chk, bool force,
+                                     hipStream_t s) {
+  const bool can_whiten = !h->compacted && h->w64_d.p;
+  if (can_whiten) {
+    TDA_TRY(h->alloc(h->dbar_d, (size_t)h->n_pad * sizeof(double)));
+    TDA_TRY(h->alloc(h->yd_d, (size_t)h->n_pad * sizeof(double)));
+    TDA_TRY(h->alloc(h->ydpos_d, (size_t)h->N * sizeof(double)));
+  }
+  {
+    TimedScope ts("data_check", s);
+    HIP_TRY(launch_data_check(d, (const int32_t *)h->idx_d.p, (int32_t)h->n_pad,
+                              (DataCache *)h->cache_d.p, chk, can_whiten ? 1 : 0, force ? 1 : 0, s));
+  }
+  if (can_whiten) {
+    TimedScope ts("data_whiten", s);
+    HIP_TRY(launch_data_whiten((const double *)h->w64_d.p, (const int64_t *)h->w64_off_d.p,
+                               (const int32_t *)h->w64_rb_d.p, (const int32_t *)h->blk_first_d.p,
+                               (const int32_t *)h->blk_last_d.p, (const int32_t *)h->idx_d.p,
+                               (const int32_t *)h->pos2row_d.p, (int32_t)h->n_pad, h->N, d,
+                               (double *)h->dbar_d.p, (double *)h->yd_d.p,
+                               (double *)h->ydpos_d.p, (DataCache *)h->cache_d.p, chk, s));
+  }
+  return TDA_OK;
+}
+
+// Whiten d now (tda_set_data, server registration); a compact handle then releases its
+// FP64 operator and solve panels.
 static tda_status set_data_impl(tda_ctx *h, const double *d, hipStream_t s) {
   if (h->compacted)
     return fail_with(TDA_ESTATE, "compact handle: the FP64 operator was released after its data");
-  TDA_TRY(h->alloc(h->dbar_d, (size_t)h->n_pad * sizeof(double)));
-  TDA_TRY(h->alloc(h->yd_d, (size_t)h->n_pad * sizeof(double)));
-  TDA_TRY(h->alloc(h->ydpos_d, (size_t)h->N * sizeof(double)));
-  TDA_TRY(h->alloc(h->qdd_d, sizeof(double)));
-  HIP_TRY(launch_data_whiten((const double *)h->w64_d.p, (const int64_t *)h->w64_off_d.p,
-                             (const int32_t *)h->w64_rb_d.p, (const int32_t *)h->blk_first_d.p,
-                             (const int32_t *)h->blk_last_d.p, (const int32_t *)h->idx_d.p,
-                             (int32_t)h->n_pad, h->N, d, (double *)h->dbar_d.p,
-                             (double *)h->yd_d.p, (double *)h->ydpos_d.p, (double *)h->qdd_d.p, s));
+  TDA_TRY(enqueue_data_check(h, d, (DataCheck *)h->chk_d.p, true, s));
   h->data_ptr = d;
   if (h->flags & TDA_FLAG_COMPACT) {
     HIP_TRY(hipStreamSynchronize(s));
@@ -1095,7 +1195,7 @@ static MixItem make_mix_item(const tda_ctx *h, const double *H, int64_t ldh, int
   return mi;
 }
 
-static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi) {
+static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi, const DataCheck *chk) {
   RefItem ri{};
   ri.segs = (const SegDev *)h->segdev_d.p;
   ri.n_segs = (int32_t)h->segdev_h.size();
@@ -1106,7 +1206,7 @@ static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi) {
   ri.ldh = mi.ldh;
   ri.Hrows = mi.Hrows;
   ri.yd_pos = (const double *)h->ydpos_d.p;
-  ri.qdd = (const double *)h->qdd_d.p;
+  ri.qdd = &chk->qdd;
   ri.idx = (const int32_t *)h->idx_d.p;
   ri.e64 = mi.e64;
   ri.qpart = mi.qpart;
@@ -1317,14 +1417,16 @@ static tda_status loglik_cdo(tda_ctx *h, const double *d, const double *H, int64
 static tda_status loglik_mixed(tda_ctx *h, const double *d, const double *H, int64_t B,
                                int64_t ldh, double *out, hipStream_t s, double *out_dh,
                                double *out_hh) {
-  if (d != h->data_ptr) TDA_TRY(set_data_impl(h, d, s));
+  DataCheck *chk = (DataCheck *)h->chk_d.p;
+  TDA_TRY(enqueue_data_check(h, d, chk, false, s));
+  h->data_ptr = d;
   const int64_t Bp = (B + MT - 1) / MT * MT;
   TDA_TRY(h->alloc(h->ws_mix, mix_ws_bytes(h, Bp)));
   if (fft_ws_bytes(h->max_m)) TDA_TRY(h->alloc(h->ws_fft, fft_ws_bytes(h->max_m)));
   const MixWs ws = carve_mix_ws(h, Bp, (char *)h->ws_mix.p);
   std::vector<MixItem> mis{make_mix_item(h, H, ldh, B, Bp, ws, out)};
   mis[0].hh_out = out_hh;
-  std::vector<RefItem> ris{make_ref_item(h, mis[0])};
+  std::vector<RefItem> ris{make_ref_item(h, mis[0], chk)};
   ris[0].dh_out = out_dh;
   ris[0].hh_out = out_hh;
   std::vector<const tda_ctx *> hs{h};
@@ -1385,9 +1487,13 @@ bool handle_ready(tda_handle h, int32_t precision) {
   return h->precision == precision;
 }
 tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s) {
-  if (h->precision != TDA_PREC_MIXED || h->data_ptr == d) return TDA_OK;
+  if (h->precision != TDA_PREC_MIXED) return TDA_OK;
+  if (h->compacted)
+    return h->data_ptr == d ? TDA_OK
+                            : fail_with(TDA_ESTATE, "compact handle: data other than its cached data");
   return set_data_impl(h, d, s);
 }
+const double *handle_data(tda_handle h) { return h->data_ptr; }
 tda_status set_error(tda_status st, const char *msg) { return fail_with(st, "%s", msg); }
 }  // namespace tda
 
@@ -1461,13 +1567,24 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
     return fail_with(TDA_ESTATE, "stream capture outside a plan: use tda_plan_execute");
   if (!mc->done) HIP_TRY(hipEventCreateWithFlags(&mc->done, hipEventDisableTiming));
   if (!capturing) HIP_TRY(hipStreamWaitEvent(s, mc->done, 0));
-  for (int64_t k = 0; k < n_items; ++k) {
+  for (int64_t k = 0; k < n_items; ++k)
     if (order_handles) TDA_TRY(order_after_previous(items[k].h, s));
-    if (precision == TDA_PREC_MIXED && items[k].B > 0 && items[k].d != items[k].h->data_ptr)
-      TDA_TRY(set_data_impl(items[k].h, items[k].d, s));
-  }
-  TDA_TRY(P.alloc(P.ws_work, (size_t)parts * sizeof(double)));
+  // partial results, then one data check per item (items of one handle share the first's)
+  const size_t part_bytes = ((size_t)parts * sizeof(double) + 255) & ~(size_t)255;
+  TDA_TRY(P.alloc(P.ws_work, part_bytes + (size_t)n_items * sizeof(DataCheck)));
   double *partbuf = (double *)P.ws_work.p;
+  DataCheck *chks = (DataCheck *)((char *)P.ws_work.p + part_bytes);
+  std::vector<int64_t> chk_of(n_items, -1);
+  if (precision == TDA_PREC_MIXED)
+    for (int64_t k = 0; k < n_items; ++k) {
+      if (items[k].B == 0) continue;
+      for (int64_t q = 0; q < k && chk_of[k] < 0; ++q)
+        if (items[q].h == items[k].h && chk_of[q] >= 0) chk_of[k] = chk_of[q];
+      if (chk_of[k] >= 0) continue;
+      chk_of[k] = k;
+      TDA_TRY(enqueue_data_check(items[k].h, items[k].d, chks + k, false, s));
+      items[k].h->data_ptr = items[k].d;
+    }
   std::vector<void *> blobs;
   if (precision == TDA_PREC_GS) {
     std::vector<GsItem> gis(n_items);
@@ -1553,7 +1670,7 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
       const MixWs ws = carve_mix_ws(w.h, Bp, (char *)P.ws_mix.p + ws_off[k]);
       mis[k] = make_mix_item(w.h, w.H, w.ldh, w.B, Bp, ws, partbuf + part_off[k]);
       mis[k].Hrows = hrows ? hrows[k] : nullptr;
-      ris[k] = make_ref_item(w.h, mis[k]);
+      ris[k] = make_ref_item(w.h, mis[k], chks + std::max<int64_t>(chk_of[k], 0));
       hs[k] = w.h;
     }
     // detectors that evaluate the same templates over the same padded rows share one

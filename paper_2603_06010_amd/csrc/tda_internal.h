@@ -161,7 +161,7 @@ struct RefItem {
   int64_t ldh;
   const double *const *Hrows;
   const double *yd_pos;    // [N] C^-1 d scattered to sample positions (0 at excluded)
-  const double *qdd;       // scalar
+  const double *qdd;       // scalar: this call's q_dd (DataCheck::qdd)
   const int32_t *idx;      // [n_pad] sample index of each padded row, -1 = padding
   double *e64;             // [Bp][n_pad] residual output
   double *qpart;           // [Bp] FP64 part of q output
@@ -216,6 +216,9 @@ hipError_t launch_scatter(const int64_t *desc, int64_t n, const double *src, hip
 // retained rows (retpos >= 0), row stride ldw.
 hipError_t launch_whiten_export(const double *scratch, const int32_t *retpos, int64_t n_pad,
                                 int64_t B, double *wres, int64_t ldw, hipStream_t s);
+// rho_mf = dh / sqrt(hh), rho_opt = sqrt(hh), rho_eff^2 = 2 dh - hh (NULL outputs skipped)
+hipError_t launch_snr(const double *dh, const double *hh, int64_t B, double *rho_mf,
+                      double *rho_opt, double *rho_eff2, hipStream_t s);
 hipError_t launch_terms_combine(const double *out, double *hh, const double *dd, double cterm,
                                 int64_t B, double *dh, hipStream_t s);
 
@@ -225,10 +228,31 @@ hipError_t launch_split_w(const double *w64, const int64_t *w64_off, const int32
                           uint16_t *wa_hi, uint16_t *wa_lo, const int64_t *wa_off,
                           uint16_t *wb_hi, uint16_t *wb_lo, const int64_t *wb_off,
                           int64_t max_k, int64_t unused, hipStream_t s);
+// Whitened-data cache of a mixed handle (device): fingerprint of the retained samples of
+// the data it was computed from, valid flag, and q_dd = dbar^T dbar.
+struct DataCache {
+  uint64_t fp;
+  uint64_t valid;
+  double qdd;
+  double pad;
+};
+// Per call and handle (device, in the call's workspace): the data's fingerprint, whether
+// the whitening kernels run, and the q_dd the refinement uses (NaN: data the handle can
+// no longer whiten).  qdd is the first member: RefItem::qdd points at it.
+struct DataCheck {
+  double qdd;
+  uint64_t fp;
+  int32_t stale;
+  int32_t pad[3];
+};
+hipError_t launch_data_check(const double *d, const int32_t *idx, int32_t n_pad, DataCache *cache,
+                             DataCheck *chk, int32_t can_whiten, int32_t force, hipStream_t s);
+// dbar, y_d, y_d at sample positions and q_dd, when chk->stale; publishes the fingerprint
 hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const int32_t *w64_rb,
                               const int32_t *blk_first, const int32_t *blk_last, const int32_t *idx,
-                              int32_t n_pad, int64_t N, const double *d, double *dbar, double *yd,
-                              double *yd_pos, double *qdd, hipStream_t s);
+                              const int32_t *pos2row, int32_t n_pad, int64_t N, const double *d,
+                              double *dbar, double *yd, double *yd_pos, DataCache *cache,
+                              DataCheck *chk, hipStream_t s);
 hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
                          double *ptw, hipStream_t s);
 // from_e = 0: split the gathered templates h; 1: split the FP64 residual e64 (same layout)
