@@ -13,7 +13,7 @@ cut-off, the SNR convention for template amplitudes and the gap law.
 """
 from .workloads import (  # noqa: F401
     FS, PSD_GRID, EPS_PRIMARY, EPS_STRESS, SEED_BASE,
-    analytic_psd, make_acf, stationary_noise, chirp, whittle_snr2,
+    analytic_psd, make_acf, eig_bounds, stationary_noise, chirp, whittle_snr2,
     draw_gaps, gap_mask_from, Instance, Workload, make_workload,
     c1_workload, c2_workload, c3_workload, c4_workload, c5_workload, c5_requests,
     random_rhs_case,

@@ -66,6 +66,19 @@ def make_acf(n_lags: int, eps: float = EPS_PRIMARY) -> np.ndarray:
     return acf
 
 
+def eig_bounds(eps: float = EPS_PRIMARY) -> Tuple[float, float]:
+    """Bounds (lo, hi) on every eigenvalue of any covariance built from ``make_acf(n, eps)``.
+
+    toeplitz(make_acf(n, eps)), n <= 2^19, is the leading block of the 2^20 circulant whose
+    eigenvalues are S_k / R[0] + eps (see ``stationary_noise``), and a gapped covariance
+    C[keep, keep] is a principal submatrix of that block.  By Cauchy interlacing every
+    eigenvalue lies in [min_k S_k / R[0] + eps, max_k S_k / R[0] + eps]; min_k S_k = 0
+    (the band below 20 Hz), so lo = eps.  hi / lo bounds the condition number.
+    """
+    _, S, R = _grid()
+    return float(S.min() / R[0] + eps), float(S.max() / R[0] + eps)
+
+
 def stationary_noise(rng: np.random.Generator, n: int, count: int,
                      eps: float = EPS_PRIMARY) -> np.ndarray:
     """``count`` independent length-``n`` draws from N(0, toeplitz(make_acf(n, eps))).

@@ -86,5 +86,6 @@ def test_acf_welch_recovers_covariance_and_feeds_the_likelihood(tda):
     f = oracle.factor(acf, N)
     want = oracle.loglik(f, x[:N], np.zeros((2, N)))
     torch.cuda.synchronize()
-    assert np.all(np.abs(got - want) <= 1e-6 + 2e-9 * np.abs(want))
+    from tolerance import kappa_exact, q_of, tol_f64
+    assert np.all(np.abs(got - want) <= tol_f64(q_of(want, [f]), kappa_exact(acf, N)))
     h.close()

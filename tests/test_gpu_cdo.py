@@ -2,21 +2,22 @@
 precomputed) against the FP64 oracle through the C ABI.
 
 W comes from the FP64 triangular solve against identity columns, so its forward error is
-about kappa(L) times the unit roundoff; the quadratic form inherits it.  Tolerance:
-|dlogL| <= 1e-5 + 2e-8 |logL| (ten times the substitution path's bound, as for the other
-FP64 route that is not backward stable, the Gohberg-Semencul form).
+about kappa(L) times the unit roundoff; the quadratic form inherits it.  Tolerance: ten
+times the substitution path's bound 1e-6 + kappa(C) u q (tests/tolerance.py), as for the
+other FP64 route that is not backward stable, the Gohberg-Semencul form.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tolerance import kappa_synth, q_of, tol_f64, tol_terms
 
 pytestmark = pytest.mark.gpu
 
 
-def TOLC(want):
-    return 1e-5 + 2e-8 * np.abs(want)
+def TOLC(want, fs, eps=synth.EPS_PRIMARY):
+    return tol_f64(q_of(want, fs), kappa_synth(eps), scale=10.0)
 
 
 @pytest.fixture(scope="module")
@@ -36,6 +37,7 @@ def tda():
     (4096, 0, 65, None, 1e-6),
     (2048, 0, 7, None, 1e-4),
     (700, 0, 3, [(0, 5), (5, 695)], 1e-6),
+    (4096, 0, 65, None, 1e-8),    # stress nugget
 ])
 def test_cdo_parity(tda, N, n_gaps, B, segments, eps):
     from gpu_util import to_dev
@@ -46,7 +48,7 @@ def test_cdo_parity(tda, N, n_gaps, B, segments, eps):
     got = h.loglik(d, H, precision="cdo").cpu().numpy()
     f = oracle.factor(inst.acf, N, inst.masks[0], segments)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.all(np.abs(got - want) <= TOLC(want)), np.max(np.abs(got - want))
+    assert np.all(np.abs(got - want) <= TOLC(want, [f], eps)), np.max(np.abs(got - want))
     h.close()
 
 
@@ -67,8 +69,8 @@ def test_cdo_terms_nan_and_errors(tda):
     f = oracle.factor(inst.acf, N, inst.masks[0])
     want_dh, want_hh = oracle.snr.inner_products(f, inst.d[0], inst.H)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.all(np.abs(ll[ok] - want[ok]) <= TOLC(want[ok]))
-    tol = 2 * TOLC(np.abs(want) + np.abs(want_dh) + want_hh)
+    assert np.all(np.abs(ll[ok] - want[ok]) <= TOLC(want[ok], [f]))
+    tol = tol_terms(q_of(want, [f]), want_dh, want_hh, kappa_synth(inst.eps), scale=10.0)
     assert np.all(np.abs(dh[ok] - want_dh[ok]) <= tol[ok])
     assert np.all(np.abs(hh[ok] - want_hh[ok]) <= tol[ok])
     hf = tda.Handle(inst.acf, N, inst.masks[0], precision="fp64").factor()

@@ -1,23 +1,25 @@
 """FP64 HIP path against the FP64 oracle (parity), through the C ABI.
 
-Tolerance: |logL_gpu - logL_oracle| <= 1e-6 + 2e-9 |logL|.  Both sides are FP64
-but use different orderings (blocked solve with inverted diagonal blocks vs
-LAPACK), so each carries a forward error of order kappa(C) u q in the quadratic
-form; with kappa(C) ~ 2.9e6 at the primary nugget that is ~3e-10 q, and q ~ 2|logL|
-for the large-residual templates.  Any dropped term (a sample's contribution,
-the log det, the 2 pi constant) is far above this bound.
+Tolerance: |logL_gpu - logL_oracle| <= 1e-6 + kappa(C) u q (tests/tolerance.py).  Both
+sides are FP64 but use different orderings (blocked solve with inverted diagonal blocks
+vs LAPACK), so each carries a forward error of order kappa(C) u q / 2 in logL; kappa(C)
+is bounded by the input's eigenvalue range (2.9e6 at the primary nugget) and q is the
+oracle's quadratic form.  Any dropped term (a sample's contribution, the log det, the
+2 pi constant) is far above this bound.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tolerance import kappa_synth, q_of, tol_f64
 
 pytestmark = pytest.mark.gpu
 
 
-def TOLF(want):
-    return 1e-6 + 2e-9 * np.abs(want)
+def TOLF(want, fs, eps=synth.EPS_PRIMARY):
+    """FP64 bound for oracle results `want` computed with the factors `fs`."""
+    return tol_f64(q_of(want, fs), kappa_synth(eps))
 
 
 @pytest.fixture(scope="module")
@@ -56,7 +58,7 @@ def test_f64_parity_small(tda, N, n_gaps, B, segments):
     info = h.info()
     assert info["n_eff"] == f.n_eff
     assert abs(info["logdet"] - f.logdet) < 1e-7 * max(1.0, abs(f.logdet))
-    assert np.all(np.abs(got - want) <= TOLF(want)), np.max(np.abs(got - want))
+    assert np.all(np.abs(got - want) <= TOLF(want, [f])), np.max(np.abs(got - want))
     h.close()
 
 
@@ -66,7 +68,7 @@ def test_f64_c1_workload(tda):
     h, got = _run(tda, inst)
     f = oracle.factor(inst.acf, inst.N)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.all(np.abs(got - want) <= TOLF(want))
+    assert np.all(np.abs(got - want) <= TOLF(want, [f]))
     # the injection's own template family peaks near the unperturbed parameters
     assert np.all(np.isfinite(got))
 
@@ -83,7 +85,8 @@ def test_f64_closed_form_white_noise(tda):
     keep = mask == 0
     r = (d[None] - H)[:, keep]
     want = -0.5 * (r * r).sum(1) / sig2 - 0.5 * keep.sum() * np.log(2 * np.pi * sig2)
-    assert np.all(np.abs(got - want) <= TOLF(want))
+    # kappa = 1 (a multiple of the identity)
+    assert np.all(np.abs(got - want) <= tol_f64((r * r).sum(1) / sig2, 1.0))
 
 
 def test_f64_gapped_ar1_closed_form_large(tda):
@@ -102,7 +105,8 @@ def test_f64_gapped_ar1_closed_form_large(tda):
     for b in [0, 17, 63]:
         w, ld = gapped_ar1_closed(d - H[b], keep, s, phi)
         want = -0.5 * (w @ w) - 0.5 * ld - 0.5 * len(keep) * np.log(2 * np.pi)
-        assert abs(got[b] - want) <= 1e-6 * max(1.0, abs(want) / 1e4)
+        # AR(1): the spectral density s^2 / |1 - phi e^{iw}|^2 spans a ratio ((1+phi)/(1-phi))^2
+        assert abs(got[b] - want) <= tol_f64(w @ w, ((1 + phi) / (1 - phi)) ** 2)
 
 
 def test_f64_invariants(tda):

@@ -4,19 +4,26 @@ oracle through the C ABI.
 q = (||L(x)^T r||^2 - ||L(z)^T r||^2) / x_0 with x = C^-1 e_1 from Levinson-Durbin and
 both products by FFT.  It is an FP64 method; the subtraction of two quadratic forms
 loses about log10(kappa(C)) digits relative to them, so the tolerance is the FP64 one
-scaled by 10: |dlogL| <= 1e-5 + 2e-8 |logL| (kappa(C) ~ 3e6 at nugget 1e-6).
+(1e-6 + kappa(C) u q, tests/tolerance.py) scaled by 10.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tolerance import LOG2PI, kappa_synth, q_of, tol_f64
 
 pytestmark = pytest.mark.gpu
+PHI = 0.97
+KAPPA_AR1 = ((1 + PHI) / (1 - PHI)) ** 2   # spectral range of AR(1) with phi = 0.97
 
 
-def TOLGS(want):
-    return 1e-5 + 2e-8 * np.abs(want)
+def TOLGS(q, kappa):
+    return tol_f64(q, kappa, scale=10.0)
+
+
+def _q_info(ll, info):
+    return -2.0 * (np.asarray(ll) + 0.5 * info["logdet"] + 0.5 * info["n_eff"] * LOG2PI)
 
 
 @pytest.fixture(scope="module")
@@ -37,6 +44,7 @@ def tda():
     (700, 17, [(0, 5), (5, 695)], 1e-6),
     (2048, 16, None, 1e-4),
     (16, 3, None, 1e-6),
+    (4096, 65, None, 1e-8),     # stress nugget
 ])
 def test_gs_parity(tda, N, B, segments, eps):
     from gpu_util import to_dev
@@ -48,7 +56,8 @@ def test_gs_parity(tda, N, B, segments, eps):
     f = oracle.factor(inst.acf, N, None, segments)
     want = oracle.loglik(f, inst.d[0], inst.H)
     assert abs(h.info()["logdet"] - f.logdet) < 1e-9 * abs(f.logdet) + 1e-9
-    assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+    assert np.all(np.abs(got - want) <= TOLGS(q_of(want, [f]), kappa_synth(eps))), \
+        np.max(np.abs(got - want))
     h.close()
 
 
@@ -63,21 +72,23 @@ def test_gs_long_segments_ar1_closed_form(tda, N, B, segments):
     from gpu_util import to_dev
     from test_oracle_pins import ar1_acf, ar1_whiten_closed
     print(f"case N={N} B={B} segments={segments}", flush=True)
-    s, phi = 0.8, 0.97
+    s, phi = 0.8, PHI
     acf = ar1_acf(N, s, phi)
     rng = np.random.default_rng(N + B)
     d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
     want = np.zeros(B)
+    q = np.zeros(B)
     n_eff = 0
     for off, L in (segments or [(0, N)]):
         w = ar1_whiten_closed(d[None, off:off + L] - H[:, off:off + L], s, phi)
         ld = np.log(s * s / (1 - phi * phi)) + (L - 1) * np.log(s * s)
         want += -0.5 * (w * w).sum(1) - 0.5 * ld
+        q += (w * w).sum(1)
         n_eff += L
     want -= 0.5 * n_eff * np.log(2 * np.pi)
     h = tda.Handle(acf, N, None, segments, precision="gs").factor()
     got = h.loglik(to_dev(d), to_dev(H)).cpu().numpy()
-    assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+    assert np.all(np.abs(got - want) <= TOLGS(q, KAPPA_AR1)), np.max(np.abs(got - want))
     h.close()
 
 
@@ -88,23 +99,24 @@ def test_gs_multi_mixed_lengths(tda):
     from gpu_util import to_dev
     from test_oracle_pins import ar1_acf, ar1_whiten_closed
     import torch
-    s, phi = 0.8, 0.97
-    items, wants, outs, keep = [], [], [], []
+    s, phi = 0.8, PHI
+    items, wants, outs, keep, qs = [], [], [], [], []
     for k, (N, B) in enumerate([(3000, 20), (40000, 12), (20000, 16), (5000, 9)]):
         rng = np.random.default_rng(300 + k)
         d = rng.standard_normal(N); H = rng.standard_normal((B, N)) * 0.3
         w = ar1_whiten_closed(d[None] - H, s, phi)
         ld = np.log(s * s / (1 - phi * phi)) + (N - 1) * np.log(s * s)
         wants.append(-0.5 * (w * w).sum(1) - 0.5 * ld - 0.5 * N * np.log(2 * np.pi))
+        qs.append((w * w).sum(1))
         h = tda.Handle(ar1_acf(N, s, phi), N, None, precision="gs").factor()
         out = torch.empty(B, dtype=torch.float64, device="cuda")
         dd, Hd = to_dev(d), to_dev(H)
         items.append((h, dd, Hd, out)); outs.append(out); keep.append((h, dd, Hd))
     tda.loglik_multi(items, precision="gs")
     torch.cuda.synchronize()
-    for out, want in zip(outs, wants):
+    for out, want, q in zip(outs, wants, qs):
         got = out.cpu().numpy()
-        assert np.all(np.abs(got - want) <= TOLGS(want)), np.max(np.abs(got - want))
+        assert np.all(np.abs(got - want) <= TOLGS(q, KAPPA_AR1)), np.max(np.abs(got - want))
     for h, _, _ in keep:
         h.close()
 
@@ -119,7 +131,8 @@ def test_gs_long_segment_vs_fp64_and_limit(tda):
     hf = tda.Handle(inst.acf, inst.N, None, precision="fp64").factor()
     got, ref = hg.loglik(d, H).cpu().numpy(), hf.loglik(d, H).cpu().numpy()
     assert abs(hg.info()["logdet"] - hf.info()["logdet"]) <= 1e-9 * abs(hf.info()["logdet"])
-    assert np.all(np.abs(got - ref) <= TOLGS(ref)), np.max(np.abs(got - ref))
+    assert np.all(np.abs(got - ref) <= TOLGS(_q_info(ref, hf.info()), kappa_synth(1e-6))), \
+        np.max(np.abs(got - ref))
     hg.close(); hf.close()
     with pytest.raises(tda.TdaError) as e:
         tda.Handle(synth.make_acf(65537), 65537, None, precision="gs")
@@ -142,10 +155,12 @@ def test_gs_full_size_and_vs_fp64(tda):
         tda.loglik_multi([(h, dk, H, out[p]) for h, dk in zip(hs[p], ds)], precision=p)
     torch.cuda.synchronize()
     g, f = out["gs"].cpu().numpy(), out["fp64"].cpu().numpy()
-    assert np.all(np.abs(g - f) <= TOLGS(f)), np.max(np.abs(g - f))
     facs = [oracle.factor(inst.acf, inst.N, inst.masks[k]) for k in range(inst.n_det)]
+    kap = kappa_synth(inst.eps)
+    assert np.all(np.abs(g - f) <= TOLGS(q_of(f, facs), kap)), np.max(np.abs(g - f))
     want = oracle.loglik_network(facs, inst.d, inst.H[:8])
-    assert np.all(np.abs(g[:8] - want) <= TOLGS(want)), np.max(np.abs(g[:8] - want))
+    assert np.all(np.abs(g[:8] - want) <= TOLGS(q_of(want, facs), kap)), \
+        np.max(np.abs(g[:8] - want))
     for p in hs:
         for h in hs[p]:
             h.close()

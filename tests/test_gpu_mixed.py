@@ -3,21 +3,23 @@ multi-item batched path, against the FP64 oracle through the C ABI.
 
 Mixed tolerance: |logL_mixed - logL_oracle| <= 1e-3 (the accuracy target of the
 mixed path).  The refined quadratic form never exceeds the exact one, so
-logL_mixed >= logL_oracle - tol_f64 (variational bound; tol_f64 = 1e-6 + 2e-9|logL|
-covers the FP64 forward error of both sides, see test_gpu_f64).
+logL_mixed >= logL_oracle - tol_f64 (variational bound; tol_f64 = 1e-6 + kappa(C) u q
+covers the FP64 forward error of both sides, see tests/tolerance.py).
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tolerance import kappa_synth, q_of, tol_f64
 
 pytestmark = pytest.mark.gpu
 TOL_MIXED = 1e-3
 
 
-def TOLF(want):
-    return 1e-6 + 2e-9 * np.abs(want)
+def TOLF(want, fs, eps=synth.EPS_PRIMARY):
+    """FP64 bound for oracle results `want` computed with the factors `fs`."""
+    return tol_f64(q_of(want, fs), kappa_synth(eps))
 
 
 @pytest.fixture(scope="module")
@@ -30,10 +32,10 @@ def tda():
     return tda
 
 
-def _check_mixed(got, want):
+def _check_mixed(got, want, fs, eps=synth.EPS_PRIMARY):
     err = got - want
     assert np.max(np.abs(err)) <= TOL_MIXED, np.max(np.abs(err))
-    assert np.all(err >= -TOLF(want)), np.min(err)
+    assert np.all(err >= -TOLF(want, fs, eps)), np.min(err)
 
 
 @pytest.mark.parametrize("N,n_gaps,B,segments,eps", [
@@ -42,6 +44,8 @@ def _check_mixed(got, want):
     (2600, 1, 130, [(0, 1000), (1200, 1300), (2550, 50)], 1e-6),
     (4096, 0, 64, None, 1e-6),
     (2048, 0, 16, None, 1e-4),
+    (4096, 0, 64, None, 1e-7),     # kappa(C) up to 2.9e7: the mixed path's documented limit
+    (3000, 2, 100, None, 1e-7),
 ])
 def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
     from gpu_util import to_dev
@@ -54,15 +58,120 @@ def test_mixed_parity(tda, N, n_gaps, B, segments, eps):
     f64 = h.loglik(d, H, precision="fp64").cpu().numpy()
     f = oracle.factor(inst.acf, N, inst.masks[0], segments)
     want = oracle.loglik(f, inst.d[0], inst.H)
-    assert np.all(np.abs(f64 - want) <= TOLF(want))
-    _check_mixed(got, want)
+    assert np.all(np.abs(f64 - want) <= TOLF(want, [f], eps))
+    _check_mixed(got, want, [f], eps)
     # data cache: new data pointer is picked up, same pointer reuses the cache
     d2 = to_dev(inst.d[0][::-1].copy())
     got2 = h.loglik(d2, H).cpu().numpy()
     want2 = oracle.loglik(f, inst.d[0][::-1].copy(), inst.H)
-    _check_mixed(got2, want2)
+    _check_mixed(got2, want2, [f], eps)
     torch.cuda.synchronize()
     h.close()
+
+
+@pytest.mark.parametrize("N,n_gaps,B", [(4096, 0, 64), (3000, 2, 100)])
+def test_mixed_beyond_its_limit_stress_nugget(tda, N, n_gaps, B):
+    """Stress nugget 1e-8 (kappa(C) up to 2.9e8), beyond the mixed path's documented limit
+    (kappa about 3e7): the FP64 evaluation still meets its bound against the oracle, while
+    the mixed one loses the 1e-3 target because the FP64 refinement's FFT Toeplitz product
+    carries a rounding error of order u lambda_max ||y0||^2, and ||y0|| = ||C^-1 h|| grows
+    like 1/eps for templates that leak into the zero band below 20 Hz.  The test pins the
+    size of that loss (measured 0.11 and 0.05 here, 0.03 at two detectors x 16384)."""
+    from gpu_util import to_dev
+    import torch
+    eps = synth.EPS_STRESS
+    print(f"case N={N} gaps={n_gaps} B={B} eps={eps}", flush=True)
+    inst = synth.random_rhs_case(200 + N + B, N, 1, n_gaps, B, eps=eps)
+    h = tda.Handle(inst.acf, N, inst.masks[0], precision="mixed").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    got = h.loglik(d, H).cpu().numpy()
+    f64 = h.loglik(d, H, precision="fp64").cpu().numpy()
+    f = oracle.factor(inst.acf, N, inst.masks[0])
+    want = oracle.loglik(f, inst.d[0], inst.H)
+    assert np.all(np.abs(f64 - want) <= TOLF(want, [f], eps))
+    err = np.abs(got - want)
+    print(f"mixed vs oracle at eps {eps:g}: max {err.max():.3e}, median {np.median(err):.3e}",
+          flush=True)
+    assert np.all(np.isfinite(got)) and err.max() <= 0.25
+    torch.cuda.synchronize()
+    h.close()
+
+
+def test_data_cache_fingerprint(tda):
+    """The whitened-data cache is keyed by a device fingerprint of the retained samples:
+    new contents at the cached address (in place) are re-whitened, in single calls, batched
+    calls and captured plans; values at excluded samples do not count."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(88, 2500, 1, 2, 40)
+    mask = inst.masks[0]
+    f = oracle.factor(inst.acf, inst.N, mask)
+    h = tda.Handle(inst.acf, inst.N, mask, precision="mixed").factor()
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    base = h.loglik(d, H).cpu().numpy()
+    _check_mixed(base, oracle.loglik(f, inst.d[0], inst.H), [f])
+    rng = np.random.default_rng(3)
+    new = inst.d[0] + 0.5 * rng.standard_normal(inst.N)
+    want_new = oracle.loglik(f, new, inst.H)
+    # in place, same pointer, no tda_set_data
+    d.copy_(torch.from_numpy(new))
+    got = h.loglik(d, H).cpu().numpy()
+    _check_mixed(got, want_new, [f])
+    # NaN at an excluded sample: same fingerprint, same bits
+    d[int(np.flatnonzero(mask)[0])] = float("nan")
+    np.testing.assert_array_equal(h.loglik(d, H).cpu().numpy(), got)
+    # a fresh tensor at a new address holding the old data, then in place again in a plan
+    d0 = to_dev(inst.d[0])
+    np.testing.assert_array_equal(h.loglik(d0, H).cpu().numpy(), base)
+    out = torch.empty(40, dtype=torch.float64, device="cuda")
+    plan = tda.Plan([(h, d0, H, out)], precision="mixed")
+    stream = torch.cuda.Stream()
+    for k, x in enumerate([inst.d[0], new, inst.d[0]]):
+        d0.copy_(torch.from_numpy(x))
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.execute(stream=stream, graph=True)
+        stream.synchronize()
+        r = out.cpu().numpy()
+        if k == 1:
+            _check_mixed(r, want_new, [f])
+        else:
+            np.testing.assert_array_equal(r, base)
+    plan.close()
+    # batched call after an in-place change
+    d0.copy_(torch.from_numpy(new))
+    tda.loglik_multi([(h, d0, H, out)], precision="mixed")
+    torch.cuda.synchronize()
+    _check_mixed(out.cpu().numpy(), want_new, [f])
+    h.close()
+
+
+@pytest.mark.parametrize("allocator", ["torch", "hip"])
+def test_handle_memory_from_caller_allocator(tda, allocator):
+    """With the torch allocator (the default) every device buffer of a handle comes from
+    PyTorch's caching allocator: torch's allocated bytes grow by the handle's
+    device_bytes and return on close.  With hipMalloc they do not move."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(90, 3000, 1, 1, 300)
+    d, H = to_dev(inst.d[0]), to_dev(inst.H)
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision="mixed",
+                   allocator=allocator).factor()
+    got = h.loglik(d, H).cpu().numpy()
+    torch.cuda.synchronize()
+    held = h.info()["device_bytes"]
+    grown = torch.cuda.memory_allocated() - m0
+    if allocator == "torch":
+        assert held > 0 and grown == held, (grown, held)
+    else:
+        assert grown == 0, grown
+    f = oracle.factor(inst.acf, inst.N, inst.masks[0])
+    _check_mixed(got, oracle.loglik(f, inst.d[0], inst.H), [f])
+    h.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
 
 
 def _ar1_white_closed(X, keep, s, phi):
@@ -148,7 +257,7 @@ def test_small_batch_after_full_batch(tda, monkeypatch, variant):
     f = oracle.factor(inst.acf, inst.N, inst.masks[0])
     for B in (96, 1, 129):
         got = h.loglik(d, to_dev(inst.H[:B])).cpu().numpy()
-        _check_mixed(got, oracle.loglik(f, inst.d[0], inst.H[:B]))
+        _check_mixed(got, oracle.loglik(f, inst.d[0], inst.H[:B]), [f])
     torch.cuda.synchronize()
     h.close()
 
@@ -173,7 +282,7 @@ def test_product_variants(tda, monkeypatch, N, n_gaps, B, segments):
         monkeypatch.setenv("TDA_PRODUCT_VARIANT", str(v))
         outs[v] = h.loglik(d, H).cpu().numpy()
         torch.cuda.synchronize()
-        _check_mixed(outs[v], want)
+        _check_mixed(outs[v], want, [f])
     for v in (2, 4, 5):
         np.testing.assert_array_equal(outs[v], outs[1])
     h.close()
@@ -206,7 +315,7 @@ def test_multi_ragged_instances(tda, precision):
     import torch
     rng = np.random.default_rng(41)
     specs = [(1500, 2, 1, 40), (3000, 1, 0, 70), (800, 1, 2, 130), (2300, 2, 1, 33)]
-    items, wants, outs, keep = [], [], [], []
+    items, wants, outs, keep, facs = [], [], [], [], []
     for k, (N, n_det, n_gaps, B) in enumerate(specs):
         inst = synth.random_rhs_case(500 + k, N, n_det, n_gaps, B)
         out = torch.empty(B, dtype=torch.float64, device="cuda")
@@ -219,16 +328,17 @@ def test_multi_ragged_instances(tda, precision):
             keep.append((h, dd))
             fs.append(oracle.factor(inst.acf, N, inst.masks[det]))
         wants.append(oracle.loglik_network(fs, inst.d, inst.H))
+        facs.append(fs)
         outs.append(out)
         keep.append(Hd)
     tda.loglik_multi(items, precision=precision)
     torch.cuda.synchronize()
-    for out, want in zip(outs, wants):
+    for out, want, fs in zip(outs, wants, facs):
         got = out.cpu().numpy()
         if precision == "fp64":
-            assert np.all(np.abs(got - want) <= TOLF(want))
+            assert np.all(np.abs(got - want) <= TOLF(want, fs))
         else:
-            _check_mixed(got, want)
+            _check_mixed(got, want, fs)
 
 
 def test_multi_long_segments(tda):
@@ -296,7 +406,7 @@ def test_multi_shared_template_split(tda):
         single = h.loglik(d, Hk).cpu().numpy()
         np.testing.assert_allclose(o.cpu().numpy(), single, rtol=0, atol=1e-9)
     f = oracle.factor(inst.acf, inst.N, mask)
-    _check_mixed(outs[1].cpu().numpy(), oracle.loglik(f, inst.d[1], inst.H))
+    _check_mixed(outs[1].cpu().numpy(), oracle.loglik(f, inst.d[1], inst.H), [f])
     for h in hs:
         h.close()
 
@@ -384,12 +494,12 @@ def test_scale_invariance(tda, precision):
     n_eff = h1.info()["n_eff"]
     assert abs(h2.info()["logdet"] - h1.info()["logdet"] - n_eff * np.log(s)) < 1e-9 * n_eff * abs(np.log(s))
     want = base - 0.5 * n_eff * np.log(s)
-    tol = TOL_MIXED if precision == "mixed" else 1e-6 + 2e-9 * np.abs(want)
-    assert np.max(np.abs(scaled - want) - tol) <= 0, np.max(np.abs(scaled - want))
-    # and against the oracle on the scaled inputs
+    # the oracle on the scaled inputs (its quadratic forms set the FP64 bound)
     f = oracle.factor(inst.acf * s, inst.N, inst.masks[0])
     ref = oracle.loglik(f, inst.d[0] * np.sqrt(s), inst.H * np.sqrt(s))
-    tol_o = TOL_MIXED if precision == "mixed" else TOLF(ref)
+    tol = TOL_MIXED if precision == "mixed" else TOLF(ref, [f])
+    assert np.max(np.abs(scaled - want) - tol) <= 0, np.max(np.abs(scaled - want))
+    tol_o = TOL_MIXED if precision == "mixed" else TOLF(ref, [f])
     assert np.all(np.abs(scaled - ref) <= tol_o), np.max(np.abs(scaled - ref))
     h1.close()
     h2.close()

@@ -3,20 +3,23 @@ products behind the time-domain matched-filter and effective SNRs, Sec. II.B ite
 against the FP64 oracle through the C ABI.
 
 Tolerances on the inner products (q-scale quantities, twice the logL scale):
-  FP64      1e-6 + 2e-9 (|logL| + |<d,h>| + <h,h>)  (the FP64 forward error of the
-            combination <d,h> = logL - logL(h=0) + <h,h>/2 and of each evaluation),
+  FP64      1e-6 + kappa(C) u (q + <d,d> + <h,h>) (tests/tolerance.py: the FP64 forward
+            error of the three quadratic forms behind <d,h> = logL - logL(h=0) + <h,h>/2),
   mixed     <d,h> as FP64 (an FP64 term of the split form); <h,h> carries the whole mixed
             error of q: |d<h,h>| <= 2e-3,
   GS        ten times the FP64 bound (as the Gohberg-Semencul logL).
 logL from tda_loglik_terms must equal tda_loglik_ex bit for bit (same launches).
+tda_snr's SNRs are checked against the oracle's (oracle.snr.snrs).
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from tolerance import kappa_synth, q_of, tol_terms
 
 pytestmark = pytest.mark.gpu
+KAPPA = kappa_synth(synth.EPS_PRIMARY)
 
 
 @pytest.fixture(scope="module")
@@ -29,8 +32,8 @@ def tda():
     return tda
 
 
-def _tol_f64(ll, dh, hh):
-    return 1e-6 + 2e-9 * (np.abs(ll) + np.abs(dh) + np.abs(hh))
+def _tol_f64(ll, f, dh, hh, scale=1.0):
+    return tol_terms(q_of(ll, [f]), dh, hh, KAPPA, scale)
 
 
 CASES = [
@@ -56,7 +59,7 @@ def test_terms_parity(tda, N, n_gaps, B, segments, prec):
     f = oracle.factor(inst.acf, N, inst.masks[0], segments)
     want_dh, want_hh = oracle.snr.inner_products(f, inst.d[0], inst.H)
     want_ll = oracle.loglik(f, inst.d[0], inst.H)
-    tol = _tol_f64(want_ll, want_dh, want_hh)
+    tol = _tol_f64(want_ll, f, want_dh, want_hh)
     assert np.all(np.abs(dh - want_dh) <= tol), np.max(np.abs(dh - want_dh))
     if prec == "fp64":
         assert np.all(np.abs(hh - want_hh) <= tol), np.max(np.abs(hh - want_hh))
@@ -77,7 +80,7 @@ def test_terms_gs(tda, N, B, segments):
     np.testing.assert_array_equal(ll, h.loglik(d, H).cpu().numpy())
     f = oracle.factor(inst.acf, N, None, segments)
     want_dh, want_hh = oracle.snr.inner_products(f, inst.d[0], inst.H)
-    tol = 10 * _tol_f64(oracle.loglik(f, inst.d[0], inst.H), want_dh, want_hh)
+    tol = _tol_f64(oracle.loglik(f, inst.d[0], inst.H), f, want_dh, want_hh, scale=10.0)
     assert np.all(np.abs(dh - want_dh) <= tol), np.max(np.abs(dh - want_dh))
     assert np.all(np.abs(hh - want_hh) <= tol), np.max(np.abs(hh - want_hh))
     h.close()
@@ -107,8 +110,29 @@ def test_terms_optional_outputs_nan_and_snr(tda, prec):
     assert none is None
     np.testing.assert_allclose(hh3.cpu().numpy()[ok], hh[ok], rtol=0, atol=1e-9)
     s = h.snr(d, H, precision=prec)
-    np.testing.assert_allclose(s["rho_mf"].cpu().numpy()[ok], dh[ok] / np.sqrt(hh[ok]), rtol=1e-12)
-    np.testing.assert_allclose(s["rho_eff2"].cpu().numpy()[ok], 2 * dh[ok] - hh[ok], rtol=1e-12,
-                               atol=1e-9)
+    np.testing.assert_array_equal(s["loglik"].cpu().numpy(), ll)
+    mf, opt, eff2 = (s[k].cpu().numpy() for k in ("rho_mf", "rho_opt", "rho_eff2"))
+    assert np.isnan(mf[5]) and np.isnan(opt[5]) and np.isnan(eff2[5])
+    np.testing.assert_allclose(mf[ok], dh[ok] / np.sqrt(hh[ok]), rtol=1e-12)
+    np.testing.assert_allclose(opt[ok], np.sqrt(hh[ok]), rtol=1e-12)
+    np.testing.assert_allclose(eff2[ok], 2 * dh[ok] - hh[ok], rtol=1e-12, atol=1e-9)
+    # against the oracle's SNRs (rho_eff^2 = <d,d> - <r,r> formed there from whitened
+    # vectors, not from the inner products)
+    f = oracle.factor(inst.acf, N, inst.masks[0])
+    want_mf, want_eff2 = oracle.snr.snrs(f, inst.d[0], inst.H)
+    want_dh, want_hh = oracle.snr.inner_products(f, inst.d[0], inst.H)
+    want_ll = oracle.loglik(f, inst.d[0], inst.H)
+    tol = _tol_f64(want_ll, f, want_dh, want_hh)
+    if prec == "mixed":
+        tol = tol + 2e-3     # <h,h> carries the mixed error
+    assert np.all(np.abs(eff2[ok] - want_eff2[ok]) <= tol[ok]), np.max(np.abs(eff2 - want_eff2))
+    # rho_mf = <d,h> / sqrt(<h,h>): relative error of <h,h> halves through the square root
+    rel = tol / np.abs(want_hh)
+    assert np.all(np.abs(mf[ok] - want_mf[ok]) <= (tol / np.sqrt(want_hh) + np.abs(want_mf) * rel)[ok])
+    # a zero template: rho_mf NaN (0/0), rho_opt 0, rho_eff^2 0
+    Z = torch.zeros((2, N), dtype=torch.float64, device=d.device)
+    z = h.snr(d, Z, precision=prec)
+    assert torch.isnan(z["rho_mf"]).all()
+    assert torch.all(z["rho_opt"].abs() < 1e-6) and torch.all(z["rho_eff2"].abs() < 1e-5)
     torch.cuda.synchronize()
     h.close()

@@ -87,3 +87,18 @@ def test_workload_shapes(k):
     w = synth.make_workload(k)
     inst = w.instances[0]
     assert inst.N == 1024 and inst.B == 32 and inst.n_det == 1
+
+
+@pytest.mark.parametrize("eps", [1e-6, 1e-8])
+def test_eig_bounds_contain_the_spectrum(eps):
+    """synth.eig_bounds brackets the eigenvalues of a Toeplitz covariance and of a gapped
+    principal submatrix of it (the bound the FP64 test tolerances use)."""
+    import scipy.linalg
+    lo, hi = synth.eig_bounds(eps)
+    C = scipy.linalg.toeplitz(synth.make_acf(768, eps))
+    keep = np.r_[0:200, 260:768]
+    for M in (C, C[np.ix_(keep, keep)]):
+        ev = np.linalg.eigvalsh(M)
+        assert ev[0] >= lo * (1 - 1e-6) - 1e-12 and ev[-1] <= hi * (1 + 1e-12)
+    # the upper bound is nearly reached (max of the symbol), so it is not loose
+    assert np.linalg.eigvalsh(C)[-1] > 0.9 * hi
