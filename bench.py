@@ -76,6 +76,97 @@ def _pct(x, p):
     return float(np.percentile(np.asarray(x), p))
 
 
+def host_cpu():
+    """Physical cores (lscpu core/socket pairs), logical CPUs, the CPUs this process may
+    use, and the BLAS library numpy/scipy call (threadpoolctl)."""
+    import subprocess
+    info = {"logical_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True, text=True,
+                             timeout=10).stdout
+        pairs = {tuple(l.split(",")) for l in out.splitlines() if l and not l.startswith("#")}
+        info["physical_cores"] = len(pairs) or None
+    except Exception:
+        info["physical_cores"] = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        info["blas"] = [{"library": i.get("internal_api"), "version": i.get("version"),
+                         "threads": i.get("num_threads"), "arch": i.get("architecture")}
+                        for i in blas]
+    except Exception:
+        info["blas"] = None
+    return info
+
+
+_POOL = {}
+
+
+def _pool_init(paths, d_np):
+    """Worker set-up: the oracle's factors, memory-mapped from files the parent wrote."""
+    import oracle
+    fs = []
+    for p in paths:
+        meta = json.load(open(p + ".json"))
+        Ls = [np.load(f"{p}.L{k}.npy", mmap_mode="r") for k in range(meta["n_seg"])]
+        idx = [np.load(f"{p}.idx{k}.npy") for k in range(meta["n_seg"])]
+        fs.append(oracle.Factor(meta["N"], [tuple(x) for x in meta["segments"]], idx, Ls,
+                                meta["logdet"], meta["n_eff"]))
+    _POOL["fs"], _POOL["d"] = fs, d_np
+
+
+def _pool_eval(h_row):
+    """One template per call, every detector (the paper's recommended CPU set-up)."""
+    import oracle
+    return float(oracle.loglik_network(_POOL["fs"], _POOL["d"], h_row[None, :])[0])
+
+
+def cpu_pool_baseline(inst, fs, sample, n_proc):
+    """The oracle in a process pool of n_proc single-threaded workers, one template per call
+    (Sec. III.B, Sec. V: a pool of size equal to the cores, one BLAS thread each).  The
+    factors go to the workers through memory-mapped files (one copy in the page cache)."""
+    import multiprocessing as mp
+    import shutil
+    import tempfile
+    need = sum(L.nbytes for f in fs for L in f.L)
+    base = "/dev/shm" if shutil.disk_usage("/dev/shm").free > 2 * need else None
+    tmp = tempfile.mkdtemp(prefix="tda_pool_", dir=base)
+    try:
+        paths = []
+        for k, f in enumerate(fs):
+            p = os.path.join(tmp, f"det{k}")
+            for j, (L, idx) in enumerate(zip(f.L, f.idx)):
+                np.save(f"{p}.L{j}.npy", L)
+                np.save(f"{p}.idx{j}.npy", idx)
+            json.dump({"N": f.N, "segments": [list(x) for x in f.segments], "n_seg": len(f.L),
+                       "logdet": f.logdet, "n_eff": f.n_eff}, open(p + ".json", "w"))
+            paths.append(p)
+        env_keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+        saved = {k: os.environ.get(k) for k in env_keys}
+        for k in env_keys:
+            os.environ[k] = "1"
+        try:
+            ctx = mp.get_context("spawn")
+            with ctx.Pool(n_proc, initializer=_pool_init, initargs=(paths, inst.d)) as pool:
+                pool.map(_pool_eval, [inst.H[0]] * n_proc)  # warm-up: workers page L in
+                t = time.perf_counter()
+                ref = pool.map(_pool_eval, list(inst.H[:sample]), chunksize=1)
+                wall = time.perf_counter() - t
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return np.array(ref), {
+        "value": sample / wall, "unit": "evals/s", "cores": n_proc, "kind": "oracle",
+        "sample": f"{sample} of the {inst.B} templates x {inst.n_det} detectors, one template per "
+                  f"call in a pool of {n_proc} processes with one BLAS thread each",
+    }
+
+
 def cpu_baseline(inst, sample, fs_cache):
     """Time the FP64 oracle (as it is) on `sample` templates against both detectors."""
     import oracle
@@ -103,8 +194,9 @@ def cpu_baseline(inst, sample, fs_cache):
         "cores": int(cores),
         "kind": "oracle",
         "sample": f"{sample} of the {inst.B} templates x {inst.n_det} detectors, N={inst.N}, "
-                  f"{reps} repetitions after 1 warm-up; factorisation ({t_factor:.1f} s, "
-                  f"once per detector) excluded like on the GPU",
+                  f"{reps} repetitions after 1 warm-up of one batched triangular solve per "
+                  f"detector (BLAS threads = {threads or 'unknown'}); factorisation "
+                  f"({t_factor:.1f} s, once per detector) excluded like on the GPU",
         "factor_s": t_factor,
     }
 
@@ -165,6 +257,8 @@ def main():
     H = torch.from_numpy(inst.H).to(dev)
 
     setup = {}
+    tda.timing_read(reset=True)
+    tda.timing_enable(True)
     t0 = time.perf_counter()
     hs = [tda.Handle(inst.acf, inst.N, inst.masks[k], precision="mixed") for k in range(inst.n_det)]
     torch.cuda.synchronize()
@@ -179,8 +273,12 @@ def main():
         h.set_data(dk)
     torch.cuda.synchronize()
     setup["whitened_data_s"] = time.perf_counter() - t0
-    log("setup", setup)
+    tda.timing_enable(False)
+    kt_setup = tda.timing_read(reset=True)
     n_eff = [h.info()["n_eff"] for h in hs]
+    n_pad = [h.info()["n_pad"] for h in hs]
+    setup["one_time"] = one_time_costs(kt_setup, n_eff, n_pad)
+    log("setup", setup)
 
     out = {p: torch.empty(inst.B, dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
     items = {p: [(h, dk, H, out[p]) for h, dk in zip(hs, d)] for p in out}
@@ -237,7 +335,7 @@ def main():
         for h in hg:
             h.close()
 
-    acf_line = cdo = snr_terms = wres = None
+    acf_line = cdo = snr_terms = wres = stress = c3_line = None
     if not args.core_only:
         # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
         # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
@@ -338,6 +436,11 @@ def main():
         log("whitened residuals", wres)
         del W, out_w, ref_w
 
+        # the same workload at the stress nugget (kappa(C) up to 2.9e8), and the gapped
+        # one-detector N = 32768 workload (where the Gohberg-Semencul route cannot apply)
+        stress = stress_leg(args, tda, torch, synth, dev, log)
+        c3_line = run_c3(args, tda, torch, synth, dev, log, steps=5, fsteps=2)
+
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
 
@@ -347,10 +450,15 @@ def main():
     cnt, tot = kt_m[dom]
     alg_flops = float(sum(n * n for n in n_eff)) * inst.B
     achieved = alg_flops / (tot / cnt * 1e-3)
+    # frac: the dominant kernel alone (one product launch); step_frac: the whole step's
+    # algorithmic rate (the same N_eff^2 B flops over ms_per_step)
+    step_rate = alg_flops / (wall_m / args.steps)
     roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved / 1e12,
                 "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_BF16,
                 "traffic": profiled_traffic(dom), "traffic_unit": "bytes per launch",
-                "avg_ms": tot / cnt, "issued_frac": 3 * achieved / PEAK_BF16}
+                "avg_ms": tot / cnt, "issued_frac": 3 * achieved / PEAK_BF16,
+                "step_achieved": step_rate / 1e12, "step_frac": step_rate / PEAK_BF16,
+                "alg_flops_per_step": alg_flops}
     dom_f = "trsm_f64"
     cf, tf = kt_f[dom_f]
     ach_f = alg_flops / (tf / cf * 1e-3)
@@ -371,7 +479,10 @@ def main():
         "config": {"workload": f"two detectors x N={inst.N} (fs=4096 Hz), {inst.B} chirp templates "
                                f"per launch, analytic-PSD ACF + nugget {synth.EPS_PRIMARY:g}, no gaps",
                    "n_det": inst.n_det, "N": inst.N, "templates_per_launch": inst.B,
-                   "n_eff": n_eff},
+                   "n_eff": n_eff,
+                   "template_amplitudes": "network SNR 8-30 by the band-limited (20-2048 Hz) "
+                                          "frequency-domain convention; the time-domain h^T C^-1 h "
+                                          "the library evaluates is larger (sharp chirp ends)"},
         "latency_ms": {"p50": _pct(lat_m, 50), "p99": _pct(lat_m, 99),
                        "unit": "one launch of all templates"},
         "fp64": {"value": evals_f, "unit": "evals/s", "ms_per_step": wall_f / fsteps * 1e3,
@@ -385,6 +496,8 @@ def main():
         "acf_estimate": acf_line,
         "snr_terms": snr_terms,
         "whitened_residual": wres,
+        "accuracy_stress": stress,
+        "c3": c3_line,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
                      "templates_compared": int(inst.B)},
@@ -403,6 +516,16 @@ def main():
     if not args.no_cpu_baseline:
         fs = []
         ref, cb = cpu_baseline(inst, args.cpu_sample, fs)
+        cb["host"] = host_cpu()
+        n_proc = min([x for x in (cb["host"]["physical_cores"], cb["host"]["affinity_cpus"], 16)
+                      if x])
+        try:
+            ref_p, pool = cpu_pool_baseline(inst, fs, args.cpu_sample, n_proc)
+            pool["max_abs_dlogL_vs_batched_oracle"] = float(np.abs(ref_p - ref).max())
+            cb["pool"] = pool
+            log("cpu pool baseline", pool)
+        except Exception as e:  # reported, never fatal to the GPU line
+            cb["pool"] = {"error": repr(e)}
         line["cpu_baseline"] = cb
         line["accuracy"]["max_abs_dlogL_mixed_vs_oracle"] = float(np.abs(res_m[:len(ref)] - ref).max())
         line["accuracy"]["max_abs_dlogL_fp64_vs_oracle"] = float(np.abs(res_f[:len(ref)] - ref).max())
@@ -412,6 +535,27 @@ def main():
         h.close()
 
 
+def one_time_costs(kt, n_eff, n_pad):
+    """Assembly and Cholesky figures from the timed set-up launches: the assembly writes
+    n_pad^2 doubles per detector (the dense block, lower part used); the Cholesky does
+    N_eff^3 / 3 algorithmic flops per detector."""
+    res = {}
+    if "assemble" in kt:
+        c, t = kt["assemble"]
+        byts = float(sum(n * n for n in n_pad)) * 8.0
+        res["assembly"] = {"ms": t, "launches": c, "bytes": byts, "GB_per_s": byts / t * 1e-6,
+                           "frac_hbm_peak": byts / (t * 1e-3) / PEAK_HBM}
+    if "cholesky" in kt:
+        c, t = kt["cholesky"]
+        fl = float(sum(n ** 3 for n in n_eff)) / 3.0
+        res["cholesky"] = {"ms": t, "launches": c, "flops": fl, "TFLOP_per_s": fl / t * 1e-9,
+                           "frac_fp64_peak": fl / (t * 1e-3) / PEAK_FP64}
+    for k in ("data_check", "data_whiten"):
+        if k in kt:
+            res[k + "_ms"] = kt[k][1]
+    return res
+
+
 def _base_line(args, value, unit, wall, steps, config, dtype):
     return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
             "warmup": args.warmup, "ms_per_step": wall / max(steps, 1) * 1e3,
@@ -419,51 +563,152 @@ def _base_line(args, value, unit, wall, steps, config, dtype):
             "data": "synthetic", "config": config}
 
 
-def bench_c3(args, tda, torch, synth, dev, log):
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+def _gold(name):
+    """Stored oracle values for sampled templates (written by tests/golden/make_golden.py,
+    which calls only the oracle), or None."""
+    try:
+        return json.load(open(os.path.join(GOLD, f"{name}_sample.json")))
+    except OSError:
+        return None
+
+
+def stress_leg(args, tda, torch, synth, dev, log):
+    """Two detectors x N at smaller nuggets, down to the stress nugget 1e-8 (kappa(C) up to
+    2.9e8): mixed vs FP64 over every template at each nugget (where mixed stops meeting
+    1e-3), and at 1e-8 also Gohberg-Semencul and the explicit inverse vs FP64 and all paths
+    against the stored oracle rows."""
+    sweep, res = [], {}
+    for eps in (1e-7, 3e-8, synth.EPS_STRESS):
+        w = synth.c2_workload(eps=eps, B=args.templates, n=args.n)
+        inst = w.instances[0]
+        d = [torch.from_numpy(x).to(dev) for x in inst.d]
+        H = torch.from_numpy(inst.H).to(dev)
+        hs = [tda.Handle(inst.acf, inst.N, m, precision="mixed").factor() for m in inst.masks]
+        out = {p: torch.empty(inst.B, dtype=torch.float64, device=dev) for p in ("mixed", "fp64")}
+        for p in out:
+            tda.loglik_multi([(h, dk, H, out[p]) for h, dk in zip(hs, d)], precision=p)
+        torch.cuda.synchronize()
+        rm, rf = out["mixed"].cpu().numpy(), out["fp64"].cpu().numpy()
+        lo, hi = synth.eig_bounds(eps)
+        dm = np.abs(rm - rf)
+        pt = {"eps": eps, "kappa_bound": hi / lo,
+              "max_abs_dlogL_mixed_vs_fp64_gpu": float(dm.max()),
+              "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(dm, 99),
+              "templates_above_1e-3": int(np.sum(dm > 1e-3)),
+              "min_dlogL_mixed_minus_fp64": float((rm - rf).min())}
+        sweep.append(pt)
+        log("nugget", pt)
+        if eps == synth.EPS_STRESS:
+            t = time.perf_counter()
+            for _ in range(3):
+                tda.loglik_multi([(h, dk, H, out["mixed"]) for h, dk in zip(hs, d)],
+                                 precision="mixed")
+            torch.cuda.synchronize()
+            res = dict(pt)
+            res["templates_compared"] = int(inst.B)
+            res["mixed_ms_per_step"] = (time.perf_counter() - t) / 3 * 1e3
+            res["meets_1e-3_vs_fp64"] = bool(dm.max() <= 1e-3)
+            rc = sum(h.loglik(dk, H, precision="cdo") for h, dk in zip(hs, d)).cpu().numpy()
+            hg = [tda.Handle(inst.acf, inst.N, None, precision="gs").factor() for _ in hs]
+            og = torch.empty(inst.B, dtype=torch.float64, device=dev)
+            tda.loglik_multi([(h, dk, H, og) for h, dk in zip(hg, d)], precision="gs")
+            rg = og.cpu().numpy()
+            res["max_abs_dlogL_gs_vs_fp64_gpu"] = float(np.abs(rg - rf).max())
+            res["max_abs_dlogL_cdo_vs_fp64_gpu"] = float(np.abs(rc - rf).max())
+            gold = _gold("c2_stress")
+            if gold and gold["N"] == inst.N and gold["eps"] == eps and inst.B > max(gold["rows"]):
+                rows, want = np.array(gold["rows"]), np.array(gold["loglik"])
+                for k, r in (("mixed", rm), ("fp64", rf), ("gs", rg), ("cdo", rc)):
+                    res[f"max_abs_dlogL_{k}_vs_oracle"] = float(np.abs(r[rows] - want).max())
+                res["oracle_rows"] = len(rows)
+            for h in hg:
+                h.close()
+        for h in hs:
+            h.close()
+        del d, H
+    res["nugget_sweep"] = sweep
+    ok = [p["kappa_bound"] for p in sweep if p["max_abs_dlogL_mixed_vs_fp64_gpu"] <= 1e-3]
+    bad = [p["kappa_bound"] for p in sweep if p["max_abs_dlogL_mixed_vs_fp64_gpu"] > 1e-3]
+    res["mixed_meets_1e-3_up_to_kappa"] = max(ok) if ok else None
+    res["mixed_misses_1e-3_from_kappa"] = min(bad) if bad else None
+    log("stress nugget", res)
+    return res
+
+
+def run_c3(args, tda, torch, synth, dev, log, steps, fsteps):
     """One detector, N = 32768 with 3 gaps (the masked covariance C[mask, mask], one
     segment whose circulant refines with split transforms), 8192 templates per launch:
-    mixed and FP64 evaluations through the same handle."""
+    mixed and FP64 evaluations through the same handle, and the stored oracle rows."""
     t0 = time.perf_counter()
     w = synth.c3_workload()
     inst = w.instances[0]
     log(f"c3 inputs in {time.perf_counter() - t0:.1f} s")
     d = torch.from_numpy(inst.d[0]).to(dev)
     H = torch.from_numpy(inst.H).to(dev)
+    tda.timing_read(reset=True)
+    tda.timing_enable(True)
     t0 = time.perf_counter()
     h = tda.Handle(inst.acf, inst.N, inst.masks[0], precision="mixed").factor()
     h.set_data(d)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
-    log(f"c3 setup {setup:.1f} s, n_eff {h.info()['n_eff']}")
+    tda.timing_enable(False)
+    info = h.info()
+    one_time = one_time_costs(tda.timing_read(reset=True), [info["n_eff"]], [info["n_pad"]])
+    log(f"c3 setup {setup:.1f} s, n_eff {info['n_eff']}")
     res = {}
     for p in ("mixed", "fp64"):
         out = torch.empty(inst.B, dtype=torch.float64, device=dev)
-        for _ in range(args.warmup):
+        for _ in range(args.warmup if p == "mixed" else 1):
             h.loglik(d, H, out=out, precision=p)
         torch.cuda.synchronize()
         tda.timing_read(reset=True)
         tda.timing_enable(True)
-        steps = args.steps if p == "mixed" else max(2, args.steps // 4)
+        n = steps if p == "mixed" else fsteps
         t = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(n):
             h.loglik(d, H, out=out, precision=p)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         tda.timing_enable(False)
-        res[p] = (wall, steps, tda.timing_read(reset=True), out.cpu().numpy())
-        log(f"c3 {p}: {wall / steps * 1e3:.2f} ms/step")
+        res[p] = (wall, n, tda.timing_read(reset=True), out.cpu().numpy())
+        log(f"c3 {p}: {wall / n * 1e3:.2f} ms/step")
     h.close()
-    wall, steps, kt, rm = res["mixed"]
-    line = _base_line(args, inst.B * steps / wall, "evals/s", wall, steps,
-                      {"workload": f"one detector x N={inst.N} with 3 gaps (64-512 samples), "
-                                   f"{inst.B} chirp templates per launch"},
-                      "bf16x3+f64")
-    fw, fs, _, rf = res["fp64"]
-    line["fp64"] = {"value": inst.B * fs / fw, "unit": "evals/s", "ms_per_step": fw / fs * 1e3}
+    wall, n, kt, rm = res["mixed"]
+    fw, fn, _, rf = res["fp64"]
+    alg = float(info["n_eff"]) ** 2 * inst.B
+    line = {"value": inst.B * n / wall, "unit": "evals/s", "ms_per_step": wall / n * 1e3,
+            "steps": n,
+            "config": {"workload": f"one detector x N={inst.N} with 3 gaps (64-512 samples), "
+                                   f"{inst.B} chirp templates per launch", "n_eff": info["n_eff"]},
+            "fp64": {"value": inst.B * fn / fw, "unit": "evals/s", "ms_per_step": fw / fn * 1e3,
+                     "steps": fn},
+            "step_frac_bf16": alg / (wall / n) / PEAK_BF16,
+            "kernels_ms": {k: v[1] / v[0] for k, v in kt.items()},
+            "setup_s": setup, "one_time": one_time}
     line["speedup_mixed_vs_fp64"] = line["value"] / line["fp64"]["value"]
-    line["accuracy"] = {"max_abs_dlogL_mixed_vs_fp64_gpu": float(np.abs(rm - rf).max())}
-    line["kernels_ms"] = {k: v[1] / v[0] for k, v in kt.items()}
-    line["setup_s"] = setup
+    dm = np.abs(rm - rf)
+    line["accuracy"] = {"max_abs_dlogL_mixed_vs_fp64_gpu": float(dm.max()),
+                        "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(dm, 99)}
+    gold = _gold("c3")
+    if gold and gold["N"] == inst.N:
+        rows, want = np.array(gold["rows"]), np.array(gold["loglik"])
+        line["accuracy"]["max_abs_dlogL_mixed_vs_oracle"] = float(np.abs(rm[rows] - want).max())
+        line["accuracy"]["max_abs_dlogL_fp64_vs_oracle"] = float(np.abs(rf[rows] - want).max())
+        line["accuracy"]["oracle_rows"] = len(rows)
+    log("c3", line)
+    return line
+
+
+def bench_c3(args, tda, torch, synth, dev, log):
+    """The gapped one-detector workload alone (see run_c3)."""
+    c3 = run_c3(args, tda, torch, synth, dev, log, args.steps, max(2, args.steps // 4))
+    line = _base_line(args, c3["value"], "evals/s", c3["ms_per_step"] * c3["steps"] * 1e-3,
+                      c3["steps"], c3.pop("config"), "bf16x3+f64")
+    line.update({k: v for k, v in c3.items() if k not in ("value", "unit", "ms_per_step", "steps")})
     print(json.dumps(line), flush=True)
 
 
