@@ -264,6 +264,25 @@ tda_status tda_snr(tda_handle h, const double *d, const double *H, int64_t B, in
                    int32_t precision, void *hip_stream);
 
 /*
+ * tda_loglik_fp64_noalloc -- tda_loglik_ex with TDA_PREC_FP64, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same kernel, same results bit for bit; the solve's scratch
+ * (the solution rows of each 32-template column tile) is a fixed device array of
+ * 64 MiB held by every GPU the library runs on until the process ends, instead of the
+ * handle's workspace, and the call allocates nothing.  Needs
+ * ceil(B / 32) * 32 * n_pad * 8 bytes <= 64 MiB (n_pad from tda_info: at N = 16384 up to
+ * 512 templates per call); larger calls fail with EINVAL and a message giving the limit.
+ * Every call on one GPU shares that array: calls that overlap on one GPU (several
+ * streams or host threads, or several handles at once) race and must be serialised by
+ * the caller.  On a capturing stream the call neither waits for nor records the
+ * handle's earlier work (the caller orders it); otherwise as tda_loglik_ex.
+ * Errors: as tda_loglik_ex; ESTATE for handles without the FP64 factor (compact mixed,
+ * Gohberg-Semencul).
+ */
+tda_status tda_loglik_fp64_noalloc(tda_handle h, const double *d, const double *H, int64_t B,
+                                   int64_t ldh, double *out, void *hip_stream);
+
+/*
  * tda_whitened_residual -- the whitened residual of every template, the vector
  * whose squared norm is the quadratic form of logL (eq:td_like_whitened):
  *   wres[b * ldw + j] = (L^-1 (d - h_b))_j,  j < n_eff,

@@ -23,6 +23,7 @@ EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
     "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
     "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_fp64_noalloc",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
     "tda_server_create", "tda_server_add_dataset", "tda_server_submit", "tda_server_poll",
@@ -123,6 +124,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_loglik_ex.argtypes = [vp, vp, vp, i64, i64, vp, i32, vp]
     L.tda_loglik_terms.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, i32, vp]
     L.tda_snr.argtypes = [vp, vp, vp, i64, i64, vp, vp, vp, vp, i32, vp]
+    L.tda_loglik_fp64_noalloc.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     L.tda_whitened_residual.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
     L.tda_acf_estimate.argtypes = [vp, i64, i64, i32, i64, vp, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
@@ -137,7 +139,7 @@ def load_library(path: str = LIB_PATH):
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
               "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
               "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
-              "tda_timing_read"):
+              "tda_timing_read", "tda_loglik_fp64_noalloc"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -242,6 +244,14 @@ class Handle:
         p = self.precision if precision is None else _precision(precision)
         _check(_lib.tda_loglik_ex(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), p,
                                   _stream(stream)))
+        return out
+
+    def loglik_noalloc(self, d, H, out, stream=None):
+        """FP64 logL through tda_loglik_fp64_noalloc (no device allocation; `out` given)."""
+        if H.dim() != 2 or H.stride(1) != 1:
+            raise ValueError("H must be 2-D with contiguous rows")
+        _check(_lib.tda_loglik_fp64_noalloc(self._h, _ptr(d), _ptr(H), H.shape[0], H.stride(0),
+                                            _ptr(out), _stream(stream)))
         return out
 
     def loglik_terms(self, d, H, precision=None, want_dh=True, want_hh=True, stream=None):

@@ -14,6 +14,14 @@
 
 using namespace tda;
 
+// Scratch of the allocation-free FP64 evaluation (tda_loglik_fp64_noalloc): the solution
+// rows of its column tiles.  A fixed device array; every GPU the library runs on holds its
+// own copy until the process ends.  Host code takes its per-device address from
+// hipGetSymbolAddress and never uses the array's name as an address.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+namespace noalloc {
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+}
 
 namespace {
 
@@ -27,6 +35,26 @@ tda_status fail_with(tda_status s, const char *fmt, ...) {
   va_end(ap);
   g_err = buf;
   return s;
+}
+
+std::mutex g_noalloc_mu;
+constexpr int kMaxDevices = 64;
+double *g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of the scratch array; the device must be current.
+// hipGetSymbolAddress runs once per device (at the first tda_cov_build on it).
+tda_status noalloc_scratch(int dev, double **out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (dev < 0 || dev >= kMaxDevices) return fail_with(TDA_EINVAL, "device %d out of range", dev);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc::scratch));
+    if (e != hipSuccess || !p)
+      return fail_with(TDA_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_noalloc_ptr[dev] = (double *)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return TDA_OK;
 }
 
 #define HIP_TRY(expr)                                                                       \
@@ -463,6 +491,15 @@ extern "C" tda_status tda_cov_build(const double *acf, int64_t acf_len, int64_t 
     delete h;
     return fail_with(TDA_EHIP, "event creation failed");
   }
+  {
+    double *unused = nullptr;
+    const tda_status st0 = noalloc_scratch(dev, &unused);
+    if (st0 != TDA_OK) {
+      hipEventDestroy(h->done);
+      delete h;
+      return st0;
+    }
+  }
   h->idx_hash = 1469598103934665603ull;
   for (int32_t v : idx) h->idx_hash = (h->idx_hash ^ (uint32_t)v) * 1099511628211ull;
   if (h->n_pad > ((int64_t)1 << 31) / TB) {
@@ -890,6 +927,47 @@ extern "C" tda_status tda_loglik(tda_handle h, const double *d, const double *H,
   return tda_loglik_ex(h, d, H, B, ldh, out, h->precision, hip_stream);
 }
 
+// ---------------------------------------------------------------- allocation-free FP64 evaluation
+
+extern "C" tda_status tda_loglik_fp64_noalloc(tda_handle h, const double *d, const double *H,
+                                              int64_t B, int64_t ldh, double *out,
+                                              void *hip_stream) {
+  TDA_TRY(check_eval(h, d, H, B, ldh, out, TDA_PREC_FP64));
+  if (B == 0) return TDA_OK;
+  if (!h->panels_d.p) return fail_with(TDA_ESTATE, "FP64 evaluation needs the FP64 factor");
+  const int64_t ntile = (B + BC - 1) / BC;
+  const size_t need = (size_t)ntile * h->n_pad * BC * sizeof(double);
+  if (need > kNoAllocScratchBytes)
+    return fail_with(TDA_EINVAL,
+                     "allocation-free evaluation needs %zu bytes of scratch, more than its %zu: "
+                     "at most %lld templates at this size",
+                     need, kNoAllocScratchBytes,
+                     (long long)(kNoAllocScratchBytes / (h->n_pad * BC * sizeof(double)) * BC));
+  DeviceGuard guard(h->device);
+  double *scr = nullptr;
+  TDA_TRY(noalloc_scratch(h->device, &scr));
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing(s, &cap));
+  const bool capturing = cap != hipStreamCaptureStatusNone;
+  if (!capturing) TDA_TRY(order_after_previous(h, s));
+  TrsmItem it{};
+  it.panels = (const double *)h->panels_d.p;
+  it.panel_off = (const int64_t *)h->panel_off_d.p;
+  it.blk_first = (const int32_t *)h->blk_first_d.p;
+  it.idx = (const int32_t *)h->idx_d.p;
+  it.d = d;
+  it.H = H;
+  it.ldh = ldh;
+  it.out = out;
+  it.scratch = scr;
+  it.cterm = h->cterm();
+  it.B = (int32_t)B;
+  it.mode = MODE_LOGLIK;
+  HIP_TRY(launch_trsm_f64_single(it, h->nblk, ntile, s));
+  if (!capturing) TDA_TRY(mark_done(h, s));
+  return TDA_OK;
+}
 
 // ---------------------------------------------------------------- mixed precision
 
