@@ -211,6 +211,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="c2: leave out the short served leg")
     ap.add_argument("--core-only", action="store_true",
                     help="c2: only the batched mixed and FP64 evaluations (for profiling runs); "
                          "the Gohberg-Semencul, explicit-inverse, inner-product and ACF lines are null")
@@ -335,7 +336,7 @@ def main():
         for h in hg:
             h.close()
 
-    acf_line = cdo = snr_terms = wres = stress = c3_line = None
+    acf_line = cdo = snr_terms = wres = stress = c3_line = c5_line = None
     if not args.core_only:
         # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
         # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
@@ -440,6 +441,9 @@ def main():
         # one-detector N = 32768 workload (where the Gohberg-Semencul route cannot apply)
         stress = stress_leg(args, tda, torch, synth, dev, log)
         c3_line = run_c3(args, tda, torch, synth, dev, log, steps=5, fsteps=2)
+        if not args.no_c5:
+            # a short served leg: 2 s of requests at a quarter of and at the full offered load
+            c5_line = run_c5(args, tda, torch, synth, dev, log, 2.0, [0.25, 1.0], ("mixed",))
 
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
@@ -498,6 +502,7 @@ def main():
         "whitened_residual": wres,
         "accuracy_stress": stress,
         "c3": c3_line,
+        "c5_served": c5_line,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
                      "templates_compared": int(inst.B)},
@@ -802,20 +807,20 @@ def _serve_trace(srv, req, Hs, out_dev, torch):
     return wall, srv.stats(), int(counts.sum())
 
 
-def bench_c5(args, tda, torch, synth, dev, log):
+def run_c5(args, tda, torch, synth, dev, log, duration, fracs, precisions):
     """Request server: 32 resident single-detector datasets (N in 4096..65536), Poisson
-    arrivals of 1-64-template requests from 512 simulated walkers, swept over offered
-    loads (fractions of --rate); the FP64 server replays every 20th request of the full
-    trace."""
+    arrivals of 1-64-template requests from 512 simulated walkers, at the offered loads
+    `fracs` (fractions of --rate) for `duration` seconds each; the FP64 server (if asked
+    for) replays every 20th request of the full trace."""
     t0 = time.perf_counter()
-    w = synth.c5_workload(duration_s=args.duration, rate_hz=args.rate)
+    w = synth.c5_workload(duration_s=duration, rate_hz=args.rate)
     log(f"c5 inputs in {time.perf_counter() - t0:.1f} s")
-    fracs = [float(x) for x in args.rates.split(",") if x.strip()]
     # the server runs the default product variant: tuning trials for every coalesced
     # batch shape would otherwise land inside the latency measurements
+    saved = os.environ.get("TDA_AUTOTUNE")
     os.environ["TDA_AUTOTUNE"] = "0"
     sweep, res = [], {}
-    for prec in ("mixed", "fp64"):
+    for prec in precisions:
         t0 = time.perf_counter()
         srv = tda.Server(precision=prec, n_slots=3, max_batch=2048, staging_bytes=256 << 20)
         keep, Hs = [], []
@@ -834,10 +839,10 @@ def bench_c5(args, tda, torch, synth, dev, log):
         _serve_trace(srv, synth.c5_requests(args.rate * min(fracs), 0.5, trace=99), Hs, dev, torch)
         if prec == "mixed":
             for i, f in enumerate(fracs):
-                req = w.requests if f == 1.0 else synth.c5_requests(args.rate * f, args.duration,
+                req = w.requests if f == 1.0 else synth.c5_requests(args.rate * f, duration,
                                                                      trace=i + 1)
                 wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
-                point = {"offered_evals_per_s": tmpl / args.duration,
+                point = {"offered_evals_per_s": tmpl / duration,
                          "achieved_evals_per_s": tmpl / wall, "requests": len(req["t"]),
                          "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                          "mean_templates_per_launch": st["mean_templates_per_launch"]}
@@ -854,22 +859,36 @@ def bench_c5(args, tda, torch, synth, dev, log):
         del keep, Hs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    if saved is None:
+        os.environ.pop("TDA_AUTOTUNE", None)
+    else:
+        os.environ["TDA_AUTOTUNE"] = saved
     wall, st, setup, n, tmpl = res["mixed"]
     top = max(fracs)
-    line = _base_line(args, tmpl / wall, "evals/s", wall, 1,
-                      {"workload": f"request server: 32 resident datasets N in 4096..65536, Poisson "
-                                   f"{args.rate * top:g} req/s x {args.duration:g} s, 1-64 templates "
-                                   f"per request, 512 walkers", "requests": n, "templates": tmpl},
-                      "bf16x3+f64")
-    line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"],
-                          "unit": "submit to results written"}
-    line["offered_evals_per_s"] = tmpl / args.duration
-    line["server"] = st
-    line["load_sweep"] = sweep
-    line["setup_s"] = setup
-    fw, fst, fsetup, fn, ftmpl = res["fp64"]
-    line["fp64"] = {"value": ftmpl / fw, "unit": "evals/s", "offered_fraction": 1 / 20,
-                    "latency_ms": {"p50": fst["p50_ms"], "p99": fst["p99_ms"]}, "setup_s": fsetup}
+    line = {"value": tmpl / wall, "unit": "evals/s",
+            "config": {"workload": f"request server: 32 resident datasets N in 4096..65536, "
+                                   f"Poisson {args.rate * top:g} req/s x {duration:g} s, 1-64 "
+                                   f"templates per request, 512 walkers", "requests": n,
+                       "templates": tmpl},
+            "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"],
+                           "unit": "submit to results written"},
+            "offered_evals_per_s": tmpl / duration, "server": st, "load_sweep": sweep,
+            "setup_s": setup}
+    if "fp64" in res:
+        fw, fst, fsetup, fn, ftmpl = res["fp64"]
+        line["fp64"] = {"value": ftmpl / fw, "unit": "evals/s", "offered_fraction": 1 / 20,
+                        "latency_ms": {"p50": fst["p50_ms"], "p99": fst["p99_ms"]},
+                        "setup_s": fsetup}
+    return line
+
+
+def bench_c5(args, tda, torch, synth, dev, log):
+    """The request server alone over the --rates sweep (see run_c5)."""
+    fracs = [float(x) for x in args.rates.split(",") if x.strip()]
+    c5 = run_c5(args, tda, torch, synth, dev, log, args.duration, fracs, ("mixed", "fp64"))
+    wall = c5["server"]["busy_s"] or 1.0
+    line = _base_line(args, c5["value"], "evals/s", wall, 1, c5.pop("config"), "bf16x3+f64")
+    line.update({k: v for k, v in c5.items() if k not in ("value", "unit")})
     print(json.dumps(line), flush=True)
 
 

@@ -34,9 +34,9 @@
  *                     exact one (variational bound) and its error is
  *                     quadratic in the BF16 product error.  Its FP64 FFT
  *                     product rounds at about u lambda_max ||C^-1 h||^2, which
- *                     keeps |dlogL| <= 1e-3 up to kappa(C) of about 3e7 on the
- *                     benchmark inputs and exceeds it from about 1e8; beyond
- *                     that use TDA_PREC_FP64.
+ *                     keeps |dlogL| <= 1e-3 up to kappa(C) of about 1e7 (3e7
+ *                     for the two-detector N = 16384 bank) and exceeds it from
+ *                     about 1e8; beyond that use TDA_PREC_FP64.
  *   TDA_PREC_GS    -- FP64 evaluation through the Gohberg-Semencul form of the
  *                     Toeplitz inverse (Sec. III.A.3): x = C^-1 e_1 and log det C
  *                     by Levinson-Durbin once per segment, then per template

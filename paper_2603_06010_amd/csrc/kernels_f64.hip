@@ -53,39 +53,123 @@ hipError_t launch_assemble(const double *acf, const int32_t *idx, int64_t n_keep
 
 constexpr int TS = CP + 1;  // LDS row stride (bank spread)
 
+// The 128 x 128 diagonal block is factored in LDS by blocks of 32 columns: one wave
+// factors each 32 x 32 diagonal block in registers (lane l holds row l; pivots and column
+// entries come from other lanes by cross-lane reads) and inverts it (lane l computes
+// column l of the inverse); then all threads solve the rows below against it and update
+// the rest of the block.  The inverse X = L^-1 of the whole block follows by blocks of 32,
+// X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj, one block diagonal at a time.  X's strict lower
+// part is kept transposed in T's strict upper part (X[r][c] at T[c][r]), its diagonal in
+// diagX.
+constexpr int PB = 32;              // sub-block of the diagonal-block factorisation
+constexpr int POTF2_TMP = 3 * PB * PB;  // products of one block diagonal of the inverse
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// X[R][C] for R >= C of the inverse being built (see above)
+__device__ __forceinline__ double xinv(const double *T, const double *diagX, int R, int C) {
+  return R == C ? diagX[R] : T[C * TS + R];
+}
+
 __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t lda, int64_t k,
                                                double *__restrict__ dinv,
                                                double *__restrict__ logdiag,
                                                int32_t *__restrict__ fail) {
   if (fail[0] >= 0) return;
-  extern __shared__ double T[];  // CP x TS
+  extern __shared__ double T[];  // CP x TS, then POTF2_TMP
+  double *tmp = T + CP * TS;
   __shared__ double diagX[CP];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < CP * CP; e += 256) {
     const int c = e / CP, r = e % CP;
     if (r >= c) T[r * TS + c] = A[(k + c) * lda + k + r];
   }
   if (tid == 0) bad = -1;
   __syncthreads();
-  const int cl = tid & (CP - 1);
-  const int half = tid >> 7;
-  for (int j = 0; j < CP; ++j) {
-    if (tid == 0) {
-      const double dj = T[j * TS + j];
-      if (!(dj > 0.0) || !isfinite(dj))
-        bad = j;
-      else
-        T[j * TS + j] = sqrt(dj);
+  for (int b0 = 0; b0 < CP; b0 += PB) {
+    // (a) diagonal block: factor and invert in registers (wave 0, lanes 0..31)
+    if (wave == 0) {
+      const int l = lane;
+      double x[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) x[c] = (l < PB && c <= l) ? T[(b0 + l) * TS + b0 + c] : 0.0;
+      int badj = -1;
+#pragma unroll
+      for (int j = 0; j < PB; ++j) {
+        const double djj = readlane_d(x[j], j);
+        if (badj < 0 && (!(djj > 0.0) || !isfinite(djj))) badj = j;
+        const double piv = sqrt(djj);
+        x[j] = l == j ? piv : (l > j ? x[j] / piv : x[j]);
+#pragma unroll
+        for (int c = j + 1; c < PB; ++c) {
+          const double lcj = readlane_d(x[j], c);
+          if (l >= c) x[c] -= x[j] * lcj;
+        }
+      }
+      // column l of Y = L_bb^-1: Y[i][l] = (delta_il - sum_{q<i} L[i][q] Y[q][l]) / L[i][i]
+      double y[PB];
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        double s = l == i ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) s -= readlane_d(x[q], i) * y[q];
+        y[i] = s / readlane_d(x[i], i);
+      }
+      if (l < PB) {
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c <= l) T[(b0 + l) * TS + b0 + c] = x[c];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+          if (i == l) diagX[b0 + l] = y[i];
+          if (i > l) T[(b0 + l) * TS + b0 + i] = y[i];
+        }
+      }
+      if (l == 0 && badj >= 0) bad = b0 + badj;
     }
     __syncthreads();
     if (bad >= 0) break;
-    const double piv = T[j * TS + j];
-    for (int r = j + 1 + tid; r < CP; r += 256) T[r * TS + j] /= piv;
+    // (b) rows below within the block: X_r = A_r L_bb^-T, X_r[c] = sum_{q<=c} A_r[q] Y[c][q]
+    const int nrow = CP - b0 - PB;
+    const int nout = nrow * PB;
+    double res[12];
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+      const int e = tid + 256 * u;
+      res[u] = 0.0;
+      if (e < nout) {
+        const int r = b0 + PB + e / PB, c = e % PB;
+        double acc = 0.0;
+        for (int q = 0; q <= c; ++q)
+          acc += T[r * TS + b0 + q] * xinv(T, diagX, b0 + c, b0 + q);
+        res[u] = acc;
+      }
+    }
     __syncthreads();
-    if (cl > j) {
-      const double lcj = T[cl * TS + j];
-      for (int r = cl + half; r < CP; r += 2) T[r * TS + cl] -= T[r * TS + j] * lcj;
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+      const int e = tid + 256 * u;
+      if (e < nout) T[(b0 + PB + e / PB) * TS + b0 + e % PB] = res[u];
+    }
+    __syncthreads();
+    // (c) trailing update of the block: T[r][c] -= X_r . X_c for b0+PB <= c <= r
+    const int ntri = nrow * (nrow + 1) / 2;
+    for (int e = tid; e < ntri; e += 256) {
+      int rr = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+      while (rr * (rr + 1) / 2 > e) --rr;
+      while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
+      const int cc = e - rr * (rr + 1) / 2;
+      const int r = b0 + PB + rr, c = b0 + PB + cc;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int q = 0; q < PB; ++q) acc += T[r * TS + b0 + q] * T[c * TS + b0 + q];
+      T[r * TS + c] -= acc;
     }
     __syncthreads();
   }
@@ -98,18 +182,33 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
     const int c = e / CP, r = e % CP;
     if (r >= c) A[(k + c) * lda + k + r] = T[r * TS + c];
   }
-  // X = L^-1 (lower): thread c solves column c; X[r][c] (r > c) kept in T[c][r] (strict upper).
-  if (tid < CP) {
-    const int c = tid;
-    const double xcc = 1.0 / T[c * TS + c];
-    diagX[c] = xcc;
-    for (int r = c + 1; r < CP; ++r) {
-      double s = T[r * TS + c] * xcc;
-      for (int q = c + 1; q < r; ++q) s += T[r * TS + q] * T[c * TS + q];
-      T[c * TS + r] = -s / T[r * TS + r];
+  // off-diagonal blocks of X = L^-1, one block diagonal (distance dd) at a time:
+  // tmp_ij = sum_{kb=j..i-1} L_i,kb X_kb,j, then X_ij = -Y_ii tmp_ij
+  for (int dd = 1; dd < CP / PB; ++dd) {
+    const int nb = CP / PB - dd;
+    for (int e = tid; e < nb * PB * PB; e += 256) {
+      const int bi = e / (PB * PB), r = (e / PB) % PB, c = e % PB;
+      const int i = bi + dd, j = bi;
+      double acc = 0.0;
+      for (int kb = j; kb < i; ++kb)
+        for (int q = 0; q < PB; ++q) {
+          const int Q = PB * kb + q, C = PB * j + c;
+          if (Q < C) continue;  // X is lower triangular
+          acc += T[(PB * i + r) * TS + Q] * xinv(T, diagX, Q, C);
+        }
+      tmp[e] = acc;
     }
+    __syncthreads();
+    for (int e = tid; e < nb * PB * PB; e += 256) {
+      const int bi = e / (PB * PB), r = (e / PB) % PB, c = e % PB;
+      const int i = bi + dd, j = bi;
+      double acc = 0.0;
+      for (int q = 0; q <= r; ++q)
+        acc += xinv(T, diagX, PB * i + r, PB * i + q) * tmp[bi * PB * PB + q * PB + c];
+      T[(PB * j + c) * TS + PB * i + r] = -acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // dinv[t*CP + c] = X[c][t]  (row t of X^T)
   for (int e = tid; e < CP * CP; e += 256) {
     const int t = e / CP, c = e % CP;
@@ -118,10 +217,10 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
     else if (c == t) v = diagX[t];
     dinv[e] = v;
   }
-  if (tid == 0) {
-    double s = 0.0;
-    for (int j = 0; j < CP; ++j) s += log(T[j * TS + j]);
-    logdiag[0] = s;
+  if (wave == 0) {
+    double s = log(T[lane * TS + lane]) + log(T[(lane + 64) * TS + lane + 64]);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) logdiag[0] = s;
   }
 }
 
@@ -150,53 +249,156 @@ __global__ __launch_bounds__(256) void k_panel(double *__restrict__ A, int64_t l
     for (int j = 0; j < 4; ++j) A[(k + 16 * ct + lc) * lda + i0 + lr + 4 * j] = acc[ct][j];
 }
 
-// trailing update of lower 64x64 tiles (I >= J) of the region [k+CP, n)
-__global__ __launch_bounds__(256) void k_syrk(double *__restrict__ A, int64_t lda, int64_t k,
+// Trailing update A_IJ -= L_Ik L_Jk^T of the region [k+CP, n) in lower 128 x 128 tiles
+// (I >= J), K = CP: the 128 rows x 16 columns of both panels per step are staged in LDS
+// (double-buffered, one chunk loaded into registers while the previous one is multiplied).
+// Four waves each take a 64 x 64 quarter as 4 x 4 FP64 matrix-core tiles, with the MFMA's
+// fast index on C's rows so that the read-modify-write of C is coalesced.
+// col_only != 0: the tiles of tile column jb only (I = jb + blockIdx.x); else the lower
+// triangle of tiles from (jb, jb).
+constexpr int SY = 128;       // tile edge
+constexpr int SK = 16;        // panel columns per LDS stage
+constexpr int SYP = SY + 16;  // LDS row stride (bank spread between the four k rows)
+
+__global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t lda, int64_t k,
+                                              int32_t jb, int32_t col_only,
                                               const int32_t *__restrict__ fail) {
   if (fail[0] >= 0) return;
+  __shared__ double Ls[2][2][SK][SYP];  // [buffer][I or J panel rows][column][row]
   const int64_t e = blockIdx.x;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-  while (I * (I + 1) / 2 > e) --I;
-  while ((I + 1) * (I + 2) / 2 <= e) ++I;
-  const int64_t J = e - I * (I + 1) / 2;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int lr = lane >> 4, lc = lane & 15;
-  const int64_t k1 = k + CP;
-  const int64_t I0 = k1 + 64 * I + 16 * w, J0 = k1 + 64 * J;
-  d4 acc[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int t0 = 0; t0 < CP; t0 += 4) {
-    const double *col = A + (k + t0 + lr) * lda;
-    const double a = col[I0 + lc];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma64(a, col[J0 + 16 * ct + lc], acc[ct]);
+  int64_t I, J;
+  if (col_only) {
+    J = jb;
+    I = jb + e;
+  } else {
+    int64_t t = (int64_t)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+    while (t * (t + 1) / 2 > e) --t;
+    while ((t + 1) * (t + 2) / 2 <= e) ++t;
+    I = jb + t;
+    J = jb + e - t * (t + 1) / 2;
   }
+  const int64_t k1 = k + CP;
+  const int64_t I0 = k1 + SY * I, J0 = k1 + SY * J;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;  // rows I0 + 64 wr .., columns J0 + 64 wc ..
+  const int lr = lane >> 4, lc = lane & 15;
+  // staging: pair p = tid + 256 u (u < 8) of (which, column t, rows 2q and 2q + 1)
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 stage[8];
+  auto load_chunk = [&](int c) __attribute__((always_inline)) {
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct)
+    for (int u = 0; u < 8; ++u) {
+      const int p = tid + 256 * u;
+      const int which = p >> 10, t = (p >> 6) & (SK - 1), q = p & 63;
+      const int64_t row0 = which ? J0 : I0;
+      stage[u] = *(const d2 *)(A + (k + SK * c + t) * lda + row0 + 2 * q);
+    }
+  };
+  auto store_chunk = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) A[(J0 + 16 * ct + lc) * lda + I0 + lr + 4 * j] -= acc[ct][j];
+    for (int u = 0; u < 8; ++u) {
+      const int p = tid + 256 * u;
+      const int which = p >> 10, t = (p >> 6) & (SK - 1), q = p & 63;
+      *(d2 *)&Ls[buf][which][t][2 * q] = stage[u];
+    }
+  };
+  d4 acc[4][4];  // [J group of 16][I group of 16]: D[m][n] = C[I row n][J column m]
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = d4{0, 0, 0, 0};
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  constexpr int NCH = CP / SK;
+  for (int c = 0; c < NCH; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < NCH) load_chunk(c + 1);
+#pragma unroll
+    for (int t0 = 0; t0 < SK; t0 += 4) {
+      double a[4], b[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) a[mi] = Ls[buf][1][t0 + lr][64 * wc + 16 * mi + lc];
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) b[ni] = Ls[buf][0][t0 + lr][64 * wr + 16 * ni + lc];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = mfma64(a[mi], b[ni], acc[mi][ni]);
+    }
+    if (c + 1 < NCH) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+  // C[r][cc] -= acc, r = I0 + 64 wr + 16 ni + lc, cc = J0 + 64 wc + 16 mi + lr + 4 j; lower part only
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t r = I0 + 64 * wr + 16 * ni + lc;
+        const int64_t cc = J0 + 64 * wc + 16 * mi + lr + 4 * j;
+        if (I != J || r >= cc) A[cc * lda + r] -= acc[mi][ni][j];
+      }
 }
 
+// One segment's factorisation.  Look-ahead over two streams: after panel k, the first
+// tile column of its trailing update (the next panel's columns), the next diagonal block
+// and the next panel run on stream a while the rest of the trailing update runs on stream
+// b.  Stream a's first tile column also waits for b's previous trailing update, which
+// wrote the same columns.
 hipError_t launch_cholesky(double *A, int64_t n, double *dinv, double *logdiag, int32_t *fail,
                            hipStream_t s) {
-  const size_t lds = sizeof(double) * CP * TS;
-  for (int64_t k = 0; k < n; k += CP) {
-    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), lds, s, A, n, k, dinv + (k / CP) * CP * CP,
+  const size_t lds = sizeof(double) * (CP * TS + POTF2_TMP);
+  hipStream_t sa = nullptr, sb = nullptr;
+  hipEvent_t e0 = nullptr, ea = nullptr, eb = nullptr;
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (err == hipSuccess && x != hipSuccess) err = x;
+    return err == hipSuccess;
+  };
+  auto diag_and_panel = [&](int64_t k) {
+    hipLaunchKernelGGL(k_potf2, dim3(1), dim3(256), lds, sa, A, n, k, dinv + (k / CP) * CP * CP,
                        logdiag + k / CP, fail);
     const int64_t rest = n - k - CP;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_panel, dim3((unsigned)(rest / 64)), dim3(256), 0, s, A, n, k,
+    if (rest > 0)
+      hipLaunchKernelGGL(k_panel, dim3((unsigned)(rest / 64)), dim3(256), 0, sa, A, n, k,
                          dinv + (k / CP) * CP * CP, fail);
-      const int64_t T = rest / 64;
-      hipLaunchKernelGGL(k_syrk, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, A, n, k,
-                         fail);
+    return chk(hipGetLastError());
+  };
+  if (chk(hipStreamCreateWithFlags(&sa, hipStreamNonBlocking)) &&
+      chk(hipStreamCreateWithFlags(&sb, hipStreamNonBlocking)) &&
+      chk(hipEventCreateWithFlags(&e0, hipEventDisableTiming)) &&
+      chk(hipEventCreateWithFlags(&ea, hipEventDisableTiming)) &&
+      chk(hipEventCreateWithFlags(&eb, hipEventDisableTiming)) && chk(hipEventRecord(e0, s)) &&
+      chk(hipStreamWaitEvent(sa, e0, 0)) && chk(hipStreamWaitEvent(sb, e0, 0)) &&
+      diag_and_panel(0)) {
+    for (int64_t k = 0; k + CP < n && err == hipSuccess; k += CP) {
+      const int64_t T = (n - k - CP) / SY;  // tile rows of the trailing region
+      chk(hipEventRecord(ea, sa));           // panel k finished
+      if (T > 1) {
+        chk(hipStreamWaitEvent(sb, ea, 0));
+        hipLaunchKernelGGL(k_syrk, dim3((unsigned)((T - 1) * T / 2)), dim3(256), 0, sb, A, n, k, 1,
+                           0, fail);
+      }
+      if (k > 0) chk(hipStreamWaitEvent(sa, eb, 0));  // b's previous update of these columns
+      hipLaunchKernelGGL(k_syrk, dim3((unsigned)T), dim3(256), 0, sa, A, n, k, 0, 1, fail);
+      chk(hipGetLastError());
+      chk(hipEventRecord(eb, sb));
+      diag_and_panel(k + CP);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    chk(hipEventRecord(ea, sa));
+    chk(hipEventRecord(eb, sb));
+    chk(hipStreamWaitEvent(s, ea, 0));
+    chk(hipStreamWaitEvent(s, eb, 0));
   }
-  return hipSuccess;
+  // the caller synchronises right after the factorisation anyway
+  if (sa) (void)hipStreamSynchronize(sa), (void)hipStreamDestroy(sa);
+  if (sb) (void)hipStreamSynchronize(sb), (void)hipStreamDestroy(sb);
+  if (e0) (void)hipEventDestroy(e0);
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  return err;
 }
 
 // ---------------------------------------------------------------- inverses of TB x TB diagonal blocks
@@ -490,7 +692,7 @@ void register_kernel_attributes() {
   register_mixed_attributes();
   register_acf_attributes();
   hipFuncSetAttribute((const void *)k_potf2, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)(sizeof(double) * CP * TS));
+                      (int)(sizeof(double) * (CP * TS + POTF2_TMP)));
   hipFuncSetAttribute((const void *)k_diag_inverse, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)(sizeof(double) * CP * TS));
 }
