@@ -214,7 +214,10 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="c2: leave out the short served leg")
     ap.add_argument("--core-only", action="store_true",
                     help="c2: only the batched mixed and FP64 evaluations (for profiling runs); "
-                         "the Gohberg-Semencul, explicit-inverse, inner-product and ACF lines are null")
+                         "every other leg is null (same as --legs none)")
+    ap.add_argument("--legs", default="gs,acf,cdo,terms,wres,stress,c3,c5",
+                    help="c2: the legs run beside the mixed and FP64 evaluations, comma-"
+                         "separated from gs, acf, cdo, terms, wres, stress, c3, c5 (or none)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default): two detectors x N=16384, 4096 templates per launch; "
                          "c3: one detector x N=32768 with 3 gaps, 8192 templates; "
@@ -228,6 +231,10 @@ def main():
                     help="after timing, run one device copy of this many MiB (reference "
                          "kernel for hardware byte counters)")
     args = ap.parse_args()
+    legs = set() if args.core_only else {x.strip() for x in args.legs.split(",")} - {"none", ""}
+    if args.no_c5:
+        legs.discard("c5")
+    args.leg = lambda name: name in legs
     if args.gpus != 1:
         print("bench.py: measures one GPU only; run with --gpus 1 (templates and datasets "
               "shard across GPUs with no exchange in the hot loop)", file=sys.stderr)
@@ -316,7 +323,7 @@ def main():
 
     # Gohberg-Semencul FP64 path on the same inputs (segments without excluded samples)
     gs = None
-    if not args.core_only and not any(m is not None and np.any(m) for m in inst.masks):
+    if args.leg("gs") and not any(m is not None and np.any(m) for m in inst.masks):
         t0 = time.perf_counter()
         hg = [tda.Handle(inst.acf, inst.N, inst.masks[k], precision="gs").factor()
               for k in range(inst.n_det)]
@@ -337,7 +344,7 @@ def main():
             h.close()
 
     acf_line = cdo = snr_terms = wres = stress = c3_line = c5_line = None
-    if not args.core_only:
+    if args.leg("acf"):
         # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
         # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
         # N = 16384 covariance
@@ -360,6 +367,7 @@ def main():
         log("acf", acf_line)
         del xs
 
+    if args.leg("cdo"):
         # explicit-inverse FP64 evaluation (the paper's CDO form) on the same mixed handles:
         # one call per detector, network sum on the host side of the comparison
         csteps = max(3, args.steps // 4)
@@ -386,6 +394,7 @@ def main():
         log("cdo", cdo)
         del cdo_out
 
+    if args.leg("terms"):
         # inner products behind the SNRs (tda_loglik_terms): mixed per detector, timed, and
         # compared with the FP64 evaluation of the same terms on the GPU
         tsteps = max(3, args.steps // 4)
@@ -412,6 +421,7 @@ def main():
         log("snr terms", snr_terms)
         del terms_m, terms_f
 
+    if args.leg("wres"):
         # whitened residuals (tda_whitened_residual) of one detector: the FP64 solve plus the
         # export of L^-1 (d - h) for every template; the export kernel against the HBM peak
         wsteps = 3
@@ -437,13 +447,15 @@ def main():
         log("whitened residuals", wres)
         del W, out_w, ref_w
 
-        # the same workload at the stress nugget (kappa(C) up to 2.9e8), and the gapped
-        # one-detector N = 32768 workload (where the Gohberg-Semencul route cannot apply)
+    # the same workload at smaller nuggets down to the stress nugget (kappa(C) up to 2.9e8),
+    # and the gapped one-detector N = 32768 workload (where Gohberg-Semencul cannot apply)
+    if args.leg("stress"):
         stress = stress_leg(args, tda, torch, synth, dev, log)
+    if args.leg("c3"):
         c3_line = run_c3(args, tda, torch, synth, dev, log, steps=5, fsteps=2)
-        if not args.no_c5:
-            # a short served leg: 2 s of requests at a quarter of and at the full offered load
-            c5_line = run_c5(args, tda, torch, synth, dev, log, 2.0, [0.25, 1.0], ("mixed",))
+    if args.leg("c5"):
+        # a short served leg: 2 s of requests at a quarter of and at the full offered load
+        c5_line = run_c5(args, tda, torch, synth, dev, log, 2.0, [0.25, 1.0], ("mixed",))
 
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f

@@ -53,27 +53,23 @@ hipError_t launch_assemble(const double *acf, const int32_t *idx, int64_t n_keep
 
 constexpr int TS = CP + 1;  // LDS row stride (bank spread)
 
-// The 128 x 128 diagonal block is factored in LDS by blocks of 32 columns: one wave
-// factors each 32 x 32 diagonal block in registers (lane l holds row l; pivots and column
-// entries come from other lanes by cross-lane reads) and inverts it (lane l computes
-// column l of the inverse); then all threads solve the rows below against it and update
-// the rest of the block.  The inverse X = L^-1 of the whole block follows by blocks of 32,
-// X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj, one block diagonal at a time.  X's strict lower
-// part is kept transposed in T's strict upper part (X[r][c] at T[c][r]), its diagonal in
-// diagX.
-constexpr int PB = 32;              // sub-block of the diagonal-block factorisation
-constexpr int POTF2_TMP = 3 * PB * PB;  // products of one block diagonal of the inverse
+// The 128 x 128 diagonal block is factored in LDS by blocks of 16 columns: one wave
+// factors each 16 x 16 diagonal block in registers (lane l holds row l; pivots and
+// column entries come from other lanes by cross-lane reads) and inverts it (lane l
+// computes column l of the inverse); then all threads solve the
+// rows below against it and update the rest of the block.  The inverse X = L^-1 of the
+// whole block follows by blocks of 16, X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj, one block
+// diagonal at a time.  X's strict lower part is kept transposed in T's strict upper part
+// (X[r][c] at T[c][r]), its diagonal in diagX.
+constexpr int PB = 16;                     // sub-block of the diagonal-block factorisation
+constexpr int POTF2_TMP = (CP / PB - 1) * PB * PB;  // one block diagonal of the inverse
 
+// lane `lane`'s value of v (a uniform double)
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// X[R][C] for R >= C of the inverse being built (see above)
-__device__ __forceinline__ double xinv(const double *T, const double *diagX, int R, int C) {
-  return R == C ? diagX[R] : T[C * TS + R];
 }
 
 __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t lda, int64_t k,
@@ -86,19 +82,32 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
   __shared__ double diagX[CP];
   __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < CP * CP; e += 256) {
-    const int c = e / CP, r = e % CP;
-    if (r >= c) T[r * TS + c] = A[(k + c) * lda + k + r];
+  // lower triangle of the column-major block into row-major T: eight loads in flight
+  // before their stores (column c = e / CP, row r = e % CP)
+  for (int e0 = tid; e0 < CP * CP; e0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u, c = e / CP, r = e % CP;
+      v[u] = r >= c ? A[(k + c) * lda + k + r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u, c = e / CP, r = e % CP;
+      if (r >= c) T[r * TS + c] = v[u];
+    }
   }
   if (tid == 0) bad = -1;
   __syncthreads();
   for (int b0 = 0; b0 < CP; b0 += PB) {
-    // (a) diagonal block: factor and invert in registers (wave 0, lanes 0..31)
+    // (a) diagonal block: factor and invert in registers (wave 0; lane l < PB holds row l,
+    // other lanes' entries come by cross-lane reads)
     if (wave == 0) {
       const int l = lane;
+      const bool row = l < PB;
       double x[PB];
 #pragma unroll
-      for (int c = 0; c < PB; ++c) x[c] = (l < PB && c <= l) ? T[(b0 + l) * TS + b0 + c] : 0.0;
+      for (int c = 0; c < PB; ++c) x[c] = (row && c <= l) ? T[(b0 + l) * TS + b0 + c] : 0.0;
       int badj = -1;
 #pragma unroll
       for (int j = 0; j < PB; ++j) {
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
         x[j] = l == j ? piv : (l > j ? x[j] / piv : x[j]);
 #pragma unroll
         for (int c = j + 1; c < PB; ++c) {
-          const double lcj = readlane_d(x[j], c);
+          const double lcj = readlane_d(x[j], c);  // L[c][j]
           if (l >= c) x[c] -= x[j] * lcj;
         }
       }
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
         for (int q = 0; q < i; ++q) s -= readlane_d(x[q], i) * y[q];
         y[i] = s / readlane_d(x[i], i);
       }
-      if (l < PB) {
+      if (row) {
 #pragma unroll
         for (int c = 0; c < PB; ++c)
           if (c <= l) T[(b0 + l) * TS + b0 + c] = x[c];
@@ -135,7 +144,8 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
     }
     __syncthreads();
     if (bad >= 0) break;
-    // (b) rows below within the block: X_r = A_r L_bb^-T, X_r[c] = sum_{q<=c} A_r[q] Y[c][q]
+    // (b) rows below within the block: X_r = A_r L_bb^-T,
+    // X_r[c] = A_r[c] Y[c][c] + sum_{q<c} A_r[q] Y[c][q], Y[c][q] at T[b0+q][b0+c]
     const int nrow = CP - b0 - PB;
     const int nout = nrow * PB;
     double res[12];
@@ -145,10 +155,15 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
       res[u] = 0.0;
       if (e < nout) {
         const int r = b0 + PB + e / PB, c = e % PB;
-        double acc = 0.0;
-        for (int q = 0; q <= c; ++q)
-          acc += T[r * TS + b0 + q] * xinv(T, diagX, b0 + c, b0 + q);
-        res[u] = acc;
+        const double *Ar = T + r * TS + b0;
+        double a4[4] = {Ar[c] * diagX[b0 + c], 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 3 < c; q += 4) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) a4[v] += Ar[q + v] * T[(b0 + q + v) * TS + b0 + c];
+        }
+        for (; q < c; ++q) a4[0] += Ar[q] * T[(b0 + q) * TS + b0 + c];
+        res[u] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
       }
     }
     __syncthreads();
@@ -166,10 +181,11 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
       while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
       const int cc = e - rr * (rr + 1) / 2;
       const int r = b0 + PB + rr, c = b0 + PB + cc;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int q = 0; q < PB; ++q) acc += T[r * TS + b0 + q] * T[c * TS + b0 + q];
-      T[r * TS + c] -= acc;
+      const double *Xr = T + r * TS + b0, *Xc = T + c * TS + b0;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < PB; ++q) a4[q & 3] += Xr[q] * Xc[q];
+      T[r * TS + c] -= (a4[0] + a4[1]) + (a4[2] + a4[3]);
     }
     __syncthreads();
   }
@@ -178,36 +194,54 @@ __global__ __launch_bounds__(256) void k_potf2(double *__restrict__ A, int64_t l
     return;
   }
   // L back to global (lower, incl. diagonal)
-  for (int e = tid; e < CP * CP; e += 256) {
-    const int c = e / CP, r = e % CP;
-    if (r >= c) A[(k + c) * lda + k + r] = T[r * TS + c];
+  for (int e0 = tid; e0 < CP * CP; e0 += 8 * 256) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u, c = e / CP, r = e % CP;
+      if (r >= c) A[(k + c) * lda + k + r] = T[r * TS + c];
+    }
   }
-  // off-diagonal blocks of X = L^-1, one block diagonal (distance dd) at a time:
-  // tmp_ij = sum_{kb=j..i-1} L_i,kb X_kb,j, then X_ij = -Y_ii tmp_ij
-  for (int dd = 1; dd < CP / PB; ++dd) {
-    const int nb = CP / PB - dd;
-    for (int e = tid; e < nb * PB * PB; e += 256) {
-      const int bi = e / (PB * PB), r = (e / PB) % PB, c = e % PB;
-      const int i = bi + dd, j = bi;
-      double acc = 0.0;
-      for (int kb = j; kb < i; ++kb)
-        for (int q = 0; q < PB; ++q) {
-          const int Q = PB * kb + q, C = PB * j + c;
-          if (Q < C) continue;  // X is lower triangular
-          acc += T[(PB * i + r) * TS + Q] * xinv(T, diagX, Q, C);
+  // off-diagonal blocks of X = L^-1, one block diagonal (distance dd) at a time, one
+  // 16 x 16 block per wave and FP64 matrix-core op: tmp_ij = sum_{kb=j..i-1} L_i,kb X_kb,j,
+  // then X_ij = -Y_ii tmp_ij.  Operand lane l supplies row l % 16 and k-index l / 16 of
+  // the k-step; X[R][C] (R > C) is read at T[C][R], its diagonal from diagX, zero above.
+  {
+    const int lr = lane & 15, lk = lane >> 4;
+    auto xat = [&](int R, int C) -> double {
+      return R > C ? T[C * TS + R] : (R == C ? diagX[R] : 0.0);
+    };
+    for (int dd = 1; dd < CP / PB; ++dd) {
+      const int nb = CP / PB - dd;
+      for (int bi = wave; bi < nb; bi += 4) {
+        const int i = bi + dd, j = bi;
+        d4 acc = d4{0, 0, 0, 0};
+        for (int kb = j; kb < i; ++kb)
+#pragma unroll
+          for (int s4 = 0; s4 < PB; s4 += 4) {
+            const int K = PB * kb + s4 + lk;
+            const double a = T[(PB * i + lr) * TS + K];
+            const double bv = xat(K, PB * j + lr);
+            acc = mfma64(a, bv, acc);
+          }
+        // D[q][n] at lane (q % 4) * 16 + n, register q / 4
+#pragma unroll
+        for (int u = 0; u < 4; ++u) tmp[bi * PB * PB + (lk + 4 * u) * PB + lr] = acc[u];
+      }
+      __syncthreads();
+      for (int bi = wave; bi < nb; bi += 4) {
+        const int i = bi + dd, j = bi, R0 = PB * i;
+        d4 acc = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < PB; s4 += 4) {
+          const double a = xat(R0 + lr, R0 + s4 + lk);             // Y_ii[r][q]
+          const double bv = tmp[bi * PB * PB + (s4 + lk) * PB + lr];  // tmp[q][c]
+          acc = mfma64(a, bv, acc);
         }
-      tmp[e] = acc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) T[(PB * j + lr) * TS + R0 + lk + 4 * u] = -acc[u];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < nb * PB * PB; e += 256) {
-      const int bi = e / (PB * PB), r = (e / PB) % PB, c = e % PB;
-      const int i = bi + dd, j = bi;
-      double acc = 0.0;
-      for (int q = 0; q <= r; ++q)
-        acc += xinv(T, diagX, PB * i + r, PB * i + q) * tmp[bi * PB * PB + q * PB + c];
-      T[(PB * j + c) * TS + PB * i + r] = -acc;
-    }
-    __syncthreads();
   }
   // dinv[t*CP + c] = X[c][t]  (row t of X^T)
   for (int e = tid; e < CP * CP; e += 256) {
@@ -249,8 +283,9 @@ __global__ __launch_bounds__(256) void k_panel(double *__restrict__ A, int64_t l
     for (int j = 0; j < 4; ++j) A[(k + 16 * ct + lc) * lda + i0 + lr + 4 * j] = acc[ct][j];
 }
 
-// Trailing update A_IJ -= L_Ik L_Jk^T of the region [k+CP, n) in lower 128 x 128 tiles
-// (I >= J), K = CP: the 128 rows x 16 columns of both panels per step are staged in LDS
+// Trailing update A_IJ -= L_I,K L_J,K^T over panel columns K = [kcol, kcol + kw) of the
+// region from row/column r0 in lower 128 x 128 tiles (I >= J, tile I covers rows
+// r0 + 128 I ..): the 128 rows x 16 columns of both operands per step are staged in LDS
 // (double-buffered, one chunk loaded into registers while the previous one is multiplied).
 // Four waves each take a 64 x 64 quarter as 4 x 4 FP64 matrix-core tiles, with the MFMA's
 // fast index on C's rows so that the read-modify-write of C is coalesced.
@@ -260,9 +295,10 @@ constexpr int SY = 128;       // tile edge
 constexpr int SK = 16;        // panel columns per LDS stage
 constexpr int SYP = SY + 16;  // LDS row stride (bank spread between the four k rows)
 
-__global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t lda, int64_t k,
-                                              int32_t jb, int32_t col_only,
-                                              const int32_t *__restrict__ fail) {
+__global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t lda, int64_t kcol,
+                                                 int32_t kw, int64_t r0, int32_t jb,
+                                                 int32_t col_only,
+                                                 const int32_t *__restrict__ fail) {
   if (fail[0] >= 0) return;
   __shared__ double Ls[2][2][SK][SYP];  // [buffer][I or J panel rows][column][row]
   const int64_t e = blockIdx.x;
@@ -277,8 +313,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t
     I = jb + t;
     J = jb + e - t * (t + 1) / 2;
   }
-  const int64_t k1 = k + CP;
-  const int64_t I0 = k1 + SY * I, J0 = k1 + SY * J;
+  const int64_t I0 = r0 + SY * I, J0 = r0 + SY * J;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;  // rows I0 + 64 wr .., columns J0 + 64 wc ..
   const int lr = lane >> 4, lc = lane & 15;
@@ -291,7 +326,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t
       const int p = tid + 256 * u;
       const int which = p >> 10, t = (p >> 6) & (SK - 1), q = p & 63;
       const int64_t row0 = which ? J0 : I0;
-      stage[u] = *(const d2 *)(A + (k + SK * c + t) * lda + row0 + 2 * q);
+      stage[u] = *(const d2 *)(A + (kcol + SK * c + t) * lda + row0 + 2 * q);
     }
   };
   auto store_chunk = [&](int buf) __attribute__((always_inline)) {
@@ -310,7 +345,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t
   load_chunk(0);
   store_chunk(0);
   __syncthreads();
-  constexpr int NCH = CP / SK;
+  const int NCH = kw / SK;
   for (int c = 0; c < NCH; ++c) {
     const int buf = c & 1;
     if (c + 1 < NCH) load_chunk(c + 1);
@@ -342,17 +377,20 @@ __global__ __launch_bounds__(256, 2) void k_syrk(double *__restrict__ A, int64_t
       }
 }
 
-// One segment's factorisation.  Look-ahead over two streams: after panel k, the first
-// tile column of its trailing update (the next panel's columns), the next diagonal block
-// and the next panel run on stream a while the rest of the trailing update runs on stream
-// b.  Stream a's first tile column also waits for b's previous trailing update, which
-// wrote the same columns.
+// One segment's factorisation, two 128-column panels per outer step: panel 2s (diagonal
+// block and rows below), its update of the next 128 columns, panel 2s + 1, then one
+// trailing update of everything beyond with both panels (K = 256, half the read-modify-
+// write traffic of K = 128).  Look-ahead over two streams: stream a runs the panels, the
+// first 128 columns of each trailing update and the next outer step's panels while
+// stream b runs the rest of the trailing update; a waits for b's previous update before
+// it touches the columns that update wrote.
 hipError_t launch_cholesky(double *A, int64_t n, double *dinv, double *logdiag, int32_t *fail,
                            hipStream_t s) {
   const size_t lds = sizeof(double) * (CP * TS + POTF2_TMP);
   hipStream_t sa = nullptr, sb = nullptr;
   hipEvent_t e0 = nullptr, ea = nullptr, eb = nullptr;
   hipError_t err = hipSuccess;
+  bool b_pending = false;  // eb marks an update on b that a has not waited for
   auto chk = [&](hipError_t x) {
     if (err == hipSuccess && x != hipSuccess) err = x;
     return err == hipSuccess;
@@ -371,21 +409,30 @@ hipError_t launch_cholesky(double *A, int64_t n, double *dinv, double *logdiag, 
       chk(hipEventCreateWithFlags(&e0, hipEventDisableTiming)) &&
       chk(hipEventCreateWithFlags(&ea, hipEventDisableTiming)) &&
       chk(hipEventCreateWithFlags(&eb, hipEventDisableTiming)) && chk(hipEventRecord(e0, s)) &&
-      chk(hipStreamWaitEvent(sa, e0, 0)) && chk(hipStreamWaitEvent(sb, e0, 0)) &&
-      diag_and_panel(0)) {
-    for (int64_t k = 0; k + CP < n && err == hipSuccess; k += CP) {
-      const int64_t T = (n - k - CP) / SY;  // tile rows of the trailing region
-      chk(hipEventRecord(ea, sa));           // panel k finished
+      chk(hipStreamWaitEvent(sa, e0, 0)) && chk(hipStreamWaitEvent(sb, e0, 0))) {
+    // n is a multiple of 2 CP (segments are padded to 256 rows)
+    for (int64_t k = 0; k < n && err == hipSuccess; k += 2 * CP) {
+      diag_and_panel(k);
+      // the next 128 columns need b's last update (it covered them) and panel k
+      if (b_pending) chk(hipStreamWaitEvent(sa, eb, 0));
+      b_pending = false;
+      const int64_t T1 = (n - k - CP) / SY;
+      hipLaunchKernelGGL(k_syrk, dim3((unsigned)T1), dim3(256), 0, sa, A, n, k, CP, k + CP, 0, 1,
+                         fail);
+      diag_and_panel(k + CP);
+      const int64_t r0 = k + 2 * CP, T = (n - r0) / SY;
+      if (T <= 0) break;
+      chk(hipEventRecord(ea, sa));  // both panels finished
       if (T > 1) {
         chk(hipStreamWaitEvent(sb, ea, 0));
-        hipLaunchKernelGGL(k_syrk, dim3((unsigned)((T - 1) * T / 2)), dim3(256), 0, sb, A, n, k, 1,
-                           0, fail);
+        hipLaunchKernelGGL(k_syrk, dim3((unsigned)((T - 1) * T / 2)), dim3(256), 0, sb, A, n, k,
+                           2 * CP, r0, 1, 0, fail);
+        chk(hipEventRecord(eb, sb));
+        b_pending = true;
       }
-      if (k > 0) chk(hipStreamWaitEvent(sa, eb, 0));  // b's previous update of these columns
-      hipLaunchKernelGGL(k_syrk, dim3((unsigned)T), dim3(256), 0, sa, A, n, k, 0, 1, fail);
+      hipLaunchKernelGGL(k_syrk, dim3((unsigned)T), dim3(256), 0, sa, A, n, k, 2 * CP, r0, 0, 1,
+                         fail);
       chk(hipGetLastError());
-      chk(hipEventRecord(eb, sb));
-      diag_and_panel(k + CP);
     }
     chk(hipEventRecord(ea, sa));
     chk(hipEventRecord(eb, sb));
