@@ -845,6 +845,9 @@ def run_c5(args, tda, torch, synth, dev, log, duration, fracs, precisions):
             keep.append((h, dk))
             Hs.append(H)
         torch.cuda.synchronize()
+        # the handles took their memory through torch's caching allocator, which keeps what
+        # the compaction released; hand it back for the server's own workspaces
+        torch.cuda.empty_cache()
         setup = time.perf_counter() - t0
         log(f"c5 {prec}: setup {setup:.1f} s")
         # untimed warm-up (code loading, first allocations)

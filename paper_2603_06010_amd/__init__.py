@@ -151,6 +151,21 @@ def _check(status: int):
         raise TdaError(status, msg)
 
 
+_ENOMEM = 3
+
+
+def _call(fn, *args):
+    """Call a library entry point; on TDA_ENOMEM hand PyTorch's cached device memory back
+    to the driver once and try again (handle buffers come from torch's caching allocator,
+    which keeps what it frees, while the library's own workspaces use hipMalloc)."""
+    st = fn(*args)
+    if st == _ENOMEM:
+        import torch
+        torch.cuda.empty_cache()
+        st = fn(*args)
+    _check(st)
+
+
 def _ptr(t) -> int:
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
@@ -212,9 +227,9 @@ class Handle:
                        1 if compact else 0, int(hbm_budget),
                        ctypes.pointer(self._alloc.struct) if self._alloc else None)
         h = ctypes.c_void_p()
-        _check(L.tda_cov_build(acf.ctypes.data, len(acf), int(N), mask_ptr,
-                               ctypes.cast(seg_arr, ctypes.c_void_p) if seg_arr is not None else None,
-                               nseg, ctypes.byref(opt), ctypes.byref(h)))
+        _call(L.tda_cov_build, acf.ctypes.data, len(acf), int(N), mask_ptr,
+              ctypes.cast(seg_arr, ctypes.c_void_p) if seg_arr is not None else None,
+              nseg, ctypes.byref(opt), ctypes.byref(h))
         self._h = h
         self.N = int(N)
         self.precision = _precision(precision)
@@ -224,11 +239,11 @@ class Handle:
         return self._h.value
 
     def factor(self):
-        _check(_lib.tda_factor(self._h))
+        _call(_lib.tda_factor, self._h)
         return self
 
     def set_data(self, d, stream=None):
-        _check(_lib.tda_set_data(self._h, _ptr(d), _stream(stream)))
+        _call(_lib.tda_set_data, self._h, _ptr(d), _stream(stream))
 
     def loglik(self, d, H, out=None, precision=None, stream=None):
         import torch
@@ -242,8 +257,8 @@ class Handle:
         if H.stride(1) != 1:
             raise ValueError("H rows must be contiguous")
         p = self.precision if precision is None else _precision(precision)
-        _check(_lib.tda_loglik_ex(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), p,
-                                  _stream(stream)))
+        _call(_lib.tda_loglik_ex, self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), p,
+              _stream(stream))
         return out
 
     def loglik_noalloc(self, d, H, out, stream=None):
@@ -270,9 +285,9 @@ class Handle:
         if B == 0:
             return out, dh, hh
         p = self.precision if precision is None else _precision(precision)
-        _check(_lib.tda_loglik_terms(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
-                                     _ptr(dh) if dh is not None else None,
-                                     _ptr(hh) if hh is not None else None, p, _stream(stream)))
+        _call(_lib.tda_loglik_terms, self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
+              _ptr(dh) if dh is not None else None, _ptr(hh) if hh is not None else None, p,
+              _stream(stream))
         return out, dh, hh
 
     def whitened_residual(self, d, H, stream=None):
@@ -289,8 +304,8 @@ class Handle:
         W = torch.empty((B, n_eff), dtype=torch.float64, device=H.device)
         if B == 0:
             return out, W
-        _check(_lib.tda_whitened_residual(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
-                                          _ptr(W), W.stride(0), _stream(stream)))
+        _call(_lib.tda_whitened_residual, self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out),
+              _ptr(W), W.stride(0), _stream(stream))
         return out, W
 
     def snr(self, d, H, precision=None, stream=None):
@@ -307,8 +322,8 @@ class Handle:
         out, mf, opt, eff2 = mk(), mk(), mk(), mk()
         if B:
             p = self.precision if precision is None else _precision(precision)
-            _check(_lib.tda_snr(self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), _ptr(mf),
-                                _ptr(opt), _ptr(eff2), p, _stream(stream)))
+            _call(_lib.tda_snr, self._h, _ptr(d), _ptr(H), B, H.stride(0), _ptr(out), _ptr(mf),
+                  _ptr(opt), _ptr(eff2), p, _stream(stream))
         return {"loglik": out, "rho_mf": mf, "rho_opt": opt, "rho_eff2": eff2}
 
     def info(self) -> dict:
@@ -355,8 +370,8 @@ def acf_estimate(x, n_lags, method="welch", seg_len=None, stream=None):
     if x.dtype != torch.float64 or x.dim() != 1 or not x.is_contiguous():
         raise ValueError("x must be a contiguous 1-D float64 tensor")
     out = torch.empty(n_lags, dtype=torch.float64, device=x.device)
-    _check(L.tda_acf_estimate(_ptr(x), x.shape[0], n_lags, m, int(seg_len or 0), _ptr(out),
-                              _stream(stream)))
+    _call(L.tda_acf_estimate, _ptr(x), x.shape[0], n_lags, m, int(seg_len or 0), _ptr(out),
+          _stream(stream))
     return out
 
 
@@ -366,8 +381,8 @@ def loglik_multi(items, precision="fp64", stream=None):
     arr = (_Work * max(len(items), 1))()
     for k, (h, d, H, out) in enumerate(items):
         arr[k] = _Work(h.ptr, _ptr(d), _ptr(H), H.shape[0], H.stride(0), _ptr(out))
-    _check(L.tda_loglik_multi(ctypes.cast(arr, ctypes.c_void_p), len(items),
-                              _precision(precision), _stream(stream)))
+    _call(L.tda_loglik_multi, ctypes.cast(arr, ctypes.c_void_p), len(items),
+          _precision(precision), _stream(stream))
 
 
 class _ServerOptions(ctypes.Structure):
@@ -413,13 +428,13 @@ class Server:
                              int(n_slots), int(max_batch), int(max_queue), int(staging_bytes),
                              int(dataset_budget_bytes))
         s = ctypes.c_void_p()
-        _check(L.tda_server_create(ctypes.byref(opt), ctypes.byref(s)))
+        _call(L.tda_server_create, ctypes.byref(opt), ctypes.byref(s))
         self._s = s
         self._keep = []
 
     def add_dataset(self, handle: Handle, d) -> int:
         i = ctypes.c_int32()
-        _check(_lib.tda_server_add_dataset(self._s, handle.ptr, _ptr(d), ctypes.byref(i)))
+        _call(_lib.tda_server_add_dataset, self._s, handle.ptr, _ptr(d), ctypes.byref(i))
         self._keep.append((handle, d))
         return i.value
 
@@ -474,8 +489,8 @@ class Plan:
             arr[k] = _Work(h.ptr, _ptr(d), _ptr(H), H.shape[0], H.stride(0), _ptr(out))
         self._keep = list(items)
         p = vp()
-        _check(L.tda_plan_create(ctypes.cast(arr, vp), len(items), _precision(precision),
-                                 ctypes.byref(p)))
+        _call(L.tda_plan_create, ctypes.cast(arr, vp), len(items), _precision(precision),
+              ctypes.byref(p))
         self._p = p
 
     def execute(self, stream=None, graph=False):

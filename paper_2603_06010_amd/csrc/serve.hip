@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -137,6 +138,7 @@ struct tda_server {
   int64_t submitted = 0, completed = 0, rejected = 0, launches = 0, templates = 0, max_depth = 0;
   double busy_s = 0, busy_since = -1;
   tda_status error = TDA_OK;
+  std::string error_msg;  // message of the last failed launch (the scheduler thread's)
   size_t slot_stage_bytes = 0;
 
   void scheduler();
@@ -270,6 +272,7 @@ void tda_server::scheduler() {
     lk.lock();
     if (st != TDA_OK) {
       error = st;
+      error_msg = tda_last_error();
       for (const Request &r : take) finish(r.ticket, 2);
       sl.busy = false;
       cv.notify_all();
@@ -431,7 +434,7 @@ extern "C" tda_status tda_server_poll(tda_server_t s, uint64_t ticket, int32_t *
   std::lock_guard<std::mutex> lk(s->mu);
   if (ticket == 0 || ticket >= s->next_ticket) return set_error(TDA_EINVAL, "unknown ticket");
   const uint8_t st = s->status(ticket);
-  if (st == 2) return set_error(TDA_EHIP, "request failed");
+  if (st == 2) return set_error(TDA_EHIP, ("request failed: " + s->error_msg).c_str());
   *done = st == 1;
   return TDA_OK;
 }
@@ -443,7 +446,8 @@ extern "C" tda_status tda_server_wait(tda_server_t s, uint64_t ticket, double ti
   const bool ok = s->cv.wait_for(lk, std::chrono::duration<double>(timeout_s),
                                  [&] { return s->status(ticket) != 0; });
   if (!ok) return TDA_EAGAIN;
-  return s->status(ticket) == 1 ? TDA_OK : set_error(TDA_EHIP, "request failed");
+  return s->status(ticket) == 1 ? TDA_OK
+                                 : set_error(TDA_EHIP, ("request failed: " + s->error_msg).c_str());
 }
 
 extern "C" tda_status tda_server_stats(tda_server_t s, tda_server_stats_t *st, int32_t reset) {
