@@ -49,6 +49,35 @@ __device__ __forceinline__ bf8 load_frag(const uint16_t *p) {
   return *(gbf8 *)(p);
 }
 
+// Device-memory views for the transform kernels: accesses through them compile to
+// global loads and stores.  Pointers read out of a work item are generic, and flat accesses
+// through them also count against the LDS counter, so each wait for an LDS read issued
+// behind one would wait for device memory too.
+template <class T> using gmem = __attribute__((address_space(1))) T;
+template <class T> __device__ __forceinline__ gmem<T> *gp(T *p) { return (gmem<T> *)p; }
+// Values that are the same in every lane, moved to scalar registers: pointers and sizes of a
+// work item are uniform, but read through a reference argument of a called function the
+// compiler cannot tell and holds each in vector registers.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class T> __device__ __forceinline__ T *uni(T *p) {
+  const uint64_t u = (uint64_t)p;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (T *)(lo | (hi << 32));
+}
+// a uniform device-memory view
+template <class T> __device__ __forceinline__ gmem<T> *gpu(T *p) { return uni(gp(p)); }
+// complex doubles in device memory are read and written as a plain vector type (the HIP
+// vector class has no address-space-qualified copy operations)
+typedef double dv2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 from_dv2(dv2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ dv2 to_dv2(double2 v) {
+  dv2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
 // ---------------------------------------------------------------- W64 access
 // W = L^-1 in FP64, compact column tiles of 32 columns: tile ct holds rows
 // [rb[ct], segment end) at w64[off[ct] + (r - rb[ct]) * 32 + (c % 32)].
@@ -1199,7 +1228,34 @@ hipError_t launch_refine(const RefItem *items, const int4 *work, int64_t n_work,
 // an LDS array padded by one element per 16 (bank spread for the strided writes).
 constexpr int RL_THREADS = 512;
 constexpr int RL_XN = (1 << RL_LHMAX) + ((1 << RL_LHMAX) >> 4);
-constexpr size_t RL_LDS_BYTES = (size_t)RL_XN * sizeof(double2) + RL_THREADS * sizeof(double);
+constexpr int RL_RED = 4 * (RL_THREADS / 64);  // per-wave partial sums, up to 4 values
+constexpr size_t RL_LDS_BYTES = (size_t)RL_XN * sizeof(double2) + RL_RED * sizeof(double);
+
+// Sums of K values over the workgroup, valid on thread 0 only: a butterfly within each
+// wave, then thread 0 adds the waves' partial sums in wave order (so the result does not
+// depend on timing).  Ends with a barrier, so `red` may be reused at once.
+template <int K>
+__device__ __forceinline__ void block_sum0(double (&v)[K], double *red) {
+  static_assert(K * (RL_THREADS / 64) <= RL_RED, "partial sums fit");
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] += __shfl_xor(v[i], o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < K; ++i) red[w * K + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      double a = red[i];
+      for (int u = 1; u < (int)(blockDim.x >> 6); ++u) a += red[u * K + i];
+      v[i] = a;
+    }
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 __device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
@@ -1252,7 +1308,7 @@ __device__ __forceinline__ void dft_small(double2 (&v)[1 << L]) {
 // Thread t takes j = t + RL_THREADS g, g < G; every element is read into registers before
 // any is written back, so the pass works in place.
 template <int LH, int P>
-__device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ ptw) {
+__device__ __forceinline__ void rl_pass(double2 *X, const gmem<const dv2> *__restrict__ ptw) {
   constexpr int L = rl_L(LH, P), LNS = rl_lns(LH, P), OFF = rl_off(LH, P);
   constexpr int R = 1 << L, NS = 1 << LNS, NT = 1 << (LH - L);
   constexpr int G = NT > RL_THREADS ? NT / RL_THREADS : 1;
@@ -1275,10 +1331,10 @@ __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ 
       }
       if constexpr (LNS > 0) {
         // a few twiddles at a time, so they do not all hold registers at once
-        const double2 *tk = ptw + OFF + k * (R - 1);
+        const gmem<const dv2> *tk = ptw + OFF + k * (R - 1);
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          a[g][q] = cmul(a[g][q], tk[q - 1]);
+          a[g][q] = cmul(a[g][q], from_dv2(tk[q - 1]));
           if (q % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
@@ -1309,7 +1365,7 @@ __device__ __forceinline__ void rl_pass(double2 *X, const double2 *__restrict__ 
 }
 
 template <int LH>
-__device__ __forceinline__ void rl_fft(double2 *X, const double2 *ptw) {
+__device__ __forceinline__ void rl_fft(double2 *X, const gmem<const dv2> *ptw) {
   static_assert(rl_npass(LH) <= 4, "at most four passes");
   rl_pass<LH, 0>(X, ptw);
   if constexpr (rl_npass(LH) > 1) rl_pass<LH, 1>(X, ptw);
@@ -1362,11 +1418,19 @@ __device__ __forceinline__ void rl_odd_pair(double2 vk, double2 vr, Mul la, Mul 
 }
 
 // Element-wise phases: a thread handles positions p = t + RL_THREADS i (samples 2p and
-// 2p + 1) or frequency pairs k = t + RL_THREADS i.  Every global access of a chunk of
-// RL_CH iterations is issued before any of its values is used, so the loads of a chunk
-// are in flight together (stores to e would otherwise keep later loads from being
-// hoisted).  Segments without excluded samples compute rows instead of loading them.
-constexpr int RL_CH = 4;
+// 2p + 1) or frequency pairs k = t + RL_THREADS i.  A phase issues the device-memory
+// accesses of a whole batch of positions before it uses any of them, so it waits for
+// memory once per batch: the phases that read y0 (or nothing) and the pointwise ones take
+// up to RL_CHL positions at once (all of a thread's at h = 8192), the final phase, which
+// reads four arrays, RL_CHF.  (Stores to e would otherwise keep later loads from being
+// hoisted above them.)  Segments without excluded samples compute rows instead of loading
+// them, and read or write the y0 and e values of a sample pair as one vector (the pair's
+// first row is even there).
+constexpr int RL_CH = 4;    // batch of the split transforms' phases
+constexpr int RL_CHL = 16;  // batch of the in-LDS phases that read y0 only, and pointwise ones
+constexpr int RL_CHF = 8;   // batch of the final in-LDS phase
+
+typedef float fv2 __attribute__((ext_vector_type(2)));
 
 template <int LH>
 __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int64_t b, double2 *X,
@@ -1375,71 +1439,101 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   constexpr int NI = h >= RL_THREADS ? h / RL_THREADS : 1;         // position iterations
   constexpr int NKE = (h / 2 + RL_THREADS) / RL_THREADS;           // k = 0 .. h/2
   constexpr int NKO = h / 2 >= RL_THREADS ? h / 2 / RL_THREADS : 1; // k = 0 .. h/2 - 1
-  const int t = threadIdx.x;
-  const float *__restrict__ y = it.y0 + b * it.n_pad;
-  const double *__restrict__ hrow = template_row(it, b) + sd.offset;
-  const double *__restrict__ ydp = it.yd_pos + sd.offset;
-  const int32_t *__restrict__ p2r = it.pos2row + sd.offset;
-  double *__restrict__ e = it.e64 + b * it.n_pad;
-  const double2 *__restrict__ tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
-  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
-  const double *__restrict__ lam = sd.lam;
-  const int len = (int)sd.length;
-  const bool dense = sd.nkeep == sd.length;
-  const int32_t row0 = (int32_t)sd.row0;
+  constexpr int CL = NI < RL_CHL ? NI : RL_CHL;
+  constexpr int CF = NI < RL_CHF ? NI : RL_CHF;
+  constexpr int CKE = NKE < RL_CHL ? NKE : RL_CHL;
+  constexpr int CKO = NKO < RL_CHL ? NKO : RL_CHL;
+  // the thread index is re-read (opaquely) at each phase, so that per-position rows, masks
+  // and addresses are recomputed there rather than held in registers across phases
+  int t = opaque_tid();
+  const gmem<const float> *__restrict__ y = gpu(it.y0 + b * it.n_pad);
+  const gmem<const double> *__restrict__ hrow = gpu(template_row(it, b) + sd.offset);
+  const gmem<const double> *__restrict__ ydp = gpu(it.yd_pos + sd.offset);
+  const gmem<const int32_t> *__restrict__ p2r = gpu(it.pos2row + sd.offset);
+  gmem<double> *__restrict__ e = gpu(it.e64 + b * it.n_pad);
+  const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);  // (cos, sin) of 2 pi r / m
+  const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);
+  const gmem<const double> *__restrict__ lam = gpu(sd.lam);
+  const int len = uni((int)sd.length);
+  const bool dense = uni((int)(sd.nkeep == sd.length)) != 0;
+  const int32_t row0 = uni((int32_t)sd.row0);
   const double inv_m = 1.0 / (double)(4 * h);
+  // sums kept in registers here and added to the caller's at the end (through the reference
+  // every update would be a store to memory)
+  RlAcc a{0, 0, 0, 0};
   auto wm = [&](int r) {  // w_m^r, 0 <= r < m
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
-  // padded row of sample jj of the segment; -1 if excluded or beyond the segment
-  auto row_of = [&](int jj) -> int32_t {
-    if (jj >= len) return -1;
-    return dense ? row0 + jj : p2r[jj];
+  auto in_pos = [&](int i) { return i < NI && t + RL_THREADS * i < h; };
+  // padded rows of samples 2p, 2p + 1 of position i; -1 if excluded or beyond the segment
+  auto rows = [&](int i, int32_t (&r)[2]) {
+    const int jj = 2 * (t + RL_THREADS * i);
+    const bool in = in_pos(i);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      r[u] = !in || jj + u >= len ? -1 : dense ? row0 + jj + u : p2r[jj + u];
+  };
+  // y0 at rows r (0 where excluded)
+  auto load_y = [&](const int32_t (&r)[2]) -> fv2 {
+    fv2 v;
+    if (dense && r[1] >= 0) {
+      v = *(const gmem<const fv2> *)(y + r[0]);
+    } else {
+      v.x = r[0] >= 0 ? y[r[0]] : 0.f;
+      v.y = r[1] >= 0 ? y[r[1]] : 0.f;
+    }
+    return v;
+  };
+  auto store_e = [&](const int32_t (&r)[2], double v0, double v1) {
+    if (dense && r[1] >= 0) {
+      dv2 v;
+      v.x = v0;
+      v.y = v1;
+      *(gmem<dv2> *)(e + r[0]) = v;
+    } else {
+      if (r[0] >= 0) e[r[0]] = v0;
+      if (r[1] >= 0) e[r[1]] = v1;
+    }
   };
   auto finite_or_flag = [&](float v) -> double {
     if (!isfinite(v)) {
-      acc.bad = 1.0;
+      a.bad = 1.0;
       return 0.0;
     }
     return (double)v;
   };
-  // rows and y0 values of the samples 2p, 2p + 1 of chunk i0
-  auto load_x = [&](int i0, int32_t (&rr)[RL_CH][2], float (&xv)[RL_CH][2]) {
-#pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      const bool in = i0 + c < NI && p < h;
-      rr[c][0] = in ? row_of(2 * p) : -1;
-      rr[c][1] = in ? row_of(2 * p + 1) : -1;
-    }
-#pragma unroll
-    for (int c = 0; c < RL_CH; ++c)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) xv[c][u] = rr[c][u] >= 0 ? y[rr[c][u]] : 0.f;
-  };
+  // A thread's sample pairs keep their y0 values and the circulant part t_E / m in
+  // registers from the phase that produces them to the final one, so y0 is read from
+  // device memory once and t_E never goes there.
+  fv2 yk[NI];
+  double2 te[NI];
 
   for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
 
   // ---- even frequencies: circulant part
-  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-    int32_t rr[RL_CH][2];
-    float xv[RL_CH][2];
-    load_x(i0, rr, xv);
+  t = opaque_tid();
+  for (int i0 = 0; i0 < NI; i0 += CL) {
+    int32_t r[CL][2];
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (i0 + c < NI && p < h)
-        X[lpad(p)] = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
+    for (int c = 0; c < CL; ++c) rows(i0 + c, r[c]);
+#pragma unroll
+    for (int c = 0; c < CL; ++c) yk[i0 + c] = load_y(r[c]);
+#pragma unroll
+    for (int c = 0; c < CL; ++c) {
+      if (!in_pos(i0 + c)) continue;
+      X[lpad(t + RL_THREADS * (i0 + c))] =
+          make_double2(finite_or_flag(yk[i0 + c].x), finite_or_flag(yk[i0 + c].y));
     }
   }
   __syncthreads();
   rl_fft<LH>(X, ptw);
-  for (int i0 = 0; i0 < NKE; i0 += RL_CH) {
-    double la[RL_CH], lb[RL_CH];
-    double2 cc[RL_CH];
+  t = opaque_tid();
+  for (int i0 = 0; i0 < NKE; i0 += CKE) {
+    double la[CKE], lb[CKE];
+    double2 cc[CKE];
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
+    for (int c = 0; c < CKE; ++c) {
       const int k = t + RL_THREADS * (i0 + c);
       if (i0 + c < NKE && k <= h / 2) {
         la[c] = lam[2 * k];
@@ -1448,7 +1542,7 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
       }
     }
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
+    for (int c = 0; c < CKE; ++c) {
       const int k = t + RL_THREADS * (i0 + c);
       if (!(i0 + c < NKE && k <= h / 2)) continue;
       const int kr = (h - k) & (h - 1);
@@ -1460,53 +1554,30 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   }
   __syncthreads();
   rl_fft<LH>(X, ptw);
-  // tE_{2p} + i tE_{2p+1} = conj(X[p]); kept (scaled) in e until the odd part adds to it
-  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-    int32_t rr[RL_CH][2];
+  // tE_{2p} + i tE_{2p+1} = conj(X[p]), then the odd part's input over it: each thread
+  // reads and writes only its own positions here, so no barrier between the two
+  t = opaque_tid();
+  const double2 om = wm(1);
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      const bool in = i0 + c < NI && p < h;
-      rr[c][0] = in ? row_of(2 * p) : -1;
-      rr[c][1] = in ? row_of(2 * p + 1) : -1;
-    }
-#pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (!(i0 + c < NI && p < h)) continue;
-      const double2 v = X[lpad(p)];
-      if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
-      if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
-    }
+  for (int i = 0; i < NI; ++i) {
+    if (!in_pos(i)) continue;
+    const int p = t + RL_THREADS * i;
+    const double2 v = X[lpad(p)];
+    te[i] = make_double2(v.x * inv_m, -v.y * inv_m);
+    const double2 z = make_double2(isfinite(yk[i].x) ? (double)yk[i].x : 0.0,
+                                   isfinite(yk[i].y) ? (double)yk[i].y : 0.0);
+    X[lpad(p)] = cmul(z, wm(2 * p));
   }
   __syncthreads();
 
   // ---- odd frequencies: skew-circulant part
-  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-    int32_t rr[RL_CH][2];
-    float xv[RL_CH][2];
-    double2 wp[RL_CH];
-    load_x(i0, rr, xv);
-#pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (i0 + c < NI && p < h) wp[c] = wm(2 * p);
-    }
-#pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (i0 + c < NI && p < h)
-        X[lpad(p)] = cmul(make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1])), wp[c]);
-    }
-  }
-  __syncthreads();
   rl_fft<LH>(X, ptw);
-  const double2 om = wm(1);
-  for (int i0 = 0; i0 < NKO; i0 += RL_CH) {
-    double la[RL_CH], lb[RL_CH];
-    double2 dd[RL_CH], cc[RL_CH];
+  t = opaque_tid();
+  for (int i0 = 0; i0 < NKO; i0 += CKO) {
+    double la[CKO], lb[CKO];
+    double2 dd[CKO], cc[CKO];
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
+    for (int c = 0; c < CKO; ++c) {
       const int k = t + RL_THREADS * (i0 + c);
       if (i0 + c < NKO && k < h / 2) {
         la[c] = lam[2 * k + 1];
@@ -1516,7 +1587,7 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
       }
     }
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
+    for (int c = 0; c < CKO; ++c) {
       const int k = t + RL_THREADS * (i0 + c);
       if (!(i0 + c < NKO && k < h / 2)) continue;
       const int kr = h - 1 - k;
@@ -1528,45 +1599,51 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   }
   __syncthreads();
   rl_fft<LH>(X, ptw);
-  // tO_{2p} + i tO_{2p+1} = conj(w_m^{2p} X[p]); the same thread owns positions 2p, 2p+1 in
-  // both parts, so e holds its own tE here
-  for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-    int32_t rr[RL_CH][2];
-    float xv[RL_CH][2];
-    double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
-    double2 wp[RL_CH];
-    load_x(i0, rr, xv);
+  // tO_{2p} + i tO_{2p+1} = conj(w_m^{2p} X[p]); C y0 = tE / m + tO / m
+  t = opaque_tid();
+  for (int i0 = 0; i0 < NI; i0 += CF) {
+    int32_t r[CF][2];
+    double hv[CF][2], yv[CF][2];
+    double2 wp[CF];
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (!(i0 + c < NI && p < h)) continue;
-      wp[c] = wm(2 * p);
+    for (int c = 0; c < CF; ++c) rows(i0 + c, r[c]);
+#pragma unroll
+    for (int c = 0; c < CF; ++c) {
+      if (!in_pos(i0 + c)) continue;
+      const int jj = 2 * (t + RL_THREADS * (i0 + c));
+      wp[c] = wm(jj);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int jj = 2 * p + u;
-        ev[c][u] = rr[c][u] >= 0 ? e[rr[c][u]] : 0.0;
-        hv[c][u] = rr[c][u] >= 0 ? hrow[jj] : 0.0;
-        yv[c][u] = rr[c][u] >= 0 ? ydp[jj] : 0.0;
+        hv[c][u] = r[c][u] >= 0 ? hrow[jj + u] : 0.0;
+        yv[c][u] = r[c][u] >= 0 ? ydp[jj + u] : 0.0;
       }
     }
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
-      const int p = t + RL_THREADS * (i0 + c);
-      if (!(i0 + c < NI && p < h)) continue;
-      const double2 gz = conj2(cmul(wp[c], X[lpad(p)]));
+    for (int c = 0; c < CF; ++c) {
+      if (!in_pos(i0 + c)) continue;
+      const double2 gz = conj2(cmul(wp[c], X[lpad(t + RL_THREADS * (i0 + c))]));
+      const double2 tv = te[i0 + c];
+      const fv2 yy = yk[i0 + c];
+      double ov[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        if (rr[c][u] < 0) continue;
-        const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
-        const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
-        e[rr[c][u]] = hv[c][u] - cz;
-        acc.hy += hv[c][u] * xd;
-        acc.ydh += hv[c][u] * yv[c][u];
-        acc.yc += xd * cz;
+        const double cz = (u ? tv.y : tv.x) + (u ? gz.y : gz.x) * inv_m;
+        const float yf = u ? yy.y : yy.x;
+        const double xd = isfinite(yf) ? (double)yf : 0.0;
+        ov[u] = hv[c][u] - cz;
+        if (r[c][u] < 0) continue;
+        a.hy += hv[c][u] * xd;
+        a.ydh += hv[c][u] * yv[c][u];
+        a.yc += xd * cz;
       }
+      store_e(r[c], ov[0], ov[1]);
     }
   }
   __syncthreads();
+  acc.hy += a.hy;
+  acc.ydh += a.ydh;
+  acc.yc += a.yc;
+  acc.bad += a.bad;
 }
 
 // Segments whose packed h-point DFTs (h = 2 hh, hh = 2^(LH-1) the largest in-LDS length)
@@ -1590,15 +1667,15 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
 // The thread index is re-read (opaquely) at each phase, so that per-position addresses and
 // masks are recomputed there instead of being held in registers across phases.
 template <int LH, class Stage, class Mult, class Emit>
-__device__ __forceinline__ void rl_split_parts(double2 *X, const double2 *__restrict__ tw,
-                                               const double2 *__restrict__ ptw, Stage &&stage,
+__device__ __forceinline__ void rl_split_parts(double2 *X, const gmem<const dv2> *__restrict__ tw,
+                                               const gmem<const dv2> *__restrict__ ptw, Stage &&stage,
                                                Mult &&mult, Emit &&emit) {
   constexpr int LHH = LH - 1;
   constexpr int h = 1 << LH, hh = 1 << LHH;
   static_assert(hh >= 2 * RL_THREADS && hh % (2 * RL_THREADS) == 0, "whole quadruples per thread");
   constexpr int NQ = hh / 2 / RL_THREADS;  // quadruples per thread
   auto wm = [&](int r) {  // w_m^r, 0 <= r < m
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
   int t = opaque_tid();
@@ -1702,9 +1779,9 @@ __device__ __forceinline__ void dft4(const double2 (&u)[4], double2 (&v)[4]) {
 }
 
 template <int LH, class Stage, class Mult, class Emit>
-__device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ S,
-                                              const double2 *__restrict__ tw,
-                                              const double2 *__restrict__ ptw, Stage &&stage,
+__device__ __forceinline__ void rl_quad_parts(double2 *X, gmem<dv2> *__restrict__ S,
+                                              const gmem<const dv2> *__restrict__ tw,
+                                              const gmem<const dv2> *__restrict__ ptw, Stage &&stage,
                                               Mult &&mult, Emit &&emit) {
   constexpr int LHQ = LH - 2;
   constexpr int h = 1 << LH, hq = 1 << LHQ;
@@ -1712,7 +1789,7 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
   constexpr int NI = hq / RL_THREADS;      // positions per thread and quarter
   constexpr int NG = hq / 2 / RL_THREADS;  // groups per thread
   auto wm = [&](int r) {  // w_m^r, 0 <= r < m
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
   int t = opaque_tid();
@@ -1727,7 +1804,7 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
         t = opaque_tid();
         for (int i = 0; i < NI; ++i) {
           const int n = t + RL_THREADS * i;
-          S[s * hq + n] = X[lpad(n)];
+          S[s * hq + n] = to_dv2(X[lpad(n)]);
         }
         __syncthreads();
       }
@@ -1743,13 +1820,13 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
       {
         double2 u[4];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] = S[q * hq + k0];
+        for (int q = 0; q < 3; ++q) u[q] = from_dv2(S[q * hq + k0]);
         u[3] = X[lpad(k0)];
 #pragma unroll
         for (int q = 1; q < 4; ++q) u[q] = cmul(wm(4 * q * k0), u[q]);
         dft4(u, za);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] = S[q * hq + k1];
+        for (int q = 0; q < 3; ++q) u[q] = from_dv2(S[q * hq + k1]);
         u[3] = X[lpad(k1)];
 #pragma unroll
         for (int q = 1; q < 4; ++q) u[q] = cmul(wm(4 * q * k1), u[q]);
@@ -1778,12 +1855,12 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
       dft4(ga, v);
       X[lpad(k0)] = cmul(wm(12 * k0), v[3]);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) S[q * hq + k0] = q ? cmul(wm(4 * q * k0), v[q]) : v[q];
+      for (int q = 0; q < 3; ++q) S[q * hq + k0] = to_dv2(q ? cmul(wm(4 * q * k0), v[q]) : v[q]);
       if (k1 != k0) {
         dft4(gb, v);
         X[lpad(k1)] = cmul(wm(12 * k1), v[3]);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) S[q * hq + k1] = q ? cmul(wm(4 * q * k1), v[q]) : v[q];
+        for (int q = 0; q < 3; ++q) S[q * hq + k1] = to_dv2(q ? cmul(wm(4 * q * k1), v[q]) : v[q]);
       }
     }
     __syncthreads();
@@ -1793,7 +1870,7 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
         t = opaque_tid();
         for (int i = 0; i < NI; ++i) {
           const int n = t + RL_THREADS * i;
-          X[lpad(n)] = S[s * hq + n];
+          X[lpad(n)] = from_dv2(S[s * hq + n]);
         }
         __syncthreads();
       }
@@ -1810,26 +1887,29 @@ __device__ __forceinline__ void rl_quad_parts(double2 *X, double2 *__restrict__ 
 // 2 P n + 2 s + 1.
 template <int LH, int P>
 __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &sd, int64_t b,
-                                              double2 *X, double2 *S, RlAcc &acc) {
+                                              double2 *X, gmem<dv2> *S_, RlAcc &acc) {
+  gmem<dv2> *S = uni(S_);
   static_assert(P == 2 || P == 4, "halves or quarters");
   constexpr int h = 1 << LH;
   constexpr int NI = h / P / RL_THREADS;  // position iterations per part
-  static_assert(NI % RL_CH == 0, "whole chunks");
+  constexpr int CH = NI < RL_CH ? NI : RL_CH;  // positions per batch of memory accesses
+  static_assert(NI % CH == 0, "whole chunks");
   int t = opaque_tid();
-  const float *__restrict__ y = it.y0 + b * it.n_pad;
-  const double *__restrict__ hrow = template_row(it, b) + sd.offset;
-  const double *__restrict__ ydp = it.yd_pos + sd.offset;
-  const int32_t *__restrict__ p2r = it.pos2row + sd.offset;
-  double *__restrict__ e = it.e64 + b * it.n_pad;
-  const double2 *__restrict__ tw = (const double2 *)sd.tw;  // (cos, sin) of 2 pi r / m
-  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;  // passes of the part DFTs
-  const double *__restrict__ lam = sd.lam;
-  const int len = (int)sd.length;
-  const bool dense = sd.nkeep == sd.length;
-  const int32_t row0 = (int32_t)sd.row0;
+  const gmem<const float> *__restrict__ y = gpu(it.y0 + b * it.n_pad);
+  const gmem<const double> *__restrict__ hrow = gpu(template_row(it, b) + sd.offset);
+  const gmem<const double> *__restrict__ ydp = gpu(it.yd_pos + sd.offset);
+  const gmem<const int32_t> *__restrict__ p2r = gpu(it.pos2row + sd.offset);
+  gmem<double> *__restrict__ e = gpu(it.e64 + b * it.n_pad);
+  const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);  // (cos, sin) of 2 pi r / m
+  const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);  // passes of the part DFTs
+  const gmem<const double> *__restrict__ lam = gpu(sd.lam);
+  const int len = uni((int)sd.length);
+  const bool dense = uni((int)(sd.nkeep == sd.length)) != 0;
+  const int32_t row0 = uni((int32_t)sd.row0);
   const double inv_m = 1.0 / (double)(4 * h);
+  RlAcc a{0, 0, 0, 0};  // added to the caller's sums at the end
   auto wm = [&](int r) {  // w_m^r, 0 <= r < m
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
   auto row_of = [&](int jj) -> int32_t {
@@ -1838,32 +1918,32 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   };
   auto finite_or_flag = [&](float v) -> double {
     if (!isfinite(v)) {
-      acc.bad = 1.0;
+      a.bad = 1.0;
       return 0.0;
     }
     return (double)v;
   };
   // rows and y0 values of the samples 2Pn + 2s, 2Pn + 2s + 1, n = t + RL_THREADS (i0 + c)
-  auto load_x = [&](int i0, int s, int32_t (&rr)[RL_CH][2], float (&xv)[RL_CH][2]) {
+  auto load_x = [&](int i0, int s, int32_t (&rr)[CH][2], float (&xv)[CH][2]) {
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c) {
+    for (int c = 0; c < CH; ++c) {
       const int n = t + RL_THREADS * (i0 + c);
       rr[c][0] = row_of(2 * P * n + 2 * s);
       rr[c][1] = row_of(2 * P * n + 2 * s + 1);
     }
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c)
+    for (int c = 0; c < CH; ++c)
 #pragma unroll
       for (int u = 0; u < 2; ++u) xv[c][u] = rr[c][u] >= 0 ? y[rr[c][u]] : 0.f;
   };
   auto stage = [&](int s, bool odd) {
     t = opaque_tid();
-    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-      int32_t rr[RL_CH][2];
-      float xv[RL_CH][2];
+    for (int i0 = 0; i0 < NI; i0 += CH) {
+      int32_t rr[CH][2];
+      float xv[CH][2];
       load_x(i0, s, rr, xv);
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
+      for (int c = 0; c < CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 z = make_double2(finite_or_flag(xv[c][0]), finite_or_flag(xv[c][1]));
         X[lpad(n)] = odd ? cmul(z, wm(2 * P * n + 2 * s)) : z;
@@ -1876,28 +1956,28 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   // e = h - C y0 and the dot products
   auto emit = [&](int s, bool odd) {
     t = opaque_tid();
-    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-      int32_t rr[RL_CH][2];
-      float xv[RL_CH][2];
+    for (int i0 = 0; i0 < NI; i0 += CH) {
+      int32_t rr[CH][2];
+      float xv[CH][2];
       if (!odd) {
 #pragma unroll
-        for (int c = 0; c < RL_CH; ++c) {
+        for (int c = 0; c < CH; ++c) {
           const int n = t + RL_THREADS * (i0 + c);
           rr[c][0] = row_of(2 * P * n + 2 * s);
           rr[c][1] = row_of(2 * P * n + 2 * s + 1);
         }
 #pragma unroll
-        for (int c = 0; c < RL_CH; ++c) {
+        for (int c = 0; c < CH; ++c) {
           const double2 v = X[lpad(t + RL_THREADS * (i0 + c))];
           if (rr[c][0] >= 0) e[rr[c][0]] = v.x * inv_m;
           if (rr[c][1] >= 0) e[rr[c][1]] = -v.y * inv_m;
         }
         continue;
       }
-      double ev[RL_CH][2], hv[RL_CH][2], yv[RL_CH][2];
+      double ev[CH][2], hv[CH][2], yv[CH][2];
       load_x(i0, s, rr, xv);
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
+      for (int c = 0; c < CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -1908,7 +1988,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
         }
       }
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
+      for (int c = 0; c < CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 gz = conj2(cmul(wm(2 * P * n + 2 * s), X[lpad(n)]));
 #pragma unroll
@@ -1917,9 +1997,9 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
           const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
           const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
           e[rr[c][u]] = hv[c][u] - cz;
-          acc.hy += hv[c][u] * xd;
-          acc.ydh += hv[c][u] * yv[c][u];
-          acc.yc += xd * cz;
+          a.hy += hv[c][u] * xd;
+          a.ydh += hv[c][u] * yv[c][u];
+          a.yc += xd * cz;
         }
       }
     }
@@ -1930,6 +2010,10 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
     rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
   else
     rl_quad_parts<LH>(X, S, tw, ptw, stage, mult, emit);
+  acc.hy += a.hy;
+  acc.ydh += a.ydh;
+  acc.yc += a.yc;
+  acc.bad += a.bad;
 }
 
 // Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
@@ -1942,7 +2026,7 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
   extern __shared__ double2 rl_smem[];
   double2 *X = rl_smem;
   double *red = (double *)(rl_smem + RL_XN);
-  double2 *S = qscratch ? qscratch + (int64_t)blockIdx.x * RL_QUAD_SCRATCH : nullptr;
+  gmem<dv2> *S = qscratch ? gpu((dv2 *)(qscratch + (int64_t)blockIdx.x * RL_QUAD_SCRATCH)) : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
     const RefItem &it = items[wk.x];
@@ -1964,9 +2048,10 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
         default: acc.bad = 1.0;
       }
     }
-    const double s_hy = block_sum(acc.hy, red), s_ydh = block_sum(acc.ydh, red);
-    const double s_yc = block_sum(acc.yc, red), s_bad = block_sum(acc.bad, red);
+    double sums[4] = {acc.hy, acc.ydh, acc.yc, acc.bad};
+    block_sum0(sums, red);
     if (threadIdx.x == 0) {
+      const double s_hy = sums[0], s_ydh = sums[1], s_yc = sums[2], s_bad = sums[3];
       const double nan = __builtin_nan("");
       it.qpart[b] = s_bad > 0 ? nan : it.qdd[0] - 2.0 * s_ydh + 2.0 * s_hy - s_yc;
       if (it.dh_out) it.dh_out[b] = s_bad > 0 || isnan(it.qdd[0]) ? nan : s_ydh;
@@ -2098,162 +2183,216 @@ hipError_t launch_gs_spectra(const double *x, int64_t n, int64_t m, const double
   return hipGetLastError();
 }
 
-// Sum over this thread's outputs j < length of (L(v)^T r)_j^2, with M = conj(DFT_m(v)).
+// Sums over this thread's outputs j < length of (L(v)^T r)_j^2 for the two generators
+// v = x (multiplier M1 = conj(DFT_m(x))) and v = z (M2); returns the first minus the
+// second.  Both products start from the same transform of the residual, so each part
+// (circulant, skew-circulant) takes one forward DFT and two inverse ones: the pointwise
+// stage writes the first product's input to LDS and keeps the second's in registers until
+// the first has been transformed back.  The first product's circulant output waits in the
+// workgroup's scratch at tes, the second's at tes2.
 template <int LH>
-__device__ __noinline__ double gs_sumsq(const GsItem &it, const GsSeg &sd, int64_t b,
-                                        const double2 *__restrict__ M, double2 *X,
-                                        double *__restrict__ tes) {
+__device__ __noinline__ double gs_pair(const GsItem &it, const GsSeg &sd, int64_t b,
+                                       const gmem<const dv2> *__restrict__ M1_,
+                                       const gmem<const dv2> *__restrict__ M2_, double2 *X,
+                                       gmem<double> *__restrict__ tes_) {
   constexpr int h = 1 << LH;
   constexpr int NI = h >= RL_THREADS ? h / RL_THREADS : 1;
   constexpr int NKE = (h / 2 + RL_THREADS) / RL_THREADS;
   constexpr int NKO = h / 2 >= RL_THREADS ? h / 2 / RL_THREADS : 1;
-  const int t = threadIdx.x;
-  const double *__restrict__ hrow = gs_template_row(it, b) + sd.offset;
-  const double *__restrict__ dd = it.d + sd.offset;
-  const double2 *__restrict__ tw = (const double2 *)sd.tw;
-  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
-  const int len = (int)sd.length;
+  constexpr int CL = NI < RL_CHL ? NI : RL_CHL;
+  constexpr int CK = 3;  // frequency pairs per batch of multiplier loads
+  const gmem<const dv2> *__restrict__ M1 = uni(M1_);
+  const gmem<const dv2> *__restrict__ M2 = uni(M2_);
+  gmem<double> *__restrict__ tes = uni(tes_);
+  const gmem<const double> *__restrict__ hrow = gpu(gs_template_row(it, b) + sd.offset);
+  const gmem<const double> *__restrict__ dd = gpu(it.d + sd.offset);
+  const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);
+  const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);
+  const int len = uni((int)sd.length);
+  gmem<double> *__restrict__ tes2 = tes + ((len + 1) & ~1);
   const double inv_m = 1.0 / (double)(4 * h);
+  // the thread index is re-read (opaquely) at each phase, so that per-position addresses
+  // and masks are recomputed there rather than held in registers across phases
+  int t = opaque_tid();
   auto wm = [&](int r) {
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
-  // residual samples 2p, 2p + 1 of chunk i0 (0 beyond the segment)
-  auto load_r = [&](int i0, double (&rv)[RL_CH][2]) {
+  auto in_pos = [&](int i) { return i < NI && t + RL_THREADS * i < h; };
+  // residual samples 2p, 2p + 1 into X (times w_m^{2p} for the skew-circulant part)
+  auto stage = [&](bool odd) {
+    t = opaque_tid();
+    for (int i0 = 0; i0 < NI; i0 += CL) {
+      double rv[CL][2];
+      double2 wp[CL];
 #pragma unroll
-    for (int c = 0; c < RL_CH; ++c)
+      for (int c = 0; c < CL; ++c) {
+        const int jj = 2 * (t + RL_THREADS * (i0 + c));
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int jj = 2 * (t + RL_THREADS * (i0 + c)) + u;
-        rv[c][u] = (i0 + c < NI && jj < len) ? dd[jj] - hrow[jj] : 0.0;
+        for (int u = 0; u < 2; ++u)
+          rv[c][u] = (in_pos(i0 + c) && jj + u < len) ? dd[jj + u] - hrow[jj + u] : 0.0;
+        if (odd && in_pos(i0 + c)) wp[c] = wm(jj);
       }
+#pragma unroll
+      for (int c = 0; c < CL; ++c) {
+        if (!in_pos(i0 + c)) continue;
+        const double2 z = make_double2(rv[c][0], rv[c][1]);
+        X[lpad(t + RL_THREADS * (i0 + c))] = odd ? cmul(z, wp[c]) : z;
+      }
+    }
+    __syncthreads();
   };
-  double ss = 0.0;
-  {
-    // ---- even frequencies
-    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-      double rv[RL_CH][2];
-      load_r(i0, rv);
+  // the second product's input, written by the thread that computed it
+  constexpr int NG = ((NKE > NKO ? NKE : NKO) + CK - 1) / CK * CK;
+  double2 g2k[NG], g2r[NG];
+  auto second_to_lds = [&](auto odd_c) {
+    constexpr bool odd = decltype(odd_c)::value;
+    t = opaque_tid();
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int p = t + RL_THREADS * (i0 + c);
-        if (i0 + c < NI && p < h) X[lpad(p)] = make_double2(rv[c][0], rv[c][1]);
-      }
+    for (int c = 0; c < (odd ? NKO : NKE); ++c) {
+      const int k = t + RL_THREADS * c;
+      if (odd ? !(k < h / 2) : !(k <= h / 2)) continue;
+      const int kr = odd ? h - 1 - k : (h - k) & (h - 1);
+      X[lpad(k)] = g2k[c];
+      if (odd || (k != 0 && k != h / 2)) X[lpad(kr)] = g2r[c];
     }
     __syncthreads();
-    rl_fft<LH>(X, ptw);
-    for (int i0 = 0; i0 < NKE; i0 += RL_CH) {
-      double2 ma[RL_CH], mb[RL_CH], cc[RL_CH];
+  };
+
+  // ---- even frequencies
+  stage(false);
+  rl_fft<LH>(X, ptw);
+  t = opaque_tid();
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int k = t + RL_THREADS * (i0 + c);
-        if (i0 + c < NKE && k <= h / 2) {
-          ma[c] = M[2 * k];
-          mb[c] = M[2 * h - 2 * k];
-          cc[c] = wm(2 * k);
-        }
-      }
+  for (int i0 = 0; i0 < NKE; i0 += CK) {
+    double2 m1a[CK], m1b[CK], m2a[CK], m2b[CK], cc[CK];
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int k = t + RL_THREADS * (i0 + c);
-        if (!(i0 + c < NKE && k <= h / 2)) continue;
-        const int kr = (h - k) & (h - 1);
-        double2 gk, gr;
-        rl_even_pair(X[lpad(k)], X[lpad(kr)], ma[c], mb[c], cc[c], gk, gr);
-        X[lpad(k)] = gk;
-        if (k != 0 && k != h / 2) X[lpad(kr)] = gr;
+    for (int c = 0; c < CK; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NKE && k <= h / 2) {
+        m1a[c] = from_dv2(M1[2 * k]);
+        m1b[c] = from_dv2(M1[2 * h - 2 * k]);
+        m2a[c] = from_dv2(M2[2 * k]);
+        m2b[c] = from_dv2(M2[2 * h - 2 * k]);
+        cc[c] = wm(2 * k);
       }
     }
-    __syncthreads();
-    rl_fft<LH>(X, ptw);
-    // even part of the outputs 2p, 2p + 1 parked in this workgroup's scratch (same thread later)
+#pragma unroll
+    for (int c = 0; c < CK; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NKE && k <= h / 2)) continue;
+      const int kr = (h - k) & (h - 1);
+      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+      double2 gk, gr;
+      rl_even_pair(vk, vr, m1a[c], m1b[c], cc[c], gk, gr);
+      rl_even_pair(vk, vr, m2a[c], m2b[c], cc[c], g2k[i0 + c], g2r[i0 + c]);
+      X[lpad(k)] = gk;
+      if (k != 0 && k != h / 2) X[lpad(kr)] = gr;
+    }
+  }
+  __syncthreads();
+  // the even part of outputs 2p, 2p + 1 of each product waits in scratch (same thread later)
+  auto park = [&](gmem<double> *dst) {
+    t = opaque_tid();
+#pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int p = t + RL_THREADS * i;
-      if (p >= h || 2 * p >= len) continue;
+      if (!in_pos(i) || 2 * p >= len) continue;
       const double2 g = X[lpad(p)];
-      tes[2 * p] = g.x;
-      if (2 * p + 1 < len) tes[2 * p + 1] = -g.y;
+      dst[2 * p] = g.x;
+      if (2 * p + 1 < len) dst[2 * p + 1] = -g.y;
     }
     __syncthreads();
-    // ---- odd frequencies
-    for (int i0 = 0; i0 < NI; i0 += RL_CH) {
-      double rv[RL_CH][2];
-      double2 wp[RL_CH];
-      load_r(i0, rv);
+  };
+  rl_fft<LH>(X, ptw);
+  park(tes);
+  second_to_lds(std::false_type{});
+  rl_fft<LH>(X, ptw);
+  park(tes2);
+
+  // ---- odd frequencies
+  stage(true);
+  rl_fft<LH>(X, ptw);
+  t = opaque_tid();
+  const double2 om = wm(1);
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int p = t + RL_THREADS * (i0 + c);
-        if (i0 + c < NI && p < h) wp[c] = wm(2 * p);
-      }
+  for (int i0 = 0; i0 < NKO; i0 += CK) {
+    double2 m1a[CK], m1b[CK], m2a[CK], m2b[CK], dv[CK], cc[CK];
 #pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int p = t + RL_THREADS * (i0 + c);
-        if (i0 + c < NI && p < h) X[lpad(p)] = cmul(make_double2(rv[c][0], rv[c][1]), wp[c]);
-      }
-    }
-    __syncthreads();
-    rl_fft<LH>(X, ptw);
-    const double2 om = wm(1);
-    for (int i0 = 0; i0 < NKO; i0 += RL_CH) {
-      double2 ma[RL_CH], mb[RL_CH], dv[RL_CH], cc[RL_CH];
-#pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int k = t + RL_THREADS * (i0 + c);
-        if (i0 + c < NKO && k < h / 2) {
-          ma[c] = M[2 * k + 1];
-          mb[c] = M[2 * k + 2 * h + 1];
-          dv[c] = wm(2 * k + 1);
-          cc[c] = wm(2 * k);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < RL_CH; ++c) {
-        const int k = t + RL_THREADS * (i0 + c);
-        if (!(i0 + c < NKO && k < h / 2)) continue;
-        const int kr = h - 1 - k;
-        double2 gk, gr;
-        rl_odd_pair(X[lpad(k)], X[lpad(kr)], ma[c], mb[c], dv[c], cc[c], om, gk, gr);
-        X[lpad(k)] = gk;
-        X[lpad(kr)] = gr;
+    for (int c = 0; c < CK; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (i0 + c < NKO && k < h / 2) {
+        m1a[c] = from_dv2(M1[2 * k + 1]);
+        m1b[c] = from_dv2(M1[2 * k + 2 * h + 1]);
+        m2a[c] = from_dv2(M2[2 * k + 1]);
+        m2b[c] = from_dv2(M2[2 * k + 2 * h + 1]);
+        dv[c] = wm(2 * k + 1);
+        cc[c] = wm(2 * k);
       }
     }
-    __syncthreads();
-    rl_fft<LH>(X, ptw);
+#pragma unroll
+    for (int c = 0; c < CK; ++c) {
+      const int k = t + RL_THREADS * (i0 + c);
+      if (!(i0 + c < NKO && k < h / 2)) continue;
+      const int kr = h - 1 - k;
+      const double2 vk = X[lpad(k)], vr = X[lpad(kr)];
+      double2 gk, gr;
+      rl_odd_pair(vk, vr, m1a[c], m1b[c], dv[c], cc[c], om, gk, gr);
+      rl_odd_pair(vk, vr, m2a[c], m2b[c], dv[c], cc[c], om, g2k[i0 + c], g2r[i0 + c]);
+      X[lpad(k)] = gk;
+      X[lpad(kr)] = gr;
+    }
+  }
+  __syncthreads();
+  // outputs (tE + tO) / m of one product, squared and summed
+  auto sumsq = [&](const gmem<double> *src) {
+    t = opaque_tid();
+    double ss = 0.0;
+#pragma unroll
     for (int i = 0; i < NI; ++i) {
       const int p = t + RL_THREADS * i;
-      if (p >= h || 2 * p >= len) continue;
+      if (!in_pos(i) || 2 * p >= len) continue;
       const double2 gz = conj2(cmul(wm(2 * p), X[lpad(p)]));
-      const double c0 = (tes[2 * p] + gz.x) * inv_m;
+      const double c0 = (src[2 * p] + gz.x) * inv_m;
       ss += c0 * c0;
       if (2 * p + 1 < len) {
-        const double c1 = (tes[2 * p + 1] + gz.y) * inv_m;
+        const double c1 = (src[2 * p + 1] + gz.y) * inv_m;
         ss += c1 * c1;
       }
     }
     __syncthreads();
-  }
-  return ss;
+    return ss;
+  };
+  rl_fft<LH>(X, ptw);
+  const double s1 = sumsq(tes);
+  second_to_lds(std::true_type{});
+  rl_fft<LH>(X, ptw);
+  const double s2 = sumsq(tes2);
+  return s1 - s2;
 }
 
 // gs_sumsq for transforms split in P = 2 halves (m = 8 hh) or P = 4 quarters (m = 16 hq,
 // with the workgroup's scratch S), through the drivers of the refinement.
 template <int LH, int P>
 __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd, int64_t b,
-                                              const double2 *__restrict__ M, double2 *X,
-                                              double2 *S, double *__restrict__ tes) {
+                                              const gmem<const dv2> *__restrict__ M_, double2 *X,
+                                              gmem<dv2> *S_, gmem<double> *__restrict__ tes_) {
+  const gmem<const dv2> *__restrict__ M = uni(M_);
+  gmem<dv2> *S = uni(S_);
+  gmem<double> *__restrict__ tes = uni(tes_);
   static_assert(P == 2 || P == 4, "halves or quarters");
   constexpr int h = 1 << LH;
   constexpr int NI = h / P / RL_THREADS;
   static_assert(NI % RL_CH == 0, "whole chunks");
   int t = opaque_tid();
-  const double *__restrict__ hrow = gs_template_row(it, b) + sd.offset;
-  const double *__restrict__ dd = it.d + sd.offset;
-  const double2 *__restrict__ tw = (const double2 *)sd.tw;
-  const double2 *__restrict__ ptw = (const double2 *)sd.ptw;
-  const int len = (int)sd.length;
+  const gmem<const double> *__restrict__ hrow = gpu(gs_template_row(it, b) + sd.offset);
+  const gmem<const double> *__restrict__ dd = gpu(it.d + sd.offset);
+  const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);
+  const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);
+  const int len = uni((int)sd.length);
   const double inv_m = 1.0 / (double)(4 * h);
   auto wm = [&](int r) {
-    const double2 v = tw[r];
+    const dv2 v = tw[r];
     return make_double2(v.x, -v.y);
   };
   auto stage = [&](int s, bool odd) {
@@ -2276,7 +2415,7 @@ __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd,
     }
     __syncthreads();
   };
-  auto mult = [&](int r) { return M[r]; };
+  auto mult = [&](int r) { return from_dv2(M[r]); };
   double ss = 0.0;
   // even part parked in this workgroup's scratch (the same thread reads it back)
   auto emit = [&](int s, bool odd) {
@@ -2308,10 +2447,9 @@ __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd,
 
 template <int LH>
 __device__ __forceinline__ void gs_segment(const GsItem &it, const GsSeg &sd, int64_t b, double2 *X,
-                                           double *__restrict__ tes, double &qacc) {
-  const double s1 = gs_sumsq<LH>(it, sd, b, (const double2 *)sd.M1, X, tes);
-  const double s2 = gs_sumsq<LH>(it, sd, b, (const double2 *)sd.M2, X, tes);
-  qacc += (s1 - s2) * sd.inv_x0;
+                                           gmem<double> *__restrict__ tes, double &qacc) {
+  qacc += gs_pair<LH>(it, sd, b, gp((const dv2 *)sd.M1), gp((const dv2 *)sd.M2), X, tes) *
+          sd.inv_x0;
 }
 
 // Per-workgroup scratch of `stride` doubles: the parked even part, then (qoff >= 0) the
@@ -2323,8 +2461,8 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
   extern __shared__ double2 rl_smem[];
   double2 *X = rl_smem;
   double *red = (double *)(rl_smem + RL_XN);
-  double *tes = scratch + (int64_t)blockIdx.x * stride;
-  double2 *S = qoff >= 0 ? (double2 *)(tes + qoff) : nullptr;
+  gmem<double> *tes = gpu(scratch + (int64_t)blockIdx.x * stride);
+  gmem<dv2> *S = qoff >= 0 ? (gmem<dv2> *)(tes + qoff) : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
     const GsItem &it = items[wk.x];
@@ -2341,9 +2479,9 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
 #undef TDA_GS
         case RL_LHMAX + 1: {
           const double s1 =
-              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, (const double2 *)sd.M1, X, nullptr, tes);
+              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, gp((const dv2 *)sd.M1), X, nullptr, tes);
           const double s2 =
-              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, (const double2 *)sd.M2, X, nullptr, tes);
+              gs_sumsq_split<RL_LHMAX + 1, 2>(it, sd, b, gp((const dv2 *)sd.M2), X, nullptr, tes);
           qp += (s1 - s2) * sd.inv_x0;
           break;
         }
@@ -2353,17 +2491,18 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
             break;
           }
           const double s1 =
-              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, (const double2 *)sd.M1, X, S, tes);
+              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, gp((const dv2 *)sd.M1), X, S, tes);
           const double s2 =
-              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, (const double2 *)sd.M2, X, S, tes);
+              gs_sumsq_split<RL_LHMAX + 2, 4>(it, sd, b, gp((const dv2 *)sd.M2), X, S, tes);
           qp += (s1 - s2) * sd.inv_x0;
           break;
         }
         default: bad = true;
       }
     }
-    const double q = block_sum(bad ? __builtin_nan("") : qp, red);
-    if (threadIdx.x == 0) it.out[b] = -0.5 * q + it.cterm;
+    double q[1] = {bad ? __builtin_nan("") : qp};
+    block_sum0(q, red);
+    if (threadIdx.x == 0) it.out[b] = -0.5 * q[0] + it.cterm;
   }
 }
 

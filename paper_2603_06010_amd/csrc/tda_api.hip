@@ -698,9 +698,9 @@ static tda_status build_gs(tda_ctx *h) {
 
 constexpr int32_t kGsWG = 1024;  // persistent Gohberg-Semencul workgroups (one per CU runs at once)
 
-// Per-workgroup Gohberg-Semencul scratch: the parked even part (max_len doubles, rounded
-// to an even count) and, when a segment's transforms split in quarters, their quarters;
-// fewer workgroups then.
+// Per-workgroup Gohberg-Semencul scratch: the parked even parts of the two products (max_len
+// doubles each, rounded to an even count) and, when a segment's transforms split in
+// quarters, their quarters; fewer workgroups then.
 struct GsScratch {
   int32_t n_wg;
   int64_t stride, qoff;
@@ -711,8 +711,8 @@ static GsScratch gs_scratch_plan(int64_t n_work, int64_t max_len, int64_t max_m)
   GsScratch g;
   g.n_wg = (int32_t)std::min<int64_t>(n_work, quad ? RL_QUAD_WG : kGsWG);
   const int64_t tes = (max_len + 1) & ~(int64_t)1;
-  g.qoff = quad ? tes : -1;
-  g.stride = tes + (quad ? 2 * RL_QUAD_SCRATCH : 0);
+  g.qoff = quad ? 2 * tes : -1;
+  g.stride = 2 * tes + (quad ? 2 * RL_QUAD_SCRATCH : 0);
   g.bytes = (size_t)g.n_wg * g.stride * sizeof(double);
   return g;
 }
