@@ -54,6 +54,28 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
+PROFILE_UTIL = os.path.join(ROOT, "profiles", "utilisation_c2.md")
+
+
+def profiled_clock(name):
+    """(sustained shader clock in GHz, matrix-core busy fraction at that clock) of timing
+    record `name` from the committed counter summary, or None (other kernel sources)."""
+    try:
+        with open(PROFILE_UTIL) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    sha = kernel_sources_sha256()
+    for line in lines:
+        parts = line.strip().split()
+        if len(parts) >= 5 and parts[0] == "clock" and parts[1] == name:
+            kv = dict(p.split("=", 1) for p in parts[2:] if "=" in p)
+            if kv.get("sources_sha256") != sha:
+                return None
+            return float(kv["ghz"]), float(kv["mfma_util"])
+    return None
+
+
 def profiled_traffic(name):
     """Bytes per launch (fetched + written) of timing record `name`, or None."""
     try:
@@ -482,6 +504,14 @@ def main():
                 "avg_ms": tot / cnt, "issued_frac": 3 * achieved / PEAK_BF16,
                 "step_achieved": step_rate / 1e12, "step_frac": step_rate / PEAK_BF16,
                 "alg_flops_per_step": alg_flops}
+    clk = profiled_clock(dom)
+    if clk is not None:
+        # under sustained BF16 matrix load the chip runs below the 2.4 GHz the published peak
+        # assumes; the counter run gives the clock this kernel held and its matrix-core busy
+        # fraction at that clock (profiles/utilisation_c2.md)
+        roofline["sustained_clock_ghz"] = clk[0]
+        roofline["frac_at_sustained_clock"] = achieved / (PEAK_BF16 * clk[0] / 2.4)
+        roofline["mfma_busy_at_sustained_clock"] = clk[1]
     dom_f = "trsm_f64"
     cf, tf = kt_f[dom_f]
     ach_f = alg_flops / (tf / cf * 1e-3)
