@@ -237,9 +237,9 @@ def main():
     ap.add_argument("--core-only", action="store_true",
                     help="c2: only the batched mixed and FP64 evaluations (for profiling runs); "
                          "every other leg is null (same as --legs none)")
-    ap.add_argument("--legs", default="gs,acf,cdo,terms,wres,stress,c3,c5",
+    ap.add_argument("--legs", default="gs,acf,cdo,terms,wres,stress,c3,c4,c5",
                     help="c2: the legs run beside the mixed and FP64 evaluations, comma-"
-                         "separated from gs, acf, cdo, terms, wres, stress, c3, c5 (or none)")
+                         "separated from gs, acf, cdo, terms, wres, stress, c3, c4, c5 (or none)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
                     help="c2 (default): two detectors x N=16384, 4096 templates per launch; "
                          "c3: one detector x N=32768 with 3 gaps, 8192 templates; "
@@ -365,7 +365,7 @@ def main():
         for h in hg:
             h.close()
 
-    acf_line = cdo = snr_terms = wres = stress = c3_line = c5_line = None
+    acf_line = cdo = snr_terms = wres = stress = c3_line = c4_line = c5_line = None
     if args.leg("acf"):
         # autocovariance estimation from a 256 s stretch of noise at 4096 Hz (2^20 samples):
         # Welch with 8 s segments and the direct estimator, both to the 16384 lags of the
@@ -475,10 +475,27 @@ def main():
         stress = stress_leg(args, tda, torch, synth, dev, log)
     if args.leg("c3"):
         c3_line = run_c3(args, tda, torch, synth, dev, log, steps=5, fsteps=2)
+    def guarded(name, fn):
+        # a leg that fails (say, out of device memory) is reported in the line, not fatal
+        try:
+            return fn()
+        except Exception as e:  # noqa: BLE001
+            log(f"{name} failed: {type(e).__name__}: {e}")
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            return {"error": f"{type(e).__name__}: {e}"}
+
     if args.leg("c5"):
         # a short served leg: 2 s of requests at 5 % of the offered load (below saturation,
-        # where latency is the server's own) and at the full, overloaded rate
-        c5_line = run_c5(args, tda, torch, synth, dev, log, 2.0, [0.05, 1.0], ("mixed",))
+        # where latency is the server's own) and at the full, overloaded rate.  It runs
+        # before the ragged batch, whose many handles leave the device memory fragmented
+        # enough to cut the server's batches.
+        c5_line = guarded("c5", lambda: run_c5(args, tda, torch, synth, dev, log, 2.0,
+                                               [0.05, 1.0], ("mixed",)))
+    if args.leg("c4"):
+        # the 64-instance ragged batch (one batched evaluation per step, compact handles)
+        c4_line = guarded("c4", lambda: run_c4(args, tda, torch, synth, dev, log, 4, 1))
+        c4_line.pop("wall", None)
 
     evals_m = inst.B * args.steps / wall_m
     evals_f = inst.B * fsteps / wall_f
@@ -551,6 +568,7 @@ def main():
         "whitened_residual": wres,
         "accuracy_stress": stress,
         "c3": c3_line,
+        "c4": c4_line,
         "c5_served": c5_line,
         "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(d_mf.max()),
                      "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(d_mf, 99),
@@ -766,11 +784,12 @@ def bench_c3(args, tda, torch, synth, dev, log):
     print(json.dumps(line), flush=True)
 
 
-def bench_c4(args, tda, torch, synth, dev, log):
+def run_c4(args, tda, torch, synth, dev, log, steps_m, warmup):
     """64 ragged instances (N ~ U{2048..32768}, 0-2 gaps per detector, 1-2 detectors,
     256 templates each) evaluated in one batched launch sequence per step.  The mixed pass
     keeps only the BF16 operators of its handles (compact); the FP64 pass builds FP64
-    handles afterwards (both sets at once would exceed HBM)."""
+    handles afterwards (both sets at once would exceed HBM).  Returns the key set of the
+    line (value, config, fp64, accuracy, kernels, setup)."""
     t0 = time.perf_counter()
     w = synth.c4_workload()
     log(f"c4 inputs in {time.perf_counter() - t0:.1f} s")
@@ -794,13 +813,13 @@ def bench_c4(args, tda, torch, synth, dev, log):
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         log(f"c4 {p}: setup {setup:.1f} s, {len(items)} detector items, {n_eval} evals per step")
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             tda.loglik_multi(items, precision=p)
         torch.cuda.synchronize()
         tda.timing_read(reset=True)
         tda.timing_enable(True)
         t = time.perf_counter()
-        steps = args.steps if p == "mixed" else max(2, args.steps // 4)
+        steps = steps_m if p == "mixed" else max(2, steps_m // 4)
         for _ in range(steps):
             tda.loglik_multi(items, precision=p)
         torch.cuda.synchronize()
@@ -814,18 +833,31 @@ def bench_c4(args, tda, torch, synth, dev, log):
         torch.cuda.synchronize()
         log(f"c4 {p}: {wall / steps * 1e3:.2f} ms/step")
     wall, steps, kt, rm, setup, n_items = res["mixed"]
-    line = _base_line(args, n_eval * steps / wall, "evals/s", wall, steps,
-                      {"workload": "64 ragged instances, N~U{2048..32768}, 0-2 gaps, 1-2 detectors, "
-                                   "256 templates each, one batched evaluation per step",
-                       "instances": len(w.instances), "detector_items": n_items},
-                      "bf16x3+f64")
     fw, fs, fkt, rf, fsetup, _ = res["fp64"]
-    line["fp64"] = {"value": n_eval * fs / fw, "unit": "evals/s", "ms_per_step": fw / fs * 1e3,
-                    "setup_s": fsetup}
-    line["speedup_mixed_vs_fp64"] = line["value"] / line["fp64"]["value"]
-    line["accuracy"] = {"max_abs_dlogL_mixed_vs_fp64_gpu": float(np.abs(rm - rf).max())}
-    line["kernels_ms"] = {k: v[1] / v[0] for k, v in kt.items()}
-    line["setup_s"] = setup
+    c4 = {"value": n_eval * steps / wall, "unit": "evals/s", "ms_per_step": wall / steps * 1e3,
+          "steps": steps, "wall": wall,
+          "config": {"workload": "64 ragged instances, N~U{2048..32768}, 0-2 gaps, 1-2 detectors, "
+                                 "256 templates each, one batched evaluation per step",
+                     "instances": len(w.instances), "detector_items": n_items},
+          "fp64": {"value": n_eval * fs / fw, "unit": "evals/s", "ms_per_step": fw / fs * 1e3,
+                   "setup_s": fsetup},
+          "accuracy": {"max_abs_dlogL_mixed_vs_fp64_gpu": float(np.abs(rm - rf).max()),
+                       "p99_abs_dlogL_mixed_vs_fp64_gpu": _pct(np.abs(rm - rf), 99),
+                       "evals_compared": int(rm.size)},
+          "kernels_ms": {k: v[1] / v[0] for k, v in kt.items()},
+          "setup_s": setup}
+    c4["speedup_mixed_vs_fp64"] = c4["value"] / c4["fp64"]["value"]
+    # the handles took their memory through torch's caching allocator; give it back
+    torch.cuda.empty_cache()
+    return c4
+
+
+def bench_c4(args, tda, torch, synth, dev, log):
+    """The ragged batch alone (see run_c4)."""
+    c4 = run_c4(args, tda, torch, synth, dev, log, args.steps, args.warmup)
+    line = _base_line(args, c4["value"], "evals/s", c4.pop("wall"), c4["steps"], c4.pop("config"),
+                      "bf16x3+f64")
+    line.update({k: v for k, v in c4.items() if k not in ("value", "unit", "steps", "ms_per_step")})
     print(json.dumps(line), flush=True)
 
 
@@ -864,6 +896,10 @@ def run_c5(args, tda, torch, synth, dev, log, duration, fracs, precisions):
     t0 = time.perf_counter()
     w = synth.c5_workload(duration_s=duration, rate_hz=args.rate)
     log(f"c5 inputs in {time.perf_counter() - t0:.1f} s")
+    # the batched evaluations before this leg keep workspaces sized for their largest
+    # batch; the server's slots need that memory for their own
+    tda.release_workspaces()
+    torch.cuda.empty_cache()
     # the server runs the default product variant: tuning trials for every coalesced
     # batch shape would otherwise land inside the latency measurements
     saved = os.environ.get("TDA_AUTOTUNE")
@@ -887,29 +923,11 @@ def run_c5(args, tda, torch, synth, dev, log, duration, fracs, precisions):
         torch.cuda.empty_cache()
         setup = time.perf_counter() - t0
         log(f"c5 {prec}: setup {setup:.1f} s")
-        # untimed warm-up (code loading, first allocations)
-        _serve_trace(srv, synth.c5_requests(args.rate * min(fracs), 0.5, trace=99), Hs, dev, torch)
-        if prec == "mixed":
-            for i, f in enumerate(fracs):
-                req = w.requests if f == 1.0 else synth.c5_requests(args.rate * f, duration,
-                                                                     trace=i + 1)
-                wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
-                point = {"offered_evals_per_s": tmpl / duration,
-                         "achieved_evals_per_s": tmpl / wall, "requests": len(req["t"]),
-                         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-                         "mean_templates_per_launch": st["mean_templates_per_launch"]}
-                # the server kept up when the trace drained within 10 % of its length
-                point["below_saturation"] = bool(wall <= 1.1 * duration)
-                sweep.append(point)
-                log(f"c5 mixed at {f:g} x {args.rate:g} req/s: {point}")
-                if f == max(fracs):
-                    res[prec] = (wall, st, setup, len(req["t"]), tmpl)
-        else:
-            req = {k: v[::20] for k, v in w.requests.items()}
-            wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
-            res[prec] = (wall, st, setup, len(req["t"]), tmpl)
-            log(f"c5 fp64: {st}")
-        srv.close()
+        try:
+            _c5_serve(args, srv, w, prec, fracs, duration, Hs, dev, torch, synth, log, sweep, res,
+                      setup)
+        finally:
+            srv.close()
         del keep, Hs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
@@ -917,6 +935,36 @@ def run_c5(args, tda, torch, synth, dev, log, duration, fracs, precisions):
         os.environ.pop("TDA_AUTOTUNE", None)
     else:
         os.environ["TDA_AUTOTUNE"] = saved
+    return _c5_line(args, res, sweep, duration, fracs)
+
+
+def _c5_serve(args, srv, w, prec, fracs, duration, Hs, dev, torch, synth, log, sweep, res, setup):
+    """The timed traces of one server (run_c5)."""
+    # untimed warm-up (code loading, first allocations)
+    _serve_trace(srv, synth.c5_requests(args.rate * min(fracs), 0.5, trace=99), Hs, dev, torch)
+    if prec == "mixed":
+        for i, f in enumerate(fracs):
+            req = w.requests if f == 1.0 else synth.c5_requests(args.rate * f, duration,
+                                                                 trace=i + 1)
+            wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
+            point = {"offered_evals_per_s": tmpl / duration,
+                     "achieved_evals_per_s": tmpl / wall, "requests": len(req["t"]),
+                     "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                     "mean_templates_per_launch": st["mean_templates_per_launch"]}
+            # the server kept up when the trace drained within 10 % of its length
+            point["below_saturation"] = bool(wall <= 1.1 * duration)
+            sweep.append(point)
+            log(f"c5 mixed at {f:g} x {args.rate:g} req/s: {point}")
+            if f == max(fracs):
+                res[prec] = (wall, st, setup, len(req["t"]), tmpl)
+    else:
+        req = {k: v[::20] for k, v in w.requests.items()}
+        wall, st, tmpl = _serve_trace(srv, req, Hs, dev, torch)
+        res[prec] = (wall, st, setup, len(req["t"]), tmpl)
+        log(f"c5 fp64: {st}")
+
+
+def _c5_line(args, res, sweep, duration, fracs):
     wall, st, setup, n, tmpl = res["mixed"]
     top = max(fracs)
     line = {"value": tmpl / wall, "unit": "evals/s",

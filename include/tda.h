@@ -354,6 +354,20 @@ tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, int32_t prec
                             void *hip_stream);
 
 /*
+ * tda_release_workspaces -- tda_loglik_multi keeps its device workspaces (sized for
+ * the largest batch seen so far) between calls on a device, so a steady stream of
+ * batches allocates nothing.  This call frees them after waiting for the device to
+ * finish; the next batched call allocates again.  For callers that move from one
+ * workload to another and want the memory back (a server, say, after a large
+ * batched evaluation).  Handles, plans and servers keep their own workspaces.
+ * device: a device index, or -1 for the current device.  Errors: TDA_EINVAL for a
+ * bad index, TDA_EHIP if the synchronization fails.  Must not overlap a
+ * tda_loglik_multi call on the same device (it takes the same lock, so a
+ * concurrent call waits).
+ */
+tda_status tda_release_workspaces(int32_t device);
+
+/*
  * Plans: a batched evaluation frozen once (items, precision, workspace, kernel
  * variants) and then replayed.  tda_plan_create copies the item list (the
  * pointers inside must stay valid for the plan's lifetime), runs the evaluation

@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["TdaError", "Handle", "loglik_multi", "acf_estimate", "load_library", "LIB_PATH",
+__all__ = ["TdaError", "Handle", "loglik_multi", "release_workspaces", "acf_estimate",
+           "load_library", "LIB_PATH",
            "timing_enable", "timing_read", "Server", "Plan",
            "PREC_FP64", "PREC_MIXED", "EXPORTED_SYMBOLS"]
 
@@ -22,7 +23,8 @@ PREC_FP64, PREC_MIXED, PREC_GS, PREC_CDO = 0, 1, 2, 3
 EXPORTED_SYMBOLS = [
     "tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
     "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
-    "tda_loglik_multi", "tda_info", "tda_destroy", "tda_status_str", "tda_last_error",
+    "tda_loglik_multi", "tda_release_workspaces", "tda_info", "tda_destroy", "tda_status_str",
+    "tda_last_error",
     "tda_loglik_fp64_noalloc",
     "tda_timing_enable", "tda_timing_read", "tda_plan_create", "tda_plan_execute",
     "tda_plan_destroy",
@@ -128,6 +130,7 @@ def load_library(path: str = LIB_PATH):
     L.tda_whitened_residual.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
     L.tda_acf_estimate.argtypes = [vp, i64, i64, i32, i64, vp, vp]
     L.tda_loglik_multi.argtypes = [vp, i64, i32, vp]
+    L.tda_release_workspaces.argtypes = [i32]
     L.tda_info.argtypes = [vp, ctypes.POINTER(_Info)]
     L.tda_destroy.argtypes = [vp]
     L.tda_status_str.argtypes = [ctypes.c_int]
@@ -139,7 +142,7 @@ def load_library(path: str = LIB_PATH):
     for f in ("tda_cov_build", "tda_factor", "tda_set_data", "tda_loglik", "tda_loglik_ex",
               "tda_loglik_terms", "tda_snr", "tda_whitened_residual", "tda_acf_estimate",
               "tda_loglik_multi", "tda_info", "tda_destroy", "tda_timing_enable",
-              "tda_timing_read", "tda_loglik_fp64_noalloc"):
+              "tda_timing_read", "tda_loglik_fp64_noalloc", "tda_release_workspaces"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -383,6 +386,12 @@ def loglik_multi(items, precision="fp64", stream=None):
         arr[k] = _Work(h.ptr, _ptr(d), _ptr(H), H.shape[0], H.stride(0), _ptr(out))
     _call(L.tda_loglik_multi, ctypes.cast(arr, ctypes.c_void_p), len(items),
           _precision(precision), _stream(stream))
+
+
+def release_workspaces(device=None):
+    """Free the workspaces batched evaluations keep between calls (tda_release_workspaces)."""
+    L = load_library()
+    _check(L.tda_release_workspaces(-1 if device is None else int(device)))
 
 
 class _ServerOptions(ctypes.Structure):

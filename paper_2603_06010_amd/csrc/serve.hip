@@ -269,6 +269,17 @@ void tda_server::scheduler() {
     const std::vector<Dataset> dsv = ds;
     lk.unlock();
     tda_status st = launch(sl, take, dsv);
+    // a batch whose workspace does not fit in the free device memory is split: the later
+    // half of its requests goes back to the front of the queue (arrival order kept) and the
+    // first half is launched, down to a single request
+    while (st == TDA_ENOMEM && take.size() > 1) {
+      const size_t half = take.size() / 2;
+      lk.lock();
+      for (size_t i = take.size(); i-- > half;) pending.push_front(take[i]);
+      lk.unlock();
+      take.resize(half);
+      st = launch(sl, take, dsv);
+    }
     lk.lock();
     if (st != TDA_OK) {
       error = st;

@@ -290,7 +290,10 @@ struct tda_ctx {
                        bytes, held, budget);
     if (has_user_alloc) {
       b.p = user_alloc.alloc(bytes, user_alloc.ctx);
-      if (!b.p) return fail_with(TDA_ENOMEM, "allocator returned NULL for %zu bytes", bytes);
+      if (!b.p) {
+        (void)hipGetLastError();  // a failed device allocation inside the allocator, as above
+        return fail_with(TDA_ENOMEM, "allocator returned NULL for %zu bytes", bytes);
+      }
       if ((uintptr_t)b.p & 255) {
         user_alloc.free(b.p, user_alloc.ctx);
         b.p = nullptr;
@@ -300,6 +303,9 @@ struct tda_ctx {
       hipError_t e = hipMalloc(&b.p, bytes);
       if (e != hipSuccess) {
         b.p = nullptr;
+        // the runtime also records the failure as the thread's last error; clear it, or the
+        // next kernel launch check would report it as its own
+        (void)hipGetLastError();
         return fail_with(TDA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
       }
     }
@@ -1584,6 +1590,20 @@ extern "C" tda_status tda_loglik_multi(const tda_work *items, int64_t n_items, i
   std::lock_guard<std::mutex> lk(mc->mu);
   DeviceGuard guard(items[0].h->device);
   return multi_impl(mc, items, nullptr, n_items, precision, (hipStream_t)hip_stream, true);
+}
+
+extern "C" tda_status tda_release_workspaces(int32_t device) {
+  int dev = device, n_dev = 0;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail_with(TDA_EHIP, "hipGetDevice failed");
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || dev >= n_dev)
+    return fail_with(TDA_EINVAL, "device %d out of range", dev);
+  MultiCtx *mc = multi_ctx(dev);
+  std::lock_guard<std::mutex> lk(mc->mu);
+  DeviceGuard guard(dev);
+  // earlier batched calls may still be running on their streams
+  HIP_TRY(hipDeviceSynchronize());
+  mc->pool.release_all();
+  return TDA_OK;
 }
 
 namespace {

@@ -385,6 +385,36 @@ def test_multi_matches_single(tda):
         np.testing.assert_allclose(out.cpu().numpy(), single.cpu().numpy(), rtol=0, atol=1e-9)
 
 
+def test_release_workspaces(tda):
+    """tda_release_workspaces gives the batched evaluations' device memory back (the
+    device's free memory grows by at least the mixed workspace of the batch), and the
+    next batched call allocates again and returns the same bits."""
+    from gpu_util import to_dev
+    import torch
+    inst = synth.random_rhs_case(78, 4096, 2, 1, 512)
+    hs = [tda.Handle(inst.acf, inst.N, m, precision="mixed").factor() for m in inst.masks]
+    ds = [to_dev(x) for x in inst.d]
+    H = to_dev(inst.H)
+    items = lambda o: [(hs[0], ds[0], H, o), (hs[1], ds[1], H, o)]
+    first = torch.empty(512, dtype=torch.float64, device="cuda")
+    tda.loglik_multi(items(first), precision="mixed")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    tda.release_workspaces()
+    free1 = torch.cuda.mem_get_info()[0]
+    # y0 (4 B) and e (8 B) per template and padded sample, for each of the two items
+    assert free1 - free0 >= 2 * 512 * 4096 * 12
+    again = torch.empty(512, dtype=torch.float64, device="cuda")
+    tda.loglik_multi(items(again), precision="mixed")
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(again.cpu().numpy(), first.cpu().numpy())
+    with pytest.raises(tda.TdaError) as e:
+        tda.release_workspaces(1 << 20)
+    assert e.value.name == "TDA_EINVAL"
+    for h in hs:
+        h.close()
+
+
 def test_multi_shared_template_split(tda):
     """Detectors with the same templates and the same retained rows share one template
     split in a batched call; a third item with other rows (and a fourth with other
