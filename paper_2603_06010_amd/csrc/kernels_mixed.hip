@@ -2371,8 +2371,11 @@ __device__ __noinline__ double gs_pair(const GsItem &it, const GsSeg &sd, int64_
   return s1 - s2;
 }
 
-// gs_sumsq for transforms split in P = 2 halves (m = 8 hh) or P = 4 quarters (m = 16 hq,
-// with the workgroup's scratch S), through the drivers of the refinement.
+// One correlation's sum over this thread's outputs j < length of (L(v)^T r)_j^2
+// (multiplier M), for segments whose transforms split in P = 2 halves (m = 8 hh) or P = 4
+// quarters (m = 16 hq, with the workgroup's scratch S), through the drivers of the
+// refinement.  The two correlations run one after the other here: the split drivers
+// already hold half of each transform in registers.
 template <int LH, int P>
 __device__ __noinline__ double gs_sumsq_split(const GsItem &it, const GsSeg &sd, int64_t b,
                                               const gmem<const dv2> *__restrict__ M_, double2 *X,
