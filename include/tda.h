@@ -414,7 +414,12 @@ tda_status tda_info(tda_handle h, tda_info_t *info);
  * when a request alone would exceed a slot's staging memory
  * (staging_bytes / n_slots); datasets are admitted by tda_server_add_dataset
  * only while the sum of their handles' device memory stays within
- * dataset_budget_bytes (0 = no limit), else TDA_ENOMEM.
+ * dataset_budget_bytes (0 = no limit), else TDA_ENOMEM.  The scheduler also stops
+ * coalescing where the launch's evaluation workspace would exceed the device memory
+ * free at that moment plus what the slot's workspace already holds, less 1 GiB
+ * (the first request of a launch is always taken); a launch that still fails to
+ * allocate is halved, the later half going back to the front of the queue, down to
+ * a single request, which then fails with the allocation error.
  * Latency of a request = completion observed by the server minus submit time.
  */
 typedef struct tda_server *tda_server_t;

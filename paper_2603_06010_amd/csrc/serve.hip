@@ -44,6 +44,10 @@ struct Request {
   double t_submit;
 };
 
+// device memory left free when a launch's workspace is sized (descriptor rings, the
+// runtime, other small allocations)
+constexpr size_t kMemMargin = (size_t)1 << 30;
+
 struct Dataset {
   tda_handle h;
   const double *d;
@@ -243,21 +247,38 @@ void tda_server::scheduler() {
       }
     if (free_slot < 0) continue;
     // coalesce: per dataset, arrival order, up to max_batch templates (a request is
-    // never split; an oversized request goes alone); stop at the slot's staging cap
+    // never split; an oversized request goes alone); stop at the slot's staging cap and at
+    // the device memory the launch's workspace may take: what is free now plus what this
+    // slot's workspace already holds (reused or replaced), less a margin
     std::vector<Request> take;
     std::vector<int64_t> per_ds(ds.size(), 0);
     size_t stage = 0;
+    size_t avail = SIZE_MAX, ws_items = 0, ws_fixed = 0;
+    {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+        const size_t have = free_b + multi_ctx_held(slots[free_slot].mc);
+        avail = have > kMemMargin ? have - kMemMargin : 0;
+      }
+      (void)hipGetLastError();
+    }
     std::deque<Request> keep;
     while (!pending.empty()) {
       Request r = pending.front();
       pending.pop_front();
       const int64_t cur = per_ds[r.ds];
       const size_t add = (size_t)r.B * (sizeof(void *) + sizeof(double));
+      const size_t w_old = item_ws_bytes(ds[r.ds].h, cur, opt.precision);
+      const size_t w_new = item_ws_bytes(ds[r.ds].h, cur + r.B, opt.precision);
+      const size_t fixed = std::max(ws_fixed, launch_ws_fixed_bytes(ds[r.ds].h, opt.precision));
       const bool fits_ds = cur == 0 || cur + r.B <= opt.max_batch;
       const bool fits_stage = take.empty() || stage + add <= slot_stage_bytes;
-      if (fits_ds && fits_stage) {
+      const bool fits_mem = take.empty() || ws_items - w_old + w_new + fixed <= avail;
+      if (fits_ds && fits_stage && fits_mem) {
         per_ds[r.ds] += r.B;
         stage += add;
+        ws_items += w_new - w_old;
+        ws_fixed = fixed;
         take.push_back(r);
       } else {
         keep.push_back(r);

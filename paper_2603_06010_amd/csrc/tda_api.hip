@@ -1561,6 +1561,17 @@ tda_status multi_eval(MultiCtx *mc, const tda_work *items, const double *const *
                       int64_t n_items, int32_t precision, hipStream_t s) {
   return multi_impl(mc, items, hrows, n_items, precision, s, false);
 }
+size_t item_ws_bytes(tda_handle h, int64_t B, int32_t precision) {
+  if (B <= 0) return 0;
+  if (precision == TDA_PREC_MIXED) return mix_ws_bytes(h, (B + MT - 1) / MT * MT);
+  if (precision == TDA_PREC_FP64)
+    return (size_t)((B + BC - 1) / BC) * (size_t)h->n_pad * BC * sizeof(double);
+  return 0;
+}
+size_t launch_ws_fixed_bytes(tda_handle h, int32_t precision) {
+  return precision == TDA_PREC_MIXED ? fft_ws_bytes(h->max_m) : 0;
+}
+size_t multi_ctx_held(MultiCtx *mc) { return mc ? mc->pool.held : 0; }
 int handle_device(tda_handle h) { return h->device; }
 int64_t handle_n(tda_handle h) { return h->N; }
 size_t handle_bytes(tda_handle h) { return h->held; }

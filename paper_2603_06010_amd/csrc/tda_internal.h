@@ -348,6 +348,14 @@ tda_status multi_eval(MultiCtx *mc, const tda_work *items, const double *const *
 int handle_device(tda_handle h);
 int64_t handle_n(tda_handle h);
 size_t handle_bytes(tda_handle h);
+// Device workspace a batched evaluation takes: per item of B templates (the template and
+// residual splits, y0 and e for the mixed path, the solve scratch for FP64), plus a part
+// shared by the launch (the FFT scratch of its longest circulant, the largest over items);
+// 0 where the precision keeps none worth counting.
+size_t item_ws_bytes(tda_handle h, int64_t B, int32_t precision);
+size_t launch_ws_fixed_bytes(tda_handle h, int32_t precision);
+// bytes a private batched-evaluation context holds now
+size_t multi_ctx_held(MultiCtx *mc);
 bool handle_ready(tda_handle h, int32_t precision);
 tda_status handle_set_data(tda_handle h, const double *d, hipStream_t s);
 tda_status set_error(tda_status st, const char *msg);
