@@ -78,6 +78,49 @@ __device__ __forceinline__ dv2 to_dv2(double2 v) {
   return r;
 }
 
+// ---------------------------------------------------------------- split fragment layout
+// The products read templates and residuals as BF16 hi/lo in the layout [Bp/32][tks][64][8]:
+// per tile of 32 templates and k-step of 16 padded rows, 64 lanes of 8 consecutive rows,
+// lane = template mod 32 for rows 0..7 of the step and + 32 for rows 8..15.
+__device__ __forceinline__ int64_t frag_col(int64_t b, int64_t tks) {
+  return ((b >> 5) * tks * 64 + (b & 31)) * 8;  // template b's row 0
+}
+__device__ __forceinline__ int64_t frag_row(int64_t r) {
+  return ((r >> 4) << 9) + (((r >> 3) & 1) << 8) + (r & 7);
+}
+
+// The refinement writes the residual e = h - C y0 of template b straight into that layout,
+// split (what the template split does for h), for the correction product.
+struct EsOut {
+  gmem<uint16_t> *hi, *lo;
+  __device__ __forceinline__ EsOut(uint16_t *es_hi, uint16_t *es_lo, int64_t tks, int64_t b) {
+    const int64_t o = frag_col(b, tks);
+    hi = gpu(es_hi + o);
+    lo = gpu(es_lo + o);
+  }
+  __device__ __forceinline__ void put(int32_t r, double v) const {
+    uint16_t h, l;
+    split2(v, h, l);
+    const int64_t o = frag_row(r);
+    hi[o] = h;
+    lo[o] = l;
+  }
+  // rows r[0], r[1] (-1: none); one 4-byte store per part when they are r, r + 1 with r even
+  __device__ __forceinline__ void pair(const int32_t (&r)[2], double v0, double v1) const {
+    if (r[0] >= 0 && r[1] == r[0] + 1 && !(r[0] & 1)) {
+      uint16_t h0, l0, h1, l1;
+      split2(v0, h0, l0);
+      split2(v1, h1, l1);
+      const int64_t o = frag_row(r[0]);
+      *(gmem<uint32_t> *)(hi + o) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      *(gmem<uint32_t> *)(lo + o) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    } else {
+      if (r[0] >= 0) put(r[0], v0);
+      if (r[1] >= 0) put(r[1], v1);
+    }
+  }
+};
+
 // ---------------------------------------------------------------- W64 access
 // W = L^-1 in FP64, compact column tiles of 32 columns: tile ct holds rows
 // [rb[ct], segment end) at w64[off[ct] + (r - rb[ct]) * 32 + (c % 32)].
@@ -343,37 +386,33 @@ hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *t
 
 // ---------------------------------------------------------------- template split
 // F(Hs): rows = templates (padded to Bp), K = padded sample rows; Hs[b][p] = h_b[idx[p]].
-// grid (chunks of the largest item, items); each item has (Bp/32) (n_pad/16) 64 chunks
-__global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
+// grid (chunks of the largest item, items); each item has (Bp/32) (n_pad/16) 64 chunks of
+// 8 rows of one template
+__global__ void k_split_h(const MixItem *__restrict__ items) {
   const MixItem &it = items[blockIdx.y];
   const int64_t nks = it.n_pad / 16;
   const int64_t chunks = (int64_t)(it.Bp / 32) * nks * 64;
   const int64_t chunk = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (chunk >= chunks || it.B == 0 || (!from_e && it.hs_shared)) return;
+  if (chunk >= chunks || it.B == 0 || it.hs_shared) return;
   const int lane = (int)(chunk & 63);
   const int64_t ks = (chunk >> 6) % nks;
   const int64_t tt = (chunk >> 6) / nks;
   const int64_t dst = ((tt * it.tks + ks) * 64 + lane) * 8;
   const int64_t b = 32 * tt + (lane & 31);
   const int64_t p0 = 16 * ks + 8 * (lane >> 5);
-  // the eight rows' values: e64 rows are contiguous (two 32-byte loads); template rows
-  // are gathered through idx (read as two 16-byte loads), all loads issued first
+  // the eight rows' samples, gathered through idx (read as two 16-byte loads); rows that
+  // are eight consecutive samples at a 16-byte boundary are read as four 16-byte loads
+  const int4 *ip = reinterpret_cast<const int4 *>(it.idx + p0);
+  const int4 i0 = ip[0], i1 = ip[1];
+  const int32_t pr[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+  const double *row = b < it.B ? template_row(it, b) : nullptr;
   double v[8];
-  if (from_e) {
-    if (b < it.B) {
-      const double4 *src = reinterpret_cast<const double4 *>(it.e64 + b * it.n_pad + p0);
-      const double4 u0 = src[0], u1 = src[1];
-      v[0] = u0.x; v[1] = u0.y; v[2] = u0.z; v[3] = u0.w;
-      v[4] = u1.x; v[5] = u1.y; v[6] = u1.z; v[7] = u1.w;
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = 0.0;
-    }
+  if (row && pr[0] >= 0 && pr[7] == pr[0] + 7 && !(((uintptr_t)(row + pr[0])) & 15)) {
+    const double2 *src = reinterpret_cast<const double2 *>(row + pr[0]);
+    const double2 u0 = src[0], u1 = src[1], u2 = src[2], u3 = src[3];
+    v[0] = u0.x; v[1] = u0.y; v[2] = u1.x; v[3] = u1.y;
+    v[4] = u2.x; v[5] = u2.y; v[6] = u3.x; v[7] = u3.y;
   } else {
-    const int4 *ip = reinterpret_cast<const int4 *>(it.idx + p0);
-    const int4 i0 = ip[0], i1 = ip[1];
-    const int32_t pr[8] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-    const double *row = b < it.B ? template_row(it, b) : nullptr;
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = (row && pr[e] >= 0) ? row[pr[e]] : 0.0;
   }
@@ -385,15 +424,15 @@ __global__ void k_split_h(const MixItem *__restrict__ items, int from_e) {
   vh.z = hi[4] | ((uint32_t)hi[5] << 16); vh.w = hi[6] | ((uint32_t)hi[7] << 16);
   vl.x = lo[0] | ((uint32_t)lo[1] << 16); vl.y = lo[2] | ((uint32_t)lo[3] << 16);
   vl.z = lo[4] | ((uint32_t)lo[5] << 16); vl.w = lo[6] | ((uint32_t)lo[7] << 16);
-  *reinterpret_cast<uint4 *>((from_e ? it.es_hi : it.hs_hi) + dst) = vh;
-  *reinterpret_cast<uint4 *>((from_e ? it.es_lo : it.hs_lo) + dst) = vl;
+  *reinterpret_cast<uint4 *>(it.hs_hi + dst) = vh;
+  *reinterpret_cast<uint4 *>(it.hs_lo + dst) = vl;
 }
 
-hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
+hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks,
                           hipStream_t s) {
   if (n_items <= 0 || max_chunks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_split_h, dim3((unsigned)((max_chunks + 255) / 256), (unsigned)n_items),
-                     dim3(256), 0, s, items, from_e);
+                     dim3(256), 0, s, items);
   return hipGetLastError();
 }
 
@@ -1037,8 +1076,8 @@ __device__ void refine_segment(const RefItem &it, const SegDev &sd, int64_t ba, 
   const float *yb = it.y0 + (two ? bb : ba) * it.n_pad;
   const double *ha = template_row(it, ba);
   const double *hb = template_row(it, two ? bb : ba);
-  double *ea = it.e64 + ba * it.n_pad;
-  double *eb = two ? it.e64 + bb * it.n_pad : nullptr;
+  const EsOut ea(it.es_hi, it.es_lo, it.tks, ba);
+  const EsOut eb(it.es_hi, it.es_lo, it.tks, two ? bb : ba);
   for (int k = threadIdx.x; k < n1; k += blockDim.x) {
     const int64_t r = (int64_t)k * (m / n1);
     tw1[k] = make_double2(sd.tw[2 * r], -sd.tw[2 * r + 1]);
@@ -1049,8 +1088,8 @@ __device__ void refine_segment(const RefItem &it, const SegDev &sd, int64_t ba, 
   }
   // padded rows of the segment carry e = 0
   for (int64_t p = sd.row0 + sd.nkeep + threadIdx.x; p < sd.row0 + sd.npad; p += blockDim.x) {
-    ea[p] = 0.0;
-    if (two) eb[p] = 0.0;
+    ea.put((int32_t)p, 0.0);
+    if (two) eb.put((int32_t)p, 0.0);
   }
   __syncthreads();
   // pass 1: column DFTs (length n1) of x[n2 j1 + j2], twiddle w_m^{j2 k1}, to S[k1 n2 + j2]
@@ -1128,14 +1167,14 @@ __device__ void refine_segment(const RefItem &it, const SegDev &sd, int64_t ba, 
       const double yd = it.yd_pos[jg];
       const double xa = (double)ya[p];
       const double hva = ha[jg];
-      ea[p] = hva - cza;
+      ea.put(p, hva - cza);
       acc.hy_a += hva * xa;
       acc.ydh_a += hva * yd;
       acc.yc_a += xa * cza;
       if (two) {
         const double xb = (double)yb[p];
         const double hvb = hb[jg];
-        eb[p] = hvb - czb;
+        eb.put(p, hvb - czb);
         acc.hy_b += hvb * xb;
         acc.ydh_b += hvb * yd;
         acc.yc_b += xb * czb;
@@ -1424,8 +1463,8 @@ __device__ __forceinline__ void rl_odd_pair(double2 vk, double2 vr, Mul la, Mul 
 // up to RL_CHL positions at once (all of a thread's at h = 8192), the final phase, which
 // reads four arrays, RL_CHF.  (Stores to e would otherwise keep later loads from being
 // hoisted above them.)  Segments without excluded samples compute rows instead of loading
-// them, and read or write the y0 and e values of a sample pair as one vector (the pair's
-// first row is even there).
+// them, and read a sample pair's y0 values as one vector (the pair's first row is even
+// there).  The residual e goes out split, in the products' fragment layout (EsOut).
 constexpr int RL_CH = 4;    // batch of the split transforms' phases
 constexpr int RL_CHL = 16;  // batch of the in-LDS phases that read y0 only, and pointwise ones
 constexpr int RL_CHF = 8;   // batch of the final in-LDS phase
@@ -1450,7 +1489,7 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   const gmem<const double> *__restrict__ hrow = gpu(template_row(it, b) + sd.offset);
   const gmem<const double> *__restrict__ ydp = gpu(it.yd_pos + sd.offset);
   const gmem<const int32_t> *__restrict__ p2r = gpu(it.pos2row + sd.offset);
-  gmem<double> *__restrict__ e = gpu(it.e64 + b * it.n_pad);
+  const EsOut es(it.es_hi, it.es_lo, it.tks, b);
   const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);  // (cos, sin) of 2 pi r / m
   const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);
   const gmem<const double> *__restrict__ lam = gpu(sd.lam);
@@ -1485,17 +1524,6 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
     }
     return v;
   };
-  auto store_e = [&](const int32_t (&r)[2], double v0, double v1) {
-    if (dense && r[1] >= 0) {
-      dv2 v;
-      v.x = v0;
-      v.y = v1;
-      *(gmem<dv2> *)(e + r[0]) = v;
-    } else {
-      if (r[0] >= 0) e[r[0]] = v0;
-      if (r[1] >= 0) e[r[1]] = v1;
-    }
-  };
   auto finite_or_flag = [&](float v) -> double {
     if (!isfinite(v)) {
       a.bad = 1.0;
@@ -1509,10 +1537,11 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   fv2 yk[NI];
   double2 te[NI];
 
-  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) es.put((int32_t)q, 0.0);
 
   // ---- even frequencies: circulant part
   t = opaque_tid();
+#pragma unroll
   for (int i0 = 0; i0 < NI; i0 += CL) {
     int32_t r[CL][2];
 #pragma unroll
@@ -1601,6 +1630,7 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   rl_fft<LH>(X, ptw);
   // tO_{2p} + i tO_{2p+1} = conj(w_m^{2p} X[p]); C y0 = tE / m + tO / m
   t = opaque_tid();
+#pragma unroll
   for (int i0 = 0; i0 < NI; i0 += CF) {
     int32_t r[CF][2];
     double hv[CF][2], yv[CF][2];
@@ -1636,7 +1666,7 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
         a.ydh += hv[c][u] * yv[c][u];
         a.yc += xd * cz;
       }
-      store_e(r[c], ov[0], ov[1]);
+      es.pair(r[c], ov[0], ov[1]);
     }
   }
   __syncthreads();
@@ -1899,7 +1929,8 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   const gmem<const double> *__restrict__ hrow = gpu(template_row(it, b) + sd.offset);
   const gmem<const double> *__restrict__ ydp = gpu(it.yd_pos + sd.offset);
   const gmem<const int32_t> *__restrict__ p2r = gpu(it.pos2row + sd.offset);
-  gmem<double> *__restrict__ e = gpu(it.e64 + b * it.n_pad);
+  gmem<double> *__restrict__ e = gpu(it.e64 + b * it.n_pad);  // t_E / m between the parts
+  const EsOut es(it.es_hi, it.es_lo, it.tks, b);
   const gmem<const dv2> *__restrict__ tw = gpu((const dv2 *)sd.tw);  // (cos, sin) of 2 pi r / m
   const gmem<const dv2> *__restrict__ ptw = gpu((const dv2 *)sd.ptw);  // passes of the part DFTs
   const gmem<const double> *__restrict__ lam = gpu(sd.lam);
@@ -1953,7 +1984,7 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   };
   auto mult = [&](int r) { return lam[r]; };
   // even part: t_E / m parked in e; odd part: C y0 = e + t_O / m, then the residual
-  // e = h - C y0 and the dot products
+  // h - C y0 (written split) and the dot products
   auto emit = [&](int s, bool odd) {
     t = opaque_tid();
     for (int i0 = 0; i0 < NI; i0 += CH) {
@@ -1991,21 +2022,23 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
       for (int c = 0; c < CH; ++c) {
         const int n = t + RL_THREADS * (i0 + c);
         const double2 gz = conj2(cmul(wm(2 * P * n + 2 * s), X[lpad(n)]));
+        double ov[2] = {0.0, 0.0};
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
           if (rr[c][u] < 0) continue;
           const double cz = ev[c][u] + (u ? gz.y : gz.x) * inv_m;
           const double xd = isfinite(xv[c][u]) ? (double)xv[c][u] : 0.0;
-          e[rr[c][u]] = hv[c][u] - cz;
+          ov[u] = hv[c][u] - cz;
           a.hy += hv[c][u] * xd;
           a.ydh += hv[c][u] * yv[c][u];
           a.yc += xd * cz;
         }
+        es.pair(rr[c], ov[0], ov[1]);
       }
     }
   };
 
-  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) e[q] = 0.0;
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) es.put((int32_t)q, 0.0);
   if constexpr (P == 2)
     rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
   else
@@ -2016,9 +2049,9 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
   acc.bad += a.bad;
 }
 
-// Work entry: (item, template).  Persistent grid, one workgroup per CU (the LDS array).
-// Segments of the largest circulant length also need scratch: 3 x 8192 complex doubles per
-// workgroup at qscratch (NULL when the launch has none).
+// Work entry: (item, template), item -1 for padding.  Persistent grid, one workgroup per CU
+// (the LDS array).  Segments of the largest circulant length also need scratch: 3 x 8192
+// complex doubles per workgroup at qscratch (NULL when the launch has none).
 __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__restrict__ items,
                                                            const int2 *__restrict__ work,
                                                            int64_t n_work,
@@ -2029,6 +2062,7 @@ __global__ __launch_bounds__(RL_THREADS) void k_refine_lds(const RefItem *__rest
   gmem<dv2> *S = qscratch ? gpu((dv2 *)(qscratch + (int64_t)blockIdx.x * RL_QUAD_SCRATCH)) : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
+    if (wk.x < 0) continue;  // padding of the work list
     const RefItem &it = items[wk.x];
     const int64_t b = wk.y;
     RlAcc acc{0, 0, 0, 0};

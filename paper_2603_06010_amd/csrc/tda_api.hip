@@ -1218,11 +1218,17 @@ struct MixWs {
 // fragments per template tile of the split layouts
 static int64_t tile_ksteps(const tda_ctx *h) { return h->n_pad / 16 + TKS_PAD; }
 
+// Segments whose circulant the refinement splits into halves or quarters park part of
+// C y0 in an FP64 scratch row per template.
+static bool needs_e64(const tda_ctx *h) {
+  return h->max_m > RL_MAX_M && h->max_m <= RL_MAX_M_QUAD;
+}
+
 static size_t mix_ws_bytes(const tda_ctx *h, int64_t Bp) {
   const size_t el = (size_t)Bp * h->n_pad;
   const size_t el_t = (size_t)(Bp / 32) * tile_ksteps(h) * 512;  // split layouts
-  return el_t * (2 + 2 + 2 + 2) + el * (4 + 8) + (size_t)Bp * 8 + (size_t)h->nblk * Bp * 8 +
-         6 * 256;
+  return el_t * (2 + 2 + 2 + 2) + el * (4 + (needs_e64(h) ? 8 : 0)) + (size_t)Bp * 8 +
+         (size_t)h->nblk * Bp * 8 + 6 * 256;
 }
 
 static MixWs carve_mix_ws(const tda_ctx *h, int64_t Bp, char *base) {
@@ -1239,7 +1245,7 @@ static MixWs carve_mix_ws(const tda_ctx *h, int64_t Bp, char *base) {
   w.w0_hi = (uint16_t *)take(el_t * 2);
   w.w0_lo = (uint16_t *)take(el_t * 2);
   w.y0 = (float *)take(el * 4);
-  w.e64 = (double *)take(el * 8);
+  w.e64 = needs_e64(h) ? (double *)take(el * 8) : nullptr;
   w.qpart = (double *)take((size_t)Bp * 8);
   w.corr_part = (double *)take((size_t)h->nblk * Bp * 8);
   return w;
@@ -1293,11 +1299,39 @@ static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi, const DataChec
   ri.qdd = &chk->qdd;
   ri.idx = (const int32_t *)h->idx_d.p;
   ri.e64 = mi.e64;
+  ri.es_hi = mi.es_hi;
+  ri.es_lo = mi.es_lo;
+  ri.tks = mi.tks;
   ri.qpart = mi.qpart;
   ri.out = mi.out;
   ri.cterm = mi.cterm;
   ri.n_pad = mi.n_pad;
   return ri;
+}
+
+// In-LDS refinement work in XCD order.  Workgroup i of a launch runs on XCD i mod 8 and the
+// persistent grid (a multiple of 8 workgroups) keeps each workgroup's entries on it, so
+// entry 8 q + x runs on XCD x.  The templates of one 32-template tile of the split layout go
+// to one XCD, so the partial lines of the residual they write meet in that XCD's L2; tiles
+// are dealt to the XCDs in turn, and each XCD's list is padded to the longest with empty
+// entries (item -1).
+static std::vector<int2> xcd_tiles(const std::vector<int2> &w) {
+  constexpr int NX = 8;
+  std::vector<std::vector<int2>> lists(NX);
+  int j = 0;
+  for (size_t n = 0; n < w.size();) {
+    size_t e = n + 1;
+    while (e < w.size() && w[e].x == w[n].x && w[e].y / 32 == w[n].y / 32) ++e;
+    std::vector<int2> &l = lists[j++ % NX];
+    l.insert(l.end(), w.begin() + n, w.begin() + e);
+    n = e;
+  }
+  size_t len = 0;
+  for (const auto &l : lists) len = std::max(len, l.size());
+  std::vector<int2> out(len * NX, int2{-1, -1});
+  for (int x = 0; x < NX; ++x)
+    for (size_t q = 0; q < lists[x].size(); ++q) out[q * NX + x] = lists[x][q];
+  return out;
 }
 
 // Refinement work: templates of one item in pairs sharing one complex DFT.
@@ -1369,6 +1403,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
   // the forward, backward and correction products share the work lists (block pairs):
   // whole template groups, and half groups for the half-group variant
   const std::vector<int4> wf = xcd_order(jf), wh = xcd_order(jh);
+  wrl = xcd_tiles(wrl);
   HIP_TRY(ring.reserve(8192 + n * (64 + sizeof(MixItem) + sizeof(RefItem)) +
                        (wf.size() + wh.size() + wr.size()) * sizeof(int4) +
                        (wfin.size() + wrl.size()) * sizeof(int2)));
@@ -1403,7 +1438,7 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     max_chunks = std::max<int64_t>(max_chunks, (int64_t)(mis[k].Bp / 32) * (mis[k].n_pad / 16) * 64);
   {
     TimedScope ts("split_h", s);
-    HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 0, s));
+    HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, s));
   }
   const int vf = autotune_pick("trmm_fwd", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {
@@ -1431,10 +1466,6 @@ static tda_status enqueue_mixed(DescRing &ring, const std::vector<MixItem> &mis,
     if (!wr.empty())
       HIP_TRY(launch_refine((const RefItem *)d_ri, (const int4 *)d_wr, (int64_t)wr.size(),
                             fft_scratch, 2 * max_m_scratch, kRefineWG, s));
-  }
-  {
-    TimedScope ts("split_e", s);
-    HIP_TRY(launch_split_h(dm, (int32_t)n, max_chunks, 1, s));
   }
   const int vc = autotune_pick("trmm_corr", rows, tmpl, kVariants, 4, s,
                                [](void *c, int v) {

@@ -91,11 +91,12 @@ struct MixItem {
   const double *const *Hrows;      // optional per-template row pointers
   uint16_t *hs_hi, *hs_lo;         // split templates, fragment layout, [Bp/32][tks][64][8]
                                    // (another item's, when hs_shared)
-  uint16_t *es_hi, *es_lo;         // split residual e, same layout (this item's own buffer)
+  uint16_t *es_hi, *es_lo;         // split residual e, same layout (this item's own buffer),
+                                   // written by the refinement
   uint16_t *w0_hi, *w0_lo;         // split W h, same layout as hs
   int64_t tks;                     // k-steps per template tile in those layouts (n_pad/16 + TKS_PAD)
   float *y0;                       // [Bp][n_pad]
-  double *e64;                     // [Bp][n_pad] FP64 residual h - C y0 (padded rows 0)
+  double *e64;                     // [Bp][n_pad] FP64 scratch of the split refinements (or null)
   double *corr_part;               // [nblk][Bp] per-block sums of (W e)^2
   double *qpart;                   // [Bp] FP64 part of the quadratic form
   double *out;
@@ -163,7 +164,9 @@ struct RefItem {
   const double *yd_pos;    // [N] C^-1 d scattered to sample positions (0 at excluded)
   const double *qdd;       // scalar: this call's q_dd (DataCheck::qdd)
   const int32_t *idx;      // [n_pad] sample index of each padded row, -1 = padding
-  double *e64;             // [Bp][n_pad] residual output
+  double *e64;             // [Bp][n_pad] FP64 scratch of the split refinements (else null)
+  uint16_t *es_hi, *es_lo; // residual e output, split (BF16 hi/lo) in the fragment layout
+  int64_t tks;             // k-steps per template tile in that layout
   double *qpart;           // [Bp] FP64 part of q output
   double *out;
   double *dh_out;          // optional [B]: d^T C^-1 h
@@ -255,9 +258,9 @@ hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const i
                               DataCheck *chk, hipStream_t s);
 hipError_t launch_lambda(const double *acf, int64_t length, int64_t m, double *tw, double *lam,
                          double *ptw, hipStream_t s);
-// from_e = 0: split the gathered templates h; 1: split the FP64 residual e64 (same layout)
-// one launch over all items; max_chunks = max over items of (Bp/32)(n_pad/16) 64
-hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks, int from_e,
+// Split the gathered templates h into the fragment layout of the products: one launch over
+// all items; max_chunks = max over items of (Bp/32)(n_pad/16) 64
+hipError_t launch_split_h(const MixItem *items, int32_t n_items, int64_t max_chunks,
                           hipStream_t s);
 hipError_t launch_corr(const MixItem *items, const int4 *work, int64_t n_work, int variant,
                        hipStream_t s);
