@@ -2502,6 +2502,7 @@ __global__ __launch_bounds__(RL_THREADS) void k_gs(const GsItem *__restrict__ it
   gmem<dv2> *S = qoff >= 0 ? (gmem<dv2> *)(tes + qoff) : nullptr;
   for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
     const int2 wk = work[wi];
+    if (wk.x < 0) continue;  // padding of the work list
     const GsItem &it = items[wk.x];
     const int64_t b = wk.y;
     double qp = 0.0;

@@ -702,6 +702,31 @@ static tda_status build_gs(tda_ctx *h) {
   return TDA_OK;
 }
 
+// Per-template transform work (in-LDS refinement, Gohberg-Semencul) in XCD order.  Workgroup i of a launch runs on XCD i mod 8 and the
+// persistent grid (a multiple of 8 workgroups) keeps each workgroup's entries on it, so
+// entry 8 q + x runs on XCD x.  The templates of one 32-template tile of the split layout go
+// to one XCD, so the partial lines of the residual they write meet in that XCD's L2; tiles
+// are dealt to the XCDs in turn, and each XCD's list is padded to the longest with empty
+// entries (item -1).
+static std::vector<int2> xcd_tiles(const std::vector<int2> &w) {
+  constexpr int NX = 8;
+  std::vector<std::vector<int2>> lists(NX);
+  int j = 0;
+  for (size_t n = 0; n < w.size();) {
+    size_t e = n + 1;
+    while (e < w.size() && w[e].x == w[n].x && w[e].y / 32 == w[n].y / 32) ++e;
+    std::vector<int2> &l = lists[j++ % NX];
+    l.insert(l.end(), w.begin() + n, w.begin() + e);
+    n = e;
+  }
+  size_t len = 0;
+  for (const auto &l : lists) len = std::max(len, l.size());
+  std::vector<int2> out(len * NX, int2{-1, -1});
+  for (int x = 0; x < NX; ++x)
+    for (size_t q = 0; q < lists[x].size(); ++q) out[q * NX + x] = lists[x][q];
+  return out;
+}
+
 constexpr int32_t kGsWG = 1024;  // persistent Gohberg-Semencul workgroups (one per CU runs at once)
 
 // Per-workgroup Gohberg-Semencul scratch: the parked even parts of the two products (max_len
@@ -739,18 +764,19 @@ static GsItem make_gs_item(const tda_ctx *h, const double *d, const double *H, i
 
 static tda_status loglik_gs(tda_ctx *h, const double *d, const double *H, int64_t B, int64_t ldh,
                             double *out, hipStream_t s) {
-  const GsScratch gsc = gs_scratch_plan(B, h->gs_max_len, h->max_m);
-  TDA_TRY(h->alloc(h->ws_fft, gsc.bytes));
-  const GsItem it = make_gs_item(h, d, H, ldh, B, out);
   std::vector<int2> work((size_t)B);
   for (int64_t b = 0; b < B; ++b) work[b] = int2{0, (int32_t)b};
+  work = xcd_tiles(work);
+  const GsScratch gsc = gs_scratch_plan((int64_t)work.size(), h->gs_max_len, h->max_m);
+  TDA_TRY(h->alloc(h->ws_fft, gsc.bytes));
+  const GsItem it = make_gs_item(h, d, H, ldh, B, out);
   HIP_TRY(h->ring.reserve(1024 + sizeof(GsItem) + work.size() * sizeof(int2)));
   void *d_it, *d_w;
   HIP_TRY(h->ring.push(&it, sizeof(GsItem), s, &d_it));
   HIP_TRY(h->ring.push(work.data(), work.size() * sizeof(int2), s, &d_w));
   {
     TimedScope ts("gs_fft", s);
-    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, B, (double *)h->ws_fft.p,
+    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, (int64_t)work.size(), (double *)h->ws_fft.p,
                       gsc.stride, gsc.qoff, gsc.n_wg, s));
   }
   HIP_TRY(h->ring.seal(s));
@@ -1309,31 +1335,6 @@ static RefItem make_ref_item(const tda_ctx *h, const MixItem &mi, const DataChec
   return ri;
 }
 
-// In-LDS refinement work in XCD order.  Workgroup i of a launch runs on XCD i mod 8 and the
-// persistent grid (a multiple of 8 workgroups) keeps each workgroup's entries on it, so
-// entry 8 q + x runs on XCD x.  The templates of one 32-template tile of the split layout go
-// to one XCD, so the partial lines of the residual they write meet in that XCD's L2; tiles
-// are dealt to the XCDs in turn, and each XCD's list is padded to the longest with empty
-// entries (item -1).
-static std::vector<int2> xcd_tiles(const std::vector<int2> &w) {
-  constexpr int NX = 8;
-  std::vector<std::vector<int2>> lists(NX);
-  int j = 0;
-  for (size_t n = 0; n < w.size();) {
-    size_t e = n + 1;
-    while (e < w.size() && w[e].x == w[n].x && w[e].y / 32 == w[n].y / 32) ++e;
-    std::vector<int2> &l = lists[j++ % NX];
-    l.insert(l.end(), w.begin() + n, w.begin() + e);
-    n = e;
-  }
-  size_t len = 0;
-  for (const auto &l : lists) len = std::max(len, l.size());
-  std::vector<int2> out(len * NX, int2{-1, -1});
-  for (int x = 0; x < NX; ++x)
-    for (size_t q = 0; q < lists[x].size(); ++q) out[q * NX + x] = lists[x][q];
-  return out;
-}
-
 // Refinement work: templates of one item in pairs sharing one complex DFT.
 static void add_refine_pairs(int32_t item, int64_t B, std::vector<int4> &wr) {
   for (int64_t b = 0; b < B; b += 2)
@@ -1738,6 +1739,7 @@ tda_status multi_impl(MultiCtx *mc, const tda_work *items, const double *const *
       max_m = std::max(max_m, w.h->max_m);
       for (int64_t b = 0; b < w.B; ++b) work.push_back(int2{(int32_t)k, (int32_t)b});
     }
+    work = xcd_tiles(work);
     const GsScratch gsc = gs_scratch_plan((int64_t)work.size(), max_len, max_m);
     TDA_TRY(P.alloc(P.ws_fft, gsc.bytes));
     HIP_TRY(mc->ring.reserve(4096 + gis.size() * sizeof(GsItem) + work.size() * sizeof(int2) +
