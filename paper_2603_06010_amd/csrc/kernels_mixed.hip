@@ -207,11 +207,25 @@ __global__ __launch_bounds__(1024) void k_data_check(const double *__restrict__ 
                                                      DataCheck *__restrict__ chk,
                                                      int32_t can_whiten, int32_t force) {
   __shared__ uint64_t part[1024];
+  // rows in rounds of 16 per thread, every load of a round issued before the hashing (the
+  // sum does not depend on the order)
+  constexpr int U = 16;
   uint64_t acc = 0;
-  for (int32_t r = threadIdx.x; r < n_pad; r += 1024) {
-    const int32_t p = idx[r];
-    if (p < 0) continue;
-    acc += mix64((uint64_t)__double_as_longlong(d[p]) + mix64((uint64_t)r));
+  for (int32_t r0 = 0; r0 < n_pad; r0 += 1024 * U) {
+    int32_t p[U];
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = r0 + (int32_t)threadIdx.x + 1024 * u;
+      p[u] = r < n_pad ? idx[r] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = p[u] >= 0 ? d[p[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t r = r0 + (int32_t)threadIdx.x + 1024 * u;
+      if (p[u] >= 0) acc += mix64((uint64_t)__double_as_longlong(v[u]) + mix64((uint64_t)r));
+    }
   }
   part[threadIdx.x] = acc;
   __syncthreads();
