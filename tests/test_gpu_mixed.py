@@ -191,11 +191,12 @@ def _ar1_white_closed(X, keep, s, phi):
 
 # Segments beyond the in-LDS DFT length (m = 4 x 8192): m = 65536 refines in LDS with each
 # DFT split in halves (lengths 16385 .. 32768), m = 131072 with quarters, three of them in
-# per-workgroup scratch (lengths 32769 .. 65536); dense rows and rows with excluded samples,
-# one handle with segments of both kinds.
+# per-workgroup scratch (lengths 32769 .. 65536), and longer segments with whole transforms
+# in global scratch (70000); dense rows and rows with excluded samples, one handle with
+# segments of both kinds.
 @pytest.mark.parametrize("N,n_gaps,B,segments", [
     (16385, 1, 40, None), (20000, 0, 64, None), (32768, 3, 96, None), (40000, 2, 48, None),
-    (65536, 0, 24, None), (60000, 1, 20, [(0, 40000), (40000, 20000)])])
+    (65536, 0, 24, None), (60000, 1, 20, [(0, 40000), (40000, 20000)]), (70000, 1, 12, None)])
 def test_mixed_long_segments_ar1_closed_form(tda, N, n_gaps, B, segments):
     from gpu_util import to_dev
     from test_oracle_pins import ar1_acf, gapped_ar1_closed
