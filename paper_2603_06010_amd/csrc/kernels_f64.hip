@@ -269,13 +269,32 @@ __global__ __launch_bounds__(256) void k_panel(double *__restrict__ A, int64_t l
   d4 acc[8];
 #pragma unroll
   for (int ct = 0; ct < 8; ++ct) acc[ct] = d4{0, 0, 0, 0};
-  for (int t0 = 0; t0 < CP; t0 += 4) {
-    const double a = A[(k + t0 + lr) * lda + i0 + lc];
+  // operands in batches of TG k-steps of 4, each batch fetched one batch ahead of its
+  // products (two register buffers), so that the loads of a batch wait once
+  constexpr int TG = 4, NB = CP / (4 * TG);
+  static_assert(NB % 2 == 0, "whole buffer pairs");
+  double av[2][TG], bv[2][TG][8];
+  auto fetch = [&](int buf, int g) __attribute__((always_inline)) {
 #pragma unroll
-    for (int ct = 0; ct < 8; ++ct) {
-      const double b = dinvT[(t0 + lr) * CP + 16 * ct + lc];
-      acc[ct] = mfma64(a, b, acc[ct]);
+    for (int u = 0; u < TG; ++u) {
+      const int t0 = 4 * (g * TG + u);
+      av[buf][u] = A[(k + t0 + lr) * lda + i0 + lc];
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct) bv[buf][u][ct] = dinvT[(t0 + lr) * CP + 16 * ct + lc];
     }
+  };
+  auto consume = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < TG; ++u)
+#pragma unroll
+      for (int ct = 0; ct < 8; ++ct) acc[ct] = mfma64(av[buf][u], bv[buf][u][ct], acc[ct]);
+  };
+  fetch(0, 0);
+  for (int g = 0; g < NB; g += 2) {
+    fetch(1, g + 1);
+    consume(0);
+    if (g + 2 < NB) fetch(0, g + 2);
+    consume(1);
   }
 #pragma unroll
   for (int ct = 0; ct < 8; ++ct)
