@@ -1551,7 +1551,8 @@ __device__ __noinline__ void rl_segment(const RefItem &it, const SegDev &sd, int
   fv2 yk[NI];
   double2 te[NI];
 
-  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) es.put((int32_t)q, 0.0);
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS)
+    es.put((int32_t)q, 0.0);
 
   // ---- even frequencies: circulant part
   t = opaque_tid();
@@ -2052,7 +2053,8 @@ __device__ __noinline__ void rl_segment_split(const RefItem &it, const SegDev &s
     }
   };
 
-  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS) es.put((int32_t)q, 0.0);
+  for (int64_t q = sd.row0 + sd.nkeep + t; q < sd.row0 + sd.npad; q += RL_THREADS)
+    es.put((int32_t)q, 0.0);
   if constexpr (P == 2)
     rl_split_parts<LH>(X, tw, ptw, stage, mult, emit);
   else

@@ -702,9 +702,9 @@ static tda_status build_gs(tda_ctx *h) {
   return TDA_OK;
 }
 
-// Per-template transform work (in-LDS refinement, Gohberg-Semencul) in XCD order.  Workgroup i of a launch runs on XCD i mod 8 and the
-// persistent grid (a multiple of 8 workgroups) keeps each workgroup's entries on it, so
-// entry 8 q + x runs on XCD x.  The templates of one 32-template tile of the split layout go
+// Per-template transform work (in-LDS refinement, Gohberg-Semencul) in XCD order.
+// Workgroup i of a launch runs on XCD i mod 8 and the persistent grid (a multiple of 8
+// workgroups) keeps each workgroup's entries on it, so entry 8 q + x runs on XCD x.  The templates of one 32-template tile of the split layout go
 // to one XCD, so the partial lines of the residual they write meet in that XCD's L2; tiles
 // are dealt to the XCDs in turn, and each XCD's list is padded to the longest with empty
 // entries (item -1).
@@ -776,8 +776,8 @@ static tda_status loglik_gs(tda_ctx *h, const double *d, const double *H, int64_
   HIP_TRY(h->ring.push(work.data(), work.size() * sizeof(int2), s, &d_w));
   {
     TimedScope ts("gs_fft", s);
-    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, (int64_t)work.size(), (double *)h->ws_fft.p,
-                      gsc.stride, gsc.qoff, gsc.n_wg, s));
+    HIP_TRY(launch_gs((const GsItem *)d_it, (const int2 *)d_w, (int64_t)work.size(),
+                      (double *)h->ws_fft.p, gsc.stride, gsc.qoff, gsc.n_wg, s));
   }
   HIP_TRY(h->ring.seal(s));
   return TDA_OK;
