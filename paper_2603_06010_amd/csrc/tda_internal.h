@@ -273,10 +273,11 @@ hipError_t launch_trmm_fwd(const MixItem *items, const int4 *work, int64_t n_wor
 hipError_t launch_trmm_bwd(const MixItem *items, const int4 *work, int64_t n_work, int variant,
                            hipStream_t s);
 
-// ---------------------------------------------------------------- autotuner (autotune.cpp)
+// ---------------------------------------------------------------- autotuner (autotune.hip)
 // Chooses, per (kernel, row bucket, template bucket), the fastest variant among
-// `variants` by timing one launch of each on the caller's stream the first time the key
-// is seen (that call synchronises).  Choices persist in-process and, when the
+// `variants` on the caller's stream the first time the key is seen (that call
+// synchronises): one untimed launch of each, then three timed rounds over all of them,
+// and the smallest median wins.  Choices persist in-process and, when the
 // environment variable TDA_AUTOTUNE_CACHE names a file, across processes (text lines
 // "kernel rows_log2 templates_log2 variant").  TDA_AUTOTUNE=0 disables timing and uses
 // the first variant.
