@@ -1,6 +1,6 @@
-"""Seeded random shapes through the mixed and FP64 paths: random N, gaps, two-segment
-splits and batch sizes (Sec. II.B items 1-3), each against the oracle, then all of them
-in one batched call against their single calls."""
+"""Seeded random shapes: random N, gaps, two-segment splits and batch sizes (Sec. II.B
+items 1-3) through the mixed and FP64 paths, each against the oracle, then all of them in
+one batched call against their single calls; gap-free ones through Gohberg-Semencul."""
 import numpy as np
 import pytest
 
@@ -68,4 +68,22 @@ def test_random_shapes_vs_oracle_and_batched(tda):
         diff = np.max(np.abs(out.cpu().numpy() - want))
         assert diff <= 1e-9, diff
     for h, *_ in items:
+        h.close()
+
+
+def test_random_gap_free_shapes_gohberg_semencul(tda):
+    """The Gohberg-Semencul path over seeded random gap-free shapes (one or two segments)
+    against the oracle, at ten times the FP64 bound (it subtracts two quadratic forms)."""
+    from gpu_util import to_dev
+    import torch
+    for c, N, _, B, segs in _cases(2025, 12):
+        print(f"case {c}: N={N} B={B} segments={segs}", flush=True)
+        inst = synth.random_rhs_case(4000 + c, N, 1, 0, B, segments=segs)
+        h = tda.Handle(inst.acf, N, None, segs, precision="gs").factor()
+        got = h.loglik(to_dev(inst.d[0]), to_dev(inst.H)).cpu().numpy()
+        f = oracle.factor(inst.acf, N, None, segs)
+        want = oracle.loglik(f, inst.d[0], inst.H)
+        tol = tol_f64(q_of(want, [f]), kappa_synth(EPS), scale=10.0)
+        assert np.all(np.abs(got - want) <= tol), np.max(np.abs(got - want))
+        torch.cuda.synchronize()
         h.close()
