@@ -610,12 +610,12 @@ __device__ __forceinline__ void trsm_tile(const TrsmItem &it, const TrsmTile &tl
     const int s_begin = (f - bf) * (TB / 4);
     const int s_end = (i - bf) * (TB / 4);
     const double *Wk = W + ((int64_t)f * TB - rbase) * BC;
-    // Operands of GK k-steps are fetched two groups ahead of the matrix cores (three register
-    // buffers), so the loads of a group have two groups of products to arrive.  The k-range
-    // of a block row is a multiple of 64 k-steps, so groups tile it exactly; no fetch goes
-    // past it.
-    constexpr int GK = 8;
-    double pa[3][GK][4], pb[3][GK][2];
+    // Operands of GK k-steps are fetched NBUF - 1 groups ahead of the matrix cores (NBUF
+    // register buffers in a ring), so the loads of a group have that many groups of products
+    // to arrive.  The k-range of a block row is a multiple of 64 k-steps, so groups tile it
+    // exactly; no fetch goes past it.
+    constexpr int GK = 4, NBUF = 6;
+    double pa[NBUF][GK][4], pb[NBUF][GK][2];
     auto fetch = [&](int bsel, int s0) {
 #pragma unroll
       for (int kk = 0; kk < GK; ++kk) {
@@ -637,18 +637,18 @@ __device__ __forceinline__ void trsm_tile(const TrsmItem &it, const TrsmTile &tl
         }
     };
     if (s_begin < s_end) {
-      fetch(0, s_begin);
-      if (s_begin + GK < s_end) fetch(1, s_begin + GK);
-      // buffer 0 holds group s, buffer 1 group s + GK
-      for (int s = s_begin; s < s_end; s += 3 * GK) {
-        if (s + 2 * GK < s_end) fetch(2, s + 2 * GK);
-        consume(0);
-        if (s + GK >= s_end) break;
-        if (s + 3 * GK < s_end) fetch(0, s + 3 * GK);
-        consume(1);
-        if (s + 2 * GK >= s_end) break;
-        if (s + 4 * GK < s_end) fetch(1, s + 4 * GK);
-        consume(2);
+#pragma unroll
+      for (int u = 0; u < NBUF - 1; ++u)
+        if (s_begin + u * GK < s_end) fetch(u, s_begin + u * GK);
+      // group s + u GK sits in buffer u
+      for (int s = s_begin; s < s_end; s += NBUF * GK) {
+#pragma unroll
+        for (int u = 0; u < NBUF; ++u) {
+          if (s + u * GK >= s_end) break;
+          const int ahead = s + (u + NBUF - 1) * GK;
+          if (ahead < s_end) fetch((u + NBUF - 1) % NBUF, ahead);
+          consume(u);
+        }
       }
     }
 #pragma unroll
