@@ -249,23 +249,54 @@ __global__ __launch_bounds__(1024) void k_data_check(const double *__restrict__ 
   }
 }
 
-__global__ void k_dbar(const double *__restrict__ w64, const int64_t *__restrict__ off,
-                       const int32_t *__restrict__ rb, const int32_t *__restrict__ blk_first,
-                       const int32_t *__restrict__ idx, const double *__restrict__ d,
-                       double *__restrict__ dbar, const DataCheck *__restrict__ chk) {
+// d-bar = W d over the padded rows.  A workgroup takes DB_ROWS consecutive rows (inside one
+// 256-row block, so one segment) as 8 row groups x 32 columns of a column tile: a row's 32
+// entries in a tile are contiguous, so each row group reads 256 contiguous bytes per row.
+// It sums over the segment's tiles up to its last row, then over the 32 columns in the
+// wave (fixed order).
+constexpr int DB_ROWS = 32;
+__global__ __launch_bounds__(256) void k_dbar(const double *__restrict__ w64,
+                                              const int64_t *__restrict__ off,
+                                              const int32_t *__restrict__ rb,
+                                              const int32_t *__restrict__ blk_first,
+                                              const int32_t *__restrict__ idx,
+                                              const double *__restrict__ d,
+                                              double *__restrict__ dbar,
+                                              const DataCheck *__restrict__ chk) {
   if (!chk->stale) return;
-  const int i = blockIdx.x;
-  const int64_t r = (int64_t)i * TB + threadIdx.x;
-  const int64_t c_beg = (int64_t)blk_first[i] * TB;
-  double acc = 0.0;
-  for (int64_t c = c_beg; c <= r; ++c) {
+  constexpr int NR = DB_ROWS / 8;
+  const int cc = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int64_t r0 = (int64_t)blockIdx.x * DB_ROWS;
+  const int64_t ct_beg = (int64_t)blk_first[r0 / TB] * (TB / 32);
+  const int64_t ct_end = (r0 + DB_ROWS - 1) / 32;  // the tile of the last row's diagonal
+  double acc[NR];
+#pragma unroll
+  for (int u = 0; u < NR; ++u) acc[u] = 0.0;
+#pragma unroll 4
+  for (int64_t ct = ct_beg; ct <= ct_end; ++ct) {
+    const int64_t c = ct * 32 + cc;
     const int32_t p = idx[c];
-    if (p < 0) continue;
-    acc += w64_at(w64, off, rb, r, c) * d[p];
+    const double dv = p >= 0 ? d[p] : 0.0;
+    const double *wt = w64 + off[ct] + cc;
+    const int64_t rbt = rb[ct];
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      const int64_t r = r0 + g + 8 * u;
+      if (r >= c) acc[u] += wt[(r - rbt) * 32] * dv;
+    }
   }
-  dbar[r] = acc;
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    double v = acc[u];
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 32);
+    if (cc == 0) dbar[r0 + g + 8 * u] = v;
+  }
 }
 
+// y_d = W^T d-bar: a workgroup per column tile, 8 row groups x 32 columns (256 contiguous
+// bytes per row), eight independent partial sums per thread over rows r = g + 8 k, then the
+// row groups in LDS (fixed order).
 __global__ void k_yd(const double *__restrict__ w64, const int64_t *__restrict__ off,
                      const int32_t *__restrict__ rb, const int32_t *__restrict__ blk_last,
                      const double *__restrict__ dbar, double *__restrict__ yd,
@@ -276,9 +307,17 @@ __global__ void k_yd(const double *__restrict__ w64, const int64_t *__restrict__
   const int cc = threadIdx.x & 31, g = threadIdx.x >> 5;
   const int64_t c = (int64_t)ct * 32 + cc;
   const int64_t r_end = (int64_t)(blk_last[c / TB] + 1) * TB;
-  double acc = 0.0;
-  for (int64_t r = rb[ct] + g; r < r_end; r += 8) acc += w64_at(w64, off, rb, r, c) * dbar[r];
-  part[g][cc] = acc;
+  const int64_t rbt = rb[ct];
+  const double *wt = w64 + off[ct] + cc;
+  auto term = [&](int64_t r) { return r >= c ? wt[(r - rbt) * 32] * dbar[r] : 0.0; };
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t r = rbt + g;
+  for (; r + 56 < r_end; r += 64) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] += term(r + 8 * k);
+  }
+  for (; r < r_end; r += 8) a[0] += term(r);
+  part[g][cc] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
   if (g == 0) {
     double s = 0.0;
@@ -329,8 +368,8 @@ hipError_t launch_data_whiten(const double *w64, const int64_t *w64_off, const i
                               const int32_t *pos2row, int32_t n_pad, int64_t N, const double *d,
                               double *dbar, double *yd, double *yd_pos, DataCache *cache,
                               DataCheck *chk, hipStream_t s) {
-  hipLaunchKernelGGL(k_dbar, dim3((unsigned)(n_pad / TB)), dim3(TB), 0, s, w64, w64_off, w64_rb,
-                     blk_first, idx, d, dbar, (const DataCheck *)chk);
+  hipLaunchKernelGGL(k_dbar, dim3((unsigned)(n_pad / DB_ROWS)), dim3(256), 0, s, w64, w64_off,
+                     w64_rb, blk_first, idx, d, dbar, (const DataCheck *)chk);
   hipLaunchKernelGGL(k_yd, dim3((unsigned)(n_pad / 32)), dim3(256), 0, s, w64, w64_off, w64_rb,
                      blk_last, dbar, yd, (const DataCheck *)chk);
   hipLaunchKernelGGL(k_qdd_and_scatter, dim3(1), dim3(256), 0, s, dbar, yd, pos2row, n_pad, N,
