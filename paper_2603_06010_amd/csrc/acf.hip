@@ -20,12 +20,17 @@
 
 namespace tda {
 
-constexpr int ACF_LAGS = 256;    // lags per workgroup (one per thread)
-constexpr int ACF_CHUNK = 4096;  // samples per pass through LDS
+constexpr int ACF_LAGS = 256;              // threads per workgroup
+constexpr int ACF_PER = 4;                 // lags per thread, ACF_LAGS apart
+constexpr int ACF_TILE = ACF_LAGS * ACF_PER;  // lags per workgroup
+constexpr int ACF_CHUNK = 4096;            // samples per pass through LDS
 
 // Sum over one series y of length L of products y[j] y[j + k] for the workgroup's lags
-// k0 .. k0 + 255 and j in chunks c0 .. c0 + nc - 1 of ACF_CHUNK samples.  Periodic series
-// (Welch segments) wrap j + k modulo L; the others read zero past the end.
+// k0 .. k0 + ACF_TILE - 1 and j in chunks c0 .. c0 + nc - 1 of ACF_CHUNK samples.  A
+// thread keeps the sums of the lags k0 + t + ACF_LAGS u (u < ACF_PER): independent
+// multiply-add chains, one read of y[j] for all of them, and consecutive threads read
+// consecutive LDS words.  Each lag's sum runs over j in order.  Periodic series (Welch
+// segments) wrap j + k modulo L; the others read zero past the end.
 //   part[(series * n_groups + group) * n_lags + k]
 // grid (lag tiles, chunk groups, series); series s starts at y + s * stride
 __global__ __launch_bounds__(ACF_LAGS) void k_acf_corr(const double *__restrict__ y, int64_t L,
@@ -33,11 +38,13 @@ __global__ __launch_bounds__(ACF_LAGS) void k_acf_corr(const double *__restrict_
                                                        int64_t n_lags, int32_t chunks_per_group,
                                                        double *__restrict__ part) {
   __shared__ double xa[ACF_CHUNK];
-  __shared__ double xb[ACF_CHUNK + ACF_LAGS];
-  const int64_t k0 = (int64_t)blockIdx.x * ACF_LAGS;
+  __shared__ double xb[ACF_CHUNK + ACF_TILE];
+  const int64_t k0 = (int64_t)blockIdx.x * ACF_TILE;
   const double *ys = y + (int64_t)blockIdx.z * stride;
   const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_group;
-  double s = 0.0;
+  double s[ACF_PER];
+#pragma unroll
+  for (int u = 0; u < ACF_PER; ++u) s[u] = 0.0;
   for (int64_t c = c_begin; c < c_begin + chunks_per_group; ++c) {
     const int64_t j0 = c * ACF_CHUNK;
     if (j0 >= L) break;  // uniform over the workgroup
@@ -46,16 +53,25 @@ __global__ __launch_bounds__(ACF_LAGS) void k_acf_corr(const double *__restrict_
       const int64_t t = j0 + j;
       xa[j] = t < L ? ys[t] : 0.0;
     }
-    for (int j = threadIdx.x; j < ACF_CHUNK + ACF_LAGS; j += ACF_LAGS) {
+    for (int j = threadIdx.x; j < ACF_CHUNK + ACF_TILE; j += ACF_LAGS) {
       int64_t t = j0 + k0 + j;
       if (periodic) t %= L;
       xb[j] = t < L ? ys[t] : 0.0;
     }
     __syncthreads();
-    for (int j = 0; j < ACF_CHUNK; ++j) s = fma(xa[j], xb[j + threadIdx.x], s);
+    const double *xt = xb + threadIdx.x;
+    for (int j = 0; j < ACF_CHUNK; ++j) {
+      const double a = xa[j];
+#pragma unroll
+      for (int u = 0; u < ACF_PER; ++u) s[u] = fma(a, xt[j + ACF_LAGS * u], s[u]);
+    }
   }
-  const int64_t k = k0 + threadIdx.x;
-  if (k < n_lags) part[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * n_lags + k] = s;
+  double *out = part + ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * n_lags;
+#pragma unroll
+  for (int u = 0; u < ACF_PER; ++u) {
+    const int64_t k = k0 + threadIdx.x + ACF_LAGS * u;
+    if (k < n_lags) out[k] = s[u];
+  }
 }
 
 // Welch segments: Y[s][j] = w_j (x[s L/2 + j] - mean_s), w the periodic Hann window.
@@ -100,7 +116,7 @@ extern "C" tda_status tda_acf_estimate(const double *x, int64_t n, int64_t n_lag
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
     return set_error(TDA_ESTATE, "acf: not callable on a capturing stream");
-  const int64_t tiles = (n_lags + ACF_LAGS - 1) / ACF_LAGS;
+  const int64_t tiles = (n_lags + ACF_TILE - 1) / ACF_TILE;
   if (tiles > 65535) return set_error(TDA_EINVAL, "acf: too many lags");
   int64_t series = 1, L = n, groups = 1, Ybytes = 0;
   int32_t cpg = 1;
