@@ -21,34 +21,35 @@
 namespace tda {
 
 constexpr int ACF_LAGS = 256;                 // threads per workgroup
-constexpr int ACF_PER = 4;                    // consecutive lags per thread
+constexpr int ACF_PER = 8;                    // consecutive lags per thread
 constexpr int ACF_TILE = ACF_LAGS * ACF_PER;  // lags per workgroup
-constexpr int ACF_CHUNK = 4096;               // samples per pass through LDS
+constexpr int ACF_CHUNK = 2048;               // samples per pass through LDS
 constexpr int ACF_XB = ACF_CHUNK + ACF_TILE;  // shifted samples per pass
-// LDS word of shifted sample i: one pad word per 8, so that the threads' reads, 4 words
-// apart, fall in different banks
+// LDS word of shifted sample i: one pad word per 8, so that the threads' reads, 8 words
+// apart, spread over the banks
 __device__ __forceinline__ int acf_pad(int i) { return i + (i >> 3); }
 
 // Sum over one series y of length L of products y[j] y[j + k] for the workgroup's lags
 // k0 .. k0 + ACF_TILE - 1 and j in chunks c0 .. c0 + nc - 1 of ACF_CHUNK samples.  Thread t
-// keeps the sums of the lags k0 + 4 t + u (u < 4) with y[j + 4 t + u] in a sliding window
-// of registers: per j one read of y[j] and one of y[j + 4 t + 3] for four multiply-adds in
-// independent chains.  Each lag's sum runs over j in order.  Periodic series (Welch
-// segments) wrap j + k modulo L; the others read zero past the end.
+// keeps the sums of the lags k0 + P t + u (u < P = ACF_PER) with y[j + P t + u] in a sliding
+// window of registers: per j one read of y[j] and one of y[j + P t + P - 1] for P
+// multiply-adds in independent chains.  Each lag's sum runs over j in order.  Periodic
+// series (Welch segments) wrap j + k modulo L; the others read zero past the end.
 //   part[(series * n_groups + group) * n_lags + k]
 // grid (lag tiles, chunk groups, series); series s starts at y + s * stride
 __global__ __launch_bounds__(ACF_LAGS) void k_acf_corr(const double *__restrict__ y, int64_t L,
                                                        int64_t stride, int32_t periodic,
                                                        int64_t n_lags, int32_t chunks_per_group,
                                                        double *__restrict__ part) {
-  static_assert(ACF_PER == 4, "four-register window");
   __shared__ double xa[ACF_CHUNK];
   __shared__ double xb[ACF_XB + ACF_XB / 8];
   const int64_t k0 = (int64_t)blockIdx.x * ACF_TILE;
   const double *ys = y + (int64_t)blockIdx.z * stride;
   const int64_t c_begin = (int64_t)blockIdx.y * chunks_per_group;
   const int base = ACF_PER * (int)threadIdx.x;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double sv[ACF_PER], b[ACF_PER];
+#pragma unroll
+  for (int u = 0; u < ACF_PER; ++u) sv[u] = 0.0;
   for (int64_t c = c_begin; c < c_begin + chunks_per_group; ++c) {
     const int64_t j0 = c * ACF_CHUNK;
     if (j0 >= L) break;  // uniform over the workgroup
@@ -63,20 +64,18 @@ __global__ __launch_bounds__(ACF_LAGS) void k_acf_corr(const double *__restrict_
       xb[acf_pad(j)] = t < L ? ys[t] : 0.0;
     }
     __syncthreads();
-    double b0 = xb[acf_pad(base)], b1 = xb[acf_pad(base + 1)], b2 = xb[acf_pad(base + 2)];
+#pragma unroll
+    for (int u = 0; u + 1 < ACF_PER; ++u) b[u] = xb[acf_pad(base + u)];
     for (int j = 0; j < ACF_CHUNK; ++j) {
-      const double a = xa[j], b3 = xb[acf_pad(j + base + 3)];
-      s0 = fma(a, b0, s0);
-      s1 = fma(a, b1, s1);
-      s2 = fma(a, b2, s2);
-      s3 = fma(a, b3, s3);
-      b0 = b1;
-      b1 = b2;
-      b2 = b3;
+      const double a = xa[j];
+      b[ACF_PER - 1] = xb[acf_pad(j + base + ACF_PER - 1)];
+#pragma unroll
+      for (int u = 0; u < ACF_PER; ++u) sv[u] = fma(a, b[u], sv[u]);
+#pragma unroll
+      for (int u = 0; u + 1 < ACF_PER; ++u) b[u] = b[u + 1];
     }
   }
   double *out = part + ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * n_lags;
-  const double sv[ACF_PER] = {s0, s1, s2, s3};
 #pragma unroll
   for (int u = 0; u < ACF_PER; ++u) {
     const int64_t k = k0 + base + u;
